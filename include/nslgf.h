@@ -1,0 +1,176 @@
+/*
+ * nslgf.h -- C ABI of the MI355X fast-LGF Navier-Stokes hot path.
+ *
+ * The library computes, on one GPU, the operations of the fast lattice Green's function (LGF)
+ * method for viscous incompressible flow on unbounded staggered grids (Liska & Colonius):
+ * the free-space LGF convolution that inverts the 7-point Laplacian, the integrating factor
+ * E(alpha) of the discrete heat equation, and the stages of the integrating-factor half-explicit
+ * Runge-Kutta (IF-HERK) step with its exact projection.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Box.  The computational box holds nx * ny * nz cells.  Every scalar field (a cell field, or one
+ *   component of a face or edge field) is a dense array [nz][ny][nx] with x fastest; vector fields
+ *   are three such arrays back to back, components (1), (2), (3).  Values outside the box are zero
+ *   (the mask operators of Sec. 4.1); every output is produced on the box only.
+ * Memory.  All field pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) on the
+ *   handle's device, owned by the caller, 256-byte aligned, and must not alias unless a call says
+ *   so.  The library owns its tables and workspaces (allocated lazily, freed by nslgf_destroy).
+ * Precision.  dtype NSLGF_F64 (double) or NSLGF_F32 (float) for the field data.  Tables (the LGF,
+ *   its spectrum, the integrating-factor weights) are always built in FP64; the FP32 path rounds
+ *   them once.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls enqueue
+ *   work and return without synchronising; results are ready in stream order.  Table builds and
+ *   workspace allocations happen on first use and synchronise the stream once.
+ * Errors.  Every call returns NSLGF_OK (0) or a negative code; nothing aborts and no exception
+ *   crosses the ABI.  nslgf_last_error() gives a thread-local message for the last failure.
+ *   A handle is not thread-safe: one host thread at a time per handle.
+ */
+#ifndef NSLGF_H
+#define NSLGF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum nslgf_status {
+    NSLGF_OK = 0,
+    NSLGF_EINVAL = -1,       /* bad argument (size, pointer, alpha < 0, unsupported box) */
+    NSLGF_ENOMEM = -2,       /* device allocation failed */
+    NSLGF_EHIP = -3,         /* a HIP runtime call failed */
+    NSLGF_EUNSUPPORTED = -4, /* valid request this build does not handle */
+    NSLGF_ESTATE = -5        /* stages called out of order */
+};
+
+enum nslgf_dtype { NSLGF_F64 = 0, NSLGF_F32 = 1 };
+
+enum nslgf_scheme { NSLGF_SCHEME_A = 0, NSLGF_SCHEME_B = 1, NSLGF_SCHEME_C = 2 };
+
+typedef struct nslgf_ctx *nslgf_t;
+
+/* Create a handle bound to HIP device `device` (tables, plans and workspaces live there). */
+int nslgf_create(nslgf_t *h, int device);
+/* Free every device allocation of the handle.  Waits for the device first. */
+int nslgf_destroy(nslgf_t h);
+/* Message of the last failing call on this host thread ("" if none). */
+const char *nslgf_last_error(void);
+/* Library version string. */
+const char *nslgf_version(void);
+
+/*
+ * Lattice Green's function of the 7-point Laplacian (Appendix B):
+ *   g(n) = -int_0^inf e^{-6t} I_{n1}(2t) I_{n2}(2t) I_{n3}(2t) dt,  -6 g(n) + sum_neighbours g = delta_n0.
+ * lgf_value evaluates g on the host with the same method the GPU table builder uses (quadrature of
+ * the Bessel integral for |n| < 40, the far-field expansion beyond).  Writes *out; returns 0.
+ */
+int lgf_value(int n1, int n2, int n3, double *out);
+
+/*
+ * Build (or rebuild) the LGF table and its zero-padded spectrum for a box of nx*ny*nz cells
+ * (Appendix B; preprocessing done once per box size).  The kernel is the LGF on the padded
+ * lattice of Px*Py*Pz points, P >= 2n - 1 per axis (the smallest supported 2,3,5-smooth size), made
+ * even by wrapping; its real spectrum is stored by symmetry.  `dtype` selects the precision of the
+ * stored spectrum (built in FP64).  Sizes 1 <= n <= 256 per axis.  Returns NSLGF_EINVAL otherwise.
+ * lgf_convolve builds the table lazily; calling this first only moves the cost.
+ */
+int lgf_table(nslgf_t h, int nx, int ny, int nz, int dtype, void *stream);
+
+/*
+ * LGF convolution (Sec. 2.2, Eq. dpoisson_conv): for each component q < ncomp,
+ *     dst_q(n) = dx^2 * sum_{m in box} g(n - m) src_q(m),   n in box,
+ * i.e. dst = L^{-1} src for the dimensional Laplacian (dx^2 L a = -6a + neighbours) with uniform
+ * conditions at infinity; the sources outside the box are zero.  Computed exactly (to rounding) by
+ * a zero-padded FFT convolution.  src, dst: device arrays [ncomp][nz][ny][nx] of `dtype`; src and
+ * dst must not overlap.  ncomp in 1..3.
+ */
+int lgf_convolve(nslgf_t h, const void *src, void *dst, int ncomp, int nx, int ny, int nz, double dx,
+                 int dtype, void *stream);
+
+/*
+ * Integrating factor (Sec. 2.3, Eqs. if_def and ddifussion_soln; kernel of Appendix B):
+ *     dst_q(n) = sum_{m in box} prod_j w[|n_j - m_j|] src_q(m),  w[k] = e^{-2 alpha} I_k(2 alpha),
+ * i.e. dst = M E(alpha) M src, the solution operator of the discrete heat equation over
+ * alpha = kappa (t - tau) / dx^2.  The 1D kernel is truncated where its tail falls below the
+ * rounding of the dtype.  alpha must be >= 0 (NSLGF_EINVAL otherwise; E(-alpha) is unbounded).
+ * src == dst (in place) is allowed.  Arrays [ncomp][nz][ny][nx], ncomp in 1..6.
+ */
+int if_apply(nslgf_t h, const void *src, void *dst, int ncomp, int nx, int ny, int nz, double alpha,
+             int dtype, void *stream);
+
+/*
+ * IF-HERK state of one box (Sec. 3.2 with the projection of Sec. 3.3, masked as in Sec. 5).
+ * The caller fills the scalars and the pointers; `work` must hold nslgf_state_bytes() bytes of
+ * device memory.  u: face velocity [3][nz][ny][nx] (in: u_k; out after the last stage: u_{k+1});
+ * d: cell field [nz][ny][nx] (out: total pressure d_{k+1}).  n_buf >= 0 is the buffer width: the
+ * nonlinear term and the pressure source are restricted to the box shrunk by n_buf cells on every
+ * side (the solution and support domains of Sec. 5, Eqs. rhs_final and dpoisson_final).
+ * stage_done counts the stages already applied (0 before the first stage).
+ */
+typedef struct nslgf_state {
+    int nx, ny, nz;
+    int dtype;      /* enum nslgf_dtype */
+    int scheme;     /* enum nslgf_scheme */
+    int n_buf;
+    double dx, dt, re, t;
+    void *u;
+    void *d;
+    void *work;
+    int stage_done; /* managed by herk_stage */
+    int reserved;
+} nslgf_state;
+
+/* Bytes of device workspace one state needs for its box and dtype. */
+size_t nslgf_state_bytes(int nx, int ny, int nz, int dtype);
+
+/*
+ * One stage i (1-based, 1..3) of the IF-HERK step (Sec. 3.2):
+ *     g^i = -a~_ii dt Ntilde(u^{i-1}),  r^i = q^i + dt sum_{j<i} a~_ij w^{i,j} + g^i,
+ *     d^i = L^{-1} Dbar r^i (= -L^{-1} G^T r^i),  u^i = H^i (r^i - G d^i),
+ *     w^{i,i} = (g^i - G d^i) / (a~_ii dt),  H^i = E((c~_i - c~_{i-1}) dt / (dx^2 Re)),
+ * with the final-stage form of the footnote of Sec. 3.2 in the last stage.  The last stage also
+ * writes u_{k+1} into st->u, d_{k+1} = d^s / (a~_ss dt) into st->d and advances st->t by dt.
+ * Stages must be called in order 1, 2, 3 (NSLGF_ESTATE otherwise); stage 1 restarts a step.
+ */
+int herk_stage(nslgf_t h, nslgf_state *st, int stage, void *stream);
+
+/* The three stages of one step (Scheme A, B or C per st->scheme). */
+int herk_step(nslgf_t h, nslgf_state *st, void *stream);
+
+/*
+ * Vor2Vel (Sec. 4.1, Eqs. vel_vor and vel_refresh): a = -L^{-1} w per component, u = Cbar a.
+ * w: edge vorticity [3][nz][ny][nx]; u: face velocity [3][nz][ny][nx] (must not overlap w).
+ */
+int vor2vel(nslgf_t h, const void *w, void *u, int nx, int ny, int nz, double dx, int dtype, void *stream);
+
+/*
+ * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
+ *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
+ *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])
+ *   op NSLGF_OP_CURL      C:     faces  -> edges
+ *   op NSLGF_OP_CURL_BAR  Cbar:  edges  -> faces
+ *   op NSLGF_OP_NONLINEAR Ntilde: faces -> faces (Eq. opr_def_nonlin, e = C f kept one layer
+ *                          beyond the box)
+ *   op NSLGF_OP_LAPLACIAN 7-point L per component (ncomp from 1 to 3 in `ncomp`)
+ * src and dst must not overlap.
+ */
+enum nslgf_op {
+    NSLGF_OP_GRAD = 0, NSLGF_OP_DIV = 1, NSLGF_OP_CURL = 2, NSLGF_OP_CURL_BAR = 3,
+    NSLGF_OP_NONLINEAR = 4, NSLGF_OP_LAPLACIAN = 5
+};
+int stencil_apply(nslgf_t h, int op, const void *src, void *dst, int ncomp, int nx, int ny, int nz, double dx,
+                  int dtype, void *stream);
+
+/*
+ * Maximum over cells of the cell-centred speed |u| (each face component averaged to the cell
+ * centre), used for the CFL step size dt = CFL dx / max|u| (Sec. 6).  Writes one double to the
+ * HOST pointer out (synchronises the stream).
+ */
+int max_cell_speed(nslgf_t h, const void *u, int nx, int ny, int nz, int dtype, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSLGF_H */

@@ -45,13 +45,18 @@ def _hankel_coefs(nmax: int, terms: int) -> np.ndarray:
 
 
 def _tail(ents: np.ndarray, nmax: int, T: float) -> np.ndarray:
-    """int_T^inf prod_j e^{-2t} I_{nj}(2t) dt from the product of the three Hankel series."""
+    """int_T^inf prod_j e^{-2t} I_{nj}(2t) dt from the product of the three Hankel series:
+    the coefficient of t^{-m} in the product is sum_{i+j+l=m} c[n1,i] c[n2,j] c[n3,l], and
+    int_T^inf (4 pi t)^{-3/2} t^{-m} dt = (4 pi)^{-3/2} T^{-1/2-m} / (m + 1/2)."""
     c = _hankel_coefs(nmax, _HANKEL_TERMS)
+    ca, cb, cd = c[ents[:, 0]], c[ents[:, 1]], c[ents[:, 2]]
     out = np.zeros(len(ents))
-    for idx, (a, b, d) in enumerate(ents):
-        p = np.convolve(np.convolve(c[a], c[b]), c[d])
-        m = np.arange(len(p))
-        out[idx] = np.sum(p * T ** (-0.5 - m) / (m + 0.5))
+    K = _HANKEL_TERMS
+    for i in range(K):
+        for j in range(K):
+            for l in range(K):
+                m = i + j + l
+                out += ca[:, i] * cb[:, j] * cd[:, l] * (T ** (-0.5 - m) / (m + 0.5))
     return out * (4.0 * math.pi) ** -1.5
 
 
@@ -90,7 +95,17 @@ def lgf_wedge(nmax: int) -> tuple[np.ndarray, np.ndarray]:
         if g.shape == (len(ents),):
             return ents, g
     chunk = 40000
-    g = np.concatenate([_integrate(ents[i:i + chunk], nmax) for i in range(0, len(ents), chunk)])
+    parts = [ents[i:i + chunk] for i in range(0, len(ents), chunk)]
+    if len(parts) > 2:
+        # worker processes started as fresh interpreters (never forked from a GPU process)
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+
+        workers = min(16, len(parts), os.cpu_count() or 1)
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            g = np.concatenate(list(ex.map(_integrate, parts, [nmax] * len(parts))))
+    else:
+        g = np.concatenate([_integrate(p, nmax) for p in parts])
     try:
         os.makedirs(d, exist_ok=True)
         tmp = path + f".{os.getpid()}.tmp.npy"

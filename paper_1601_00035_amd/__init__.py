@@ -1,0 +1,244 @@
+"""MI355X-native fast lattice Green's function (LGF) hot path of the NS-LGF method.
+
+Thin Python binding of libnslgf.so, whose C ABI is declared in include/nslgf.h.  Every step of the
+method runs in the library's HIP kernels; this module only marshals torch tensors (device pointers,
+sizes, the current HIP stream) into the C calls.  There is no CPU fallback: if the library is not
+built, or a tensor is not on the GPU, the call raises.
+
+Field layout: scalar fields are [nz, ny, nx] tensors, vector fields [3, nz, ny, nx], float64 or
+float32, contiguous, on a CUDA (HIP) device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libnslgf.so")
+
+F64, F32 = 0, 1
+SCHEME = {"A": 0, "B": 1, "C": 2}
+OP = {"grad": 0, "div": 1, "curl": 2, "curl_bar": 3, "nonlinear": 4, "laplacian": 5}
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
+
+
+class NslgfError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed with {_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("scheme", ctypes.c_int), ("n_buf", ctypes.c_int), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("re", ctypes.c_double), ("t", ctypes.c_double), ("u", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("work", ctypes.c_void_p), ("stage_done", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        with _lock:
+            if _lib is None:
+                if not os.path.exists(LIB_PATH):
+                    raise RuntimeError(f"{LIB_PATH} is not built; run paper_1601_00035_amd/build.py first")
+                L = ctypes.CDLL(LIB_PATH)
+                vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+                sig = {
+                    "nslgf_create": [ctypes.POINTER(vp), i],
+                    "nslgf_destroy": [vp],
+                    "lgf_value": [i, i, i, ctypes.POINTER(d)],
+                    "lgf_table": [vp, i, i, i, i, vp],
+                    "lgf_convolve": [vp, vp, vp, i, i, i, i, d, i, vp],
+                    "if_apply": [vp, vp, vp, i, i, i, i, d, i, vp],
+                    "herk_stage": [vp, ctypes.POINTER(_State), i, vp],
+                    "herk_step": [vp, ctypes.POINTER(_State), vp],
+                    "vor2vel": [vp, vp, vp, i, i, i, d, i, vp],
+                    "stencil_apply": [vp, i, vp, vp, i, i, i, i, d, i, vp],
+                    "max_cell_speed": [vp, vp, i, i, i, i, ctypes.POINTER(d), vp],
+                }
+                for name, args in sig.items():
+                    f = getattr(L, name)
+                    f.argtypes = args
+                    f.restype = i
+                L.nslgf_state_bytes.argtypes = [i, i, i, i]
+                L.nslgf_state_bytes.restype = ctypes.c_size_t
+                L.nslgf_last_error.restype = ctypes.c_char_p
+                L.nslgf_version.restype = ctypes.c_char_p
+                _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != 0:
+        raise NslgfError(fn, rc, lib().nslgf_last_error().decode())
+
+
+_handles: dict[int, ctypes.c_void_p] = {}
+
+
+def handle(device: int | None = None) -> ctypes.c_void_p:
+    """The library handle of a device (created on first use, kept for the process lifetime)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    h = _handles.get(device)
+    if h is None:
+        h = ctypes.c_void_p()
+        _check("nslgf_create", lib().nslgf_create(ctypes.byref(h), device))
+        _handles[device] = h
+    return h
+
+
+def _dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype} (float64 or float32)")
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (there is no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _box(t: torch.Tensor, vector: bool | None = None):
+    if t.dim() == 3:
+        return 1, t.shape[2], t.shape[1], t.shape[0]
+    if t.dim() == 4:
+        return t.shape[0], t.shape[3], t.shape[2], t.shape[1]
+    raise ValueError("fields are [nz, ny, nx] or [ncomp, nz, ny, nx]")
+
+
+def version() -> str:
+    return lib().nslgf_version().decode()
+
+
+def lgf_value(n1: int, n2: int, n3: int) -> float:
+    """g(n) of the 7-point Laplacian (host evaluation, same method as the table builder)."""
+    out = ctypes.c_double()
+    _check("lgf_value", lib().lgf_value(int(n1), int(n2), int(n3), ctypes.byref(out)))
+    return out.value
+
+
+def lgf_table(nx: int, ny: int, nz: int, dtype: torch.dtype = torch.float64, device: int | None = None):
+    """Build the LGF spectrum for a box (otherwise built lazily by the first convolution)."""
+    code = F64 if dtype == torch.float64 else F32
+    dev = torch.cuda.current_device() if device is None else device
+    s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check("lgf_table", lib().lgf_table(handle(dev), nx, ny, nz, code, s))
+
+
+def lgf_convolve(src: torch.Tensor, dx: float = 1.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """dst = dx^2 (g * src) per component on the box (L^{-1} src with zero conditions at infinity)."""
+    _dev(src, "src")
+    ncomp, nx, ny, nz = _box(src)
+    if out is None:
+        out = torch.empty_like(src)
+    _dev(out, "out")
+    if out.shape != src.shape or out.dtype != src.dtype:
+        raise ValueError("out must match src")
+    _check("lgf_convolve", lib().lgf_convolve(handle(src.device.index), src.data_ptr(), out.data_ptr(), ncomp, nx, ny,
+                                              nz, float(dx), _dtype(src), _stream(src)))
+    return out
+
+
+def if_apply(src: torch.Tensor, alpha: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """M E(alpha) M src per component (in place if out is src)."""
+    _dev(src, "src")
+    ncomp, nx, ny, nz = _box(src)
+    if out is None:
+        out = torch.empty_like(src)
+    _dev(out, "out")
+    _check("if_apply", lib().if_apply(handle(src.device.index), src.data_ptr(), out.data_ptr(), ncomp, nx, ny, nz,
+                                      float(alpha), _dtype(src), _stream(src)))
+    return out
+
+
+def stencil(op: str, src: torch.Tensor, dx: float) -> torch.Tensor:
+    """One point operator of the staggered grid: grad, div, curl, curl_bar, nonlinear, laplacian."""
+    _dev(src, "src")
+    code = OP[op]
+    if code == OP["grad"]:
+        nz, ny, nx = src.shape
+        out = torch.empty((3, nz, ny, nx), dtype=src.dtype, device=src.device)
+        ncomp = 1
+    elif code == OP["div"]:
+        _, nz, ny, nx = src.shape
+        out = torch.empty((nz, ny, nx), dtype=src.dtype, device=src.device)
+        ncomp = 3
+    elif code == OP["laplacian"]:
+        ncomp, nx, ny, nz = _box(src)
+        out = torch.empty_like(src)
+    else:
+        _, nz, ny, nx = src.shape
+        out = torch.empty_like(src)
+        ncomp = 3
+    _check("stencil_apply", lib().stencil_apply(handle(src.device.index), code, src.data_ptr(), out.data_ptr(), ncomp,
+                                                nx, ny, nz, float(dx), _dtype(src), _stream(src)))
+    return out
+
+
+def vor2vel(w: torch.Tensor, dx: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """u = Cbar a, a = -L^{-1} w (edge vorticity -> face velocity)."""
+    _dev(w, "w")
+    _, nz, ny, nx = w.shape
+    if out is None:
+        out = torch.empty_like(w)
+    _check("vor2vel", lib().vor2vel(handle(w.device.index), w.data_ptr(), out.data_ptr(), nx, ny, nz, float(dx),
+                                    _dtype(w), _stream(w)))
+    return out
+
+
+def max_cell_speed(u: torch.Tensor) -> float:
+    _dev(u, "u")
+    _, nz, ny, nx = u.shape
+    out = ctypes.c_double()
+    _check("max_cell_speed", lib().max_cell_speed(handle(u.device.index), u.data_ptr(), nx, ny, nz, _dtype(u),
+                                                  ctypes.byref(out), _stream(u)))
+    return out.value
+
+
+class HerkState:
+    """IF-HERK state of one box: the caller's velocity u (updated in place), the pressure d and the
+    library workspace, plus the step parameters."""
+
+    def __init__(self, u: torch.Tensor, dx: float, dt: float, re: float, scheme: str = "A", n_buf: int = 0,
+                 t: float = 0.0):
+        _dev(u, "u")
+        _, nz, ny, nx = u.shape
+        self.u = u
+        self.d = torch.zeros((nz, ny, nx), dtype=u.dtype, device=u.device)
+        nbytes = lib().nslgf_state_bytes(nx, ny, nz, _dtype(u))
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
+        self.c = _State(nx=nx, ny=ny, nz=nz, dtype=_dtype(u), scheme=SCHEME[scheme], n_buf=int(n_buf), dx=float(dx),
+                        dt=float(dt), re=float(re), t=float(t), u=u.data_ptr(), d=self.d.data_ptr(),
+                        work=self.work.data_ptr(), stage_done=0, reserved=0)
+
+    @property
+    def t(self) -> float:
+        return self.c.t
+
+    def set_dt(self, dt: float):
+        self.c.dt = float(dt)
+
+    def stage(self, i: int):
+        _check("herk_stage", lib().herk_stage(handle(self.u.device.index), ctypes.byref(self.c), int(i),
+                                              _stream(self.u)))
+
+    def step(self):
+        _check("herk_step", lib().herk_step(handle(self.u.device.index), ctypes.byref(self.c), _stream(self.u)))

@@ -1,0 +1,517 @@
+// C-ABI of the library: handle lifecycle, per-box convolution plans (LGF spectrum, twiddles,
+// workspaces), the integrating factor, the IF-HERK stage driver and Vor2Vel.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "kernels.h"
+
+namespace nslgf {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need) {
+        if (need <= bytes) return NSLGF_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of " + std::to_string(need) + " bytes failed");
+            return NSLGF_ENOMEM;
+        }
+        bytes = need;
+        return NSLGF_OK;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct ConvPlan {
+    int nx = 0, ny = 0, nz = 0, dtype = 0;
+    int Px = 0, Py = 0, Pz = 0;
+    long long XP = 0;
+    int tb = 0, tiles = 0;
+    DevBuf khat;
+    DevBuf A1, A2;  // workspaces for up to 3 components
+};
+
+}  // namespace nslgf
+
+struct nslgf_ctx {
+    int device = 0;
+    std::map<std::tuple<int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
+    std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
+    nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
+};
+
+namespace nslgf {
+
+static int get_twiddles(nslgf_ctx* h, int L, int dtype, const void** out) {
+    auto key = std::make_pair(L, dtype);
+    auto it = h->twiddles.find(key);
+    if (it == h->twiddles.end()) {
+        void* d = nullptr;
+        NSLGF_TRY(make_twiddles(L, dtype, &d));
+        auto b = std::make_unique<DevBuf>();
+        b->p = d;
+        b->bytes = (size_t)L * 2 * dtype_size(dtype);
+        it = h->twiddles.emplace(key, std::move(b)).first;
+    }
+    *out = it->second->p;
+    return NSLGF_OK;
+}
+
+static int check_box(int nx, int ny, int nz) {
+    NSLGF_CHECK_ARG(nx >= 1 && ny >= 1 && nz >= 1 && nx <= 256 && ny <= 256 && nz <= 256,
+                    "box sizes must be in 1..256 per axis");
+    return NSLGF_OK;
+}
+
+static int check_dtype(int dtype) {
+    NSLGF_CHECK_ARG(dtype == NSLGF_F64 || dtype == NSLGF_F32, "dtype must be NSLGF_F64 or NSLGF_F32");
+    return NSLGF_OK;
+}
+
+static int padded(int n) {
+    // smallest supported even length P >= 2n - 1
+    return next_supported_length(2 * n - 1 > 16 ? 2 * n - 1 : 16);
+}
+
+// Five-pass convolution of ncomp scalar fields with a plan's spectrum times `scale`.
+static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s);
+
+static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, ConvPlan** out) {
+    auto key = std::make_tuple(nx, ny, nz, dtype);
+    auto it = h->plans.find(key);
+    if (it != h->plans.end()) {
+        *out = it->second.get();
+        return NSLGF_OK;
+    }
+    auto plan = std::make_unique<ConvPlan>();
+    ConvPlan& p = *plan;
+    p.nx = nx;
+    p.ny = ny;
+    p.nz = nz;
+    p.dtype = dtype;
+    p.Px = padded(nx);
+    p.Py = padded(ny);
+    p.Pz = padded(nz);
+    if (p.Px < 0 || p.Py < 0 || p.Pz < 0) {
+        set_error("no supported padded length for this box");
+        return NSLGF_EUNSUPPORTED;
+    }
+    p.XP = ((p.Px / 2 + 1 + 7) / 8) * 8;
+    p.tb = col_tile_width(p.Pz, dtype);
+    p.tiles = ceil_div(p.Px / 2 + 1, p.tb);
+    // FP64 kernel on the padded lattice and its spectrum
+    const long long ktot = (long long)p.Px * p.Py * p.Pz;
+    DevBuf kr, spec;
+    NSLGF_TRY(kr.ensure(ktot * sizeof(double)));
+    NSLGF_TRY(spec.ensure((size_t)p.Pz * p.Py * p.XP * 2 * sizeof(double)));
+    NSLGF_TRY(build_padded_lgf(p.Px, p.Py, p.Pz, (double*)kr.p, s));
+    const void *twh, *twf, *twy, *twz;
+    NSLGF_TRY(get_twiddles(h, p.Px / 2, NSLGF_F64, &twh));
+    NSLGF_TRY(get_twiddles(h, p.Px, NSLGF_F64, &twf));
+    NSLGF_TRY(get_twiddles(h, p.Py, NSLGF_F64, &twy));
+    NSLGF_TRY(get_twiddles(h, p.Pz, NSLGF_F64, &twz));
+    RowPass r{};
+    r.in = kr.p;
+    r.out = spec.p;
+    r.nrows = (long long)p.Pz * p.Py;
+    r.in_row = p.Px;
+    r.out_row = p.XP;
+    r.ncomp = 1;
+    r.n_io = p.Px;
+    r.tw_half = twh;
+    r.tw_full = twf;
+    NSLGF_TRY(launch_row_r2c(p.Px, NSLGF_F64, r, s));
+    ColPass c{};
+    c.in = spec.p;
+    c.out = spec.p;
+    c.ncols = p.Px / 2 + 1;
+    c.nouter = p.Pz;
+    c.in_outer = c.out_outer = (long long)p.Py * p.XP;
+    c.in_row = c.out_row = p.XP;
+    c.ncomp = 1;
+    c.n_in = c.n_out = p.Py;
+    c.tw = twy;
+    NSLGF_TRY(launch_col(p.Py, NSLGF_F64, COL_FWD, c, s));
+    c.nouter = p.Py;
+    c.in_outer = c.out_outer = p.XP;
+    c.in_row = c.out_row = (long long)p.Py * p.XP;
+    c.n_in = c.n_out = p.Pz;
+    c.tw = twz;
+    NSLGF_TRY(launch_col(p.Pz, NSLGF_F64, COL_FWD, c, s));
+    const size_t kbytes = (size_t)(p.Py / 2 + 1) * p.tiles * (p.Pz / 2 + 1) * p.tb * dtype_size(dtype);
+    NSLGF_TRY(p.khat.ensure(kbytes));
+    NSLGF_TRY(extract_spectrum(spec.p, p.Px, p.Py, p.Pz, p.XP, 1.0 / (double)ktot, p.tb, p.tiles, dtype, p.khat.p, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    *out = plan.get();
+    h->plans.emplace(key, std::move(plan));
+    return NSLGF_OK;
+}
+
+static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s) {
+    const int dt = p.dtype;
+    const size_t cs = 2 * dtype_size(dt);
+    const long long a1c = (long long)p.nz * p.ny * p.XP, a2c = (long long)p.nz * p.Py * p.XP;
+    NSLGF_TRY(p.A1.ensure((size_t)3 * a1c * cs));
+    NSLGF_TRY(p.A2.ensure((size_t)3 * a2c * cs));
+    const void *twh, *twf, *twy, *twz;
+    NSLGF_TRY(get_twiddles(h, p.Px / 2, dt, &twh));
+    NSLGF_TRY(get_twiddles(h, p.Px, dt, &twf));
+    NSLGF_TRY(get_twiddles(h, p.Py, dt, &twy));
+    NSLGF_TRY(get_twiddles(h, p.Pz, dt, &twz));
+    const long long box = (long long)p.nx * p.ny * p.nz;
+    RowPass r{};
+    r.in = src;
+    r.out = p.A1.p;
+    r.nrows = (long long)p.nz * p.ny;
+    r.in_row = p.nx;
+    r.out_row = p.XP;
+    r.in_comp = box;
+    r.out_comp = a1c;
+    r.ncomp = ncomp;
+    r.n_io = p.nx;
+    r.tw_half = twh;
+    r.tw_full = twf;
+    NSLGF_TRY(launch_row_r2c(p.Px, dt, r, s));
+    ColPass c{};
+    c.in = p.A1.p;
+    c.out = p.A2.p;
+    c.ncols = p.Px / 2 + 1;
+    c.nouter = p.nz;
+    c.in_outer = (long long)p.ny * p.XP;
+    c.out_outer = (long long)p.Py * p.XP;
+    c.in_row = c.out_row = p.XP;
+    c.in_comp = a1c;
+    c.out_comp = a2c;
+    c.ncomp = ncomp;
+    c.n_in = p.ny;
+    c.n_out = p.Py;
+    c.tw = twy;
+    NSLGF_TRY(launch_col(p.Py, dt, COL_FWD, c, s));
+    ColPass z{};
+    z.in = p.A2.p;
+    z.out = p.A2.p;
+    z.ncols = p.Px / 2 + 1;
+    z.nouter = p.Py;
+    z.in_outer = z.out_outer = p.XP;
+    z.in_row = z.out_row = (long long)p.Py * p.XP;
+    z.in_comp = z.out_comp = a2c;
+    z.ncomp = ncomp;
+    z.n_in = z.n_out = p.nz;
+    z.tw = twz;
+    z.khat = p.khat.p;
+    z.khat_tiles = p.tiles;
+    z.outer_period = p.Py;
+    z.scale = scale;
+    NSLGF_TRY(launch_col(p.Pz, dt, COL_CONV, z, s));
+    ColPass y{};
+    y.in = p.A2.p;
+    y.out = p.A1.p;
+    y.ncols = p.Px / 2 + 1;
+    y.nouter = p.nz;
+    y.in_outer = (long long)p.Py * p.XP;
+    y.out_outer = (long long)p.ny * p.XP;
+    y.in_row = y.out_row = p.XP;
+    y.in_comp = a2c;
+    y.out_comp = a1c;
+    y.ncomp = ncomp;
+    y.n_in = p.Py;
+    y.n_out = p.ny;
+    y.tw = twy;
+    NSLGF_TRY(launch_col(p.Py, dt, COL_INV, y, s));
+    RowPass o{};
+    o.in = p.A1.p;
+    o.out = dst;
+    o.nrows = (long long)p.nz * p.ny;
+    o.in_row = p.XP;
+    o.out_row = p.nx;
+    o.in_comp = a1c;
+    o.out_comp = box;
+    o.ncomp = ncomp;
+    o.n_io = p.nx;
+    o.tw_half = twh;
+    o.tw_full = twf;
+    NSLGF_TRY(launch_row_c2r(p.Px, dt, o, s));
+    return NSLGF_OK;
+}
+
+// IF application through two temporaries (x: src -> t1, y: t1 -> t2, z: t2 -> dst); src == dst allowed.
+static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
+                  hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    const size_t bytes = (size_t)ncomp * n * dtype_size(dtype);
+    if (alpha == 0.0) {
+        if (src != dst) NSLGF_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        return NSLGF_OK;
+    }
+    double w[kIfMaxRadius + 1];
+    const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
+    if (r < 0) return NSLGF_EINVAL;
+    NSLGF_TRY(h->if_tmp1.ensure(bytes));
+    NSLGF_TRY(h->if_tmp2.ensure(bytes));
+    NSLGF_TRY(launch_if_axis(0, dtype, src, h->if_tmp1.p, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_TRY(launch_if_axis(1, dtype, h->if_tmp1.p, h->if_tmp2.p, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_TRY(launch_if_axis(2, dtype, h->if_tmp2.p, dst, ncomp, nx, ny, nz, w, r, s));
+    return NSLGF_OK;
+}
+
+// Shifted tableau a~, c~ (1-based, c~_0 = 0) of the three-stage schemes (Sec. 3.1, 3.2).
+static void tableau(int scheme, double at[4][4], double ct[4]) {
+    const double s3 = std::sqrt(3.0);
+    double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, b[3], c[3];
+    if (scheme == NSLGF_SCHEME_B) {
+        A[1][0] = 1.0 / 3.0;
+        A[2][0] = -1.0;
+        A[2][1] = 2.0;
+        b[0] = 0.0; b[1] = 0.75; b[2] = 0.25;
+        c[0] = 0.0; c[1] = 1.0 / 3.0; c[2] = 1.0;
+    } else if (scheme == NSLGF_SCHEME_C) {
+        A[1][0] = 8.0 / 15.0;
+        A[2][0] = 0.25;
+        A[2][1] = 5.0 / 12.0;
+        b[0] = 0.25; b[1] = 0.0; b[2] = 0.75;
+        c[0] = 0.0; c[1] = 8.0 / 15.0; c[2] = 2.0 / 3.0;
+    } else {
+        A[1][0] = 0.5;
+        A[2][0] = s3 / 3.0;
+        A[2][1] = (3.0 - s3) / 3.0;
+        b[0] = (3.0 + s3) / 6.0; b[1] = -s3 / 3.0; b[2] = (3.0 + s3) / 6.0;
+        c[0] = 0.0; c[1] = 0.5; c[2] = 1.0;
+    }
+    std::memset(at, 0, sizeof(double) * 16);
+    ct[0] = 0.0;
+    for (int i = 1; i <= 3; ++i) {
+        for (int j = 1; j <= 3; ++j) at[i][j] = (i < 3) ? A[i][j - 1] : b[j - 1];
+        ct[i] = (i < 3) ? c[i] : 1.0;
+    }
+}
+
+}  // namespace nslgf
+
+using namespace nslgf;
+
+#define NSLGF_ENTER(h)                                                                             \
+    do {                                                                                           \
+        if (!(h)) {                                                                                \
+            set_error("null handle");                                                              \
+            return NSLGF_EINVAL;                                                                   \
+        }                                                                                          \
+        NSLGF_HIP_CHECK(hipSetDevice((h)->device));                                                \
+    } while (0)
+
+extern "C" {
+
+const char* nslgf_last_error(void) { return g_last_error.c_str(); }
+const char* nslgf_version(void) { return "nslgf-mi355x 0.1"; }
+
+int nslgf_create(nslgf_t* h, int device) {
+    NSLGF_CHECK_ARG(h != nullptr, "nslgf_create: null output pointer");
+    int count = 0;
+    NSLGF_HIP_CHECK(hipGetDeviceCount(&count));
+    NSLGF_CHECK_ARG(device >= 0 && device < count, "nslgf_create: no such device");
+    NSLGF_HIP_CHECK(hipSetDevice(device));
+    auto* c = new (std::nothrow) nslgf_ctx();
+    if (!c) {
+        set_error("out of host memory");
+        return NSLGF_ENOMEM;
+    }
+    c->device = device;
+    *h = c;
+    return NSLGF_OK;
+}
+
+int nslgf_destroy(nslgf_t h) {
+    if (!h) return NSLGF_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    delete h;
+    return NSLGF_OK;
+}
+
+int lgf_value(int n1, int n2, int n3, double* out) {
+    NSLGF_CHECK_ARG(out != nullptr, "lgf_value: null output");
+    NSLGF_CHECK_ARG(std::abs(n1) <= 100000 && std::abs(n2) <= 100000 && std::abs(n3) <= 100000, "lgf_value: |n| too large");
+    *out = lgf_value_host(n1, n2, n3);
+    return NSLGF_OK;
+}
+
+int lgf_table(nslgf_t h, int nx, int ny, int nz, int dtype, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    auto key = std::make_tuple(nx, ny, nz, dtype);
+    h->plans.erase(key);
+    ConvPlan* p = nullptr;
+    return build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p);
+}
+
+int lgf_convolve(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
+                 void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(src && dst, "lgf_convolve: null pointer");
+    NSLGF_CHECK_ARG(src != dst, "lgf_convolve: src and dst must differ");
+    NSLGF_CHECK_ARG(ncomp >= 1 && ncomp <= 3, "lgf_convolve: ncomp must be 1..3");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "lgf_convolve: dx must be > 0");
+    ConvPlan* p = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p));
+    return run_conv(h, *p, src, dst, ncomp, dx * dx, (hipStream_t)stream);
+}
+
+int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
+             void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(src && dst, "if_apply: null pointer");
+    NSLGF_CHECK_ARG(ncomp >= 1 && ncomp <= 6, "if_apply: ncomp must be 1..6");
+    NSLGF_CHECK_ARG(std::isfinite(alpha) && alpha >= 0.0, "if_apply: alpha must be >= 0");
+    return run_if(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, (hipStream_t)stream);
+}
+
+size_t nslgf_state_bytes(int nx, int ny, int nz, int dtype) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return (size_t)14 * nx * ny * nz * dtype_size(dtype);
+}
+
+int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(st != nullptr, "herk_stage: null state");
+    NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+    NSLGF_TRY(check_dtype(st->dtype));
+    NSLGF_CHECK_ARG(st->u && st->d && st->work, "herk_stage: null u, d or work");
+    NSLGF_CHECK_ARG(st->scheme >= NSLGF_SCHEME_A && st->scheme <= NSLGF_SCHEME_C, "herk_stage: unknown scheme");
+    NSLGF_CHECK_ARG(std::isfinite(st->dt) && st->dt > 0 && std::isfinite(st->dx) && st->dx > 0 &&
+                        std::isfinite(st->re) && st->re > 0,
+                    "herk_stage: dt, dx and re must be > 0");
+    NSLGF_CHECK_ARG(st->n_buf >= 0, "herk_stage: n_buf must be >= 0");
+    if (stage == 1) st->stage_done = 0;
+    if (stage != st->stage_done + 1 || stage < 1 || stage > 3) {
+        set_error("herk_stage: stages must be called in order 1, 2, 3");
+        return NSLGF_ESTATE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int nx = st->nx, ny = st->ny, nz = st->nz, dt_ = st->dtype;
+    const long long M = (long long)nx * ny * nz;
+    const size_t es = dtype_size(dt_);
+    char* w = (char*)st->work;
+    void* q = w;
+    void* w1 = w + 3 * M * es;
+    void* w2 = w + 6 * M * es;
+    void* r = w + 9 * M * es;
+    void* sdiv = w + 12 * M * es;
+    void* dhat = w + 13 * M * es;
+    double at[4][4], ct[4];
+    tableau(st->scheme, at, ct);
+    const double dt = st->dt, beta = dt / (st->dx * st->dx * st->re);
+    const double alpha = (ct[stage] - ct[stage - 1]) * beta;
+    ConvPlan* plan = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dt_, s, &plan));
+    StageCoef c{};
+    c.nbuf = st->n_buf;
+    c.c_g = -at[stage][stage] * dt;
+    const double inv = 1.0 / (at[stage][stage] * dt);
+    if (stage == 1) {
+        c.c_q = 1.0;
+        c.copy_q = 1;
+        NSLGF_TRY(launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+    } else if (stage == 2) {
+        const double a_prev = (ct[1] - ct[0]) * beta;
+        NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s));  // q and w1 are adjacent
+        c.c_q = 1.0;
+        c.c_w1 = dt * at[2][1];
+        NSLGF_TRY(launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s));
+    } else {
+        // final-stage form: r^3 = H^2 (q^2 + dt (a~31 w^{2,1} + a~32 w^{2,2})) + g^3
+        const double a_prev = (ct[2] - ct[1]) * beta;
+        NSLGF_TRY(launch_axpby(dt_, r, q, 1.0, w1, dt * at[3][1], w2, dt * at[3][2], 3 * M, s));
+        NSLGF_TRY(run_if(h, r, r, 3, nx, ny, nz, a_prev, dt_, s));
+        c.c_q = 1.0;
+        NSLGF_TRY(launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+    }
+    NSLGF_TRY(launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
+    NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s));
+    if (stage == 1) {
+        NSLGF_TRY(launch_stage_project(dt_, r, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz, st->dx, s));
+    } else if (stage == 2) {
+        NSLGF_TRY(launch_stage_project(dt_, r, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny, nz,
+                                       st->dx, s));
+    } else {
+        NSLGF_TRY(launch_stage_project(dt_, r, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx, ny, nz,
+                                       st->dx, s));
+    }
+    NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s));
+    if (stage == 3) {
+        NSLGF_TRY(launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
+        st->t += dt;
+    }
+    st->stage_done = stage;
+    return NSLGF_OK;
+}
+
+int herk_step(nslgf_t h, nslgf_state* st, void* stream) {
+    for (int i = 1; i <= 3; ++i) NSLGF_TRY(herk_stage(h, st, i, stream));
+    return NSLGF_OK;
+}
+
+int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx, int dtype, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(w && u && w != u, "vor2vel: null or aliased pointers");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "vor2vel: dx must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    ConvPlan* p = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
+    const long long M = (long long)nx * ny * nz;
+    NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
+    NSLGF_TRY(run_conv(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
+    return launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s);
+}
+
+int stencil_apply(nslgf_t h, int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
+                  void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(src && dst && src != dst, "stencil_apply: null or aliased pointers");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "stencil_apply: dx must be > 0");
+    NSLGF_CHECK_ARG(op != NSLGF_OP_LAPLACIAN || (ncomp >= 1 && ncomp <= 3), "stencil_apply: ncomp must be 1..3");
+    return launch_stencil(op, dtype, src, dst, ncomp, nx, ny, nz, dx, (hipStream_t)stream);
+}
+
+int max_cell_speed(nslgf_t h, const void* u, int nx, int ny, int nz, int dtype, double* out, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(u && out, "max_cell_speed: null pointer");
+    const int nb = 1024;
+    NSLGF_TRY(h->partial.ensure(nb * sizeof(double)));
+    hipStream_t s = (hipStream_t)stream;
+    NSLGF_TRY(launch_max_speed(dtype, u, nx, ny, nz, (double*)h->partial.p, nb, s));
+    std::vector<double> host(nb);
+    NSLGF_HIP_CHECK(hipMemcpyAsync(host.data(), h->partial.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (double v : host) m = v > m ? v : m;
+    *out = m;
+    return NSLGF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Pencil FFT building blocks for CDNA4 (gfx950): Stockham passes on register-held elements with
+// LDS exchanges between passes.
+//
+// A length-L transform is split over TP = L / E threads, each holding E complex values in
+// registers.  A pass of radix R with span NS (product of the earlier radices) processes the
+// butterflies j = t + b * TP (b < E / R) of thread t: it reads x[j + r L/R], r < R, twiddles them by
+// W_{NS R}^{r (j mod NS)}, applies the length-R DFT and writes the outputs to
+// (j div NS) NS R + (j mod NS) + r NS.  Outputs of the last pass therefore sit at j + r L/R_last in
+// natural order, which is also the input layout of a following transform whose first radix is
+// R_last (used to fuse forward transform, spectral multiply and inverse transform without an
+// exchange).  Forward transforms use e^{-2 pi i jk/L}; inverse ones e^{+2 pi i jk/L}; neither scales.
+#pragma once
+
+#include "common.h"
+
+namespace nslgf {
+
+template <int... Rs> struct RList {};
+
+template <class A, class B> struct RevImpl;
+template <int... D> struct RevImpl<RList<>, RList<D...>> { using type = RList<D...>; };
+template <int H, int... T, int... D> struct RevImpl<RList<H, T...>, RList<D...>> {
+    using type = typename RevImpl<RList<T...>, RList<H, D...>>::type;
+};
+template <class A> using Reverse = typename RevImpl<A, RList<>>::type;
+
+template <class A> struct First;
+template <int H, int... T> struct First<RList<H, T...>> { static constexpr int value = H; };
+template <class A> struct Last;
+template <int H> struct Last<RList<H>> { static constexpr int value = H; };
+template <int H, int H2, int... T> struct Last<RList<H, H2, T...>> { static constexpr int value = Last<RList<H2, T...>>::value; };
+
+// Radix plan per length: forward radix list and elements per thread (every radix divides E).
+template <int L> struct Plan1D;
+#define NSLGF_FFT_PLAN(L_, E_, ...)                                                                \
+    template <> struct Plan1D<L_> {                                                                \
+        static constexpr int E = E_;                                                               \
+        using Fwd = RList<__VA_ARGS__>;                                                            \
+    };
+NSLGF_FFT_PLAN(8, 8, 8)
+NSLGF_FFT_PLAN(16, 4, 4, 4)
+NSLGF_FFT_PLAN(24, 24, 3, 8)
+NSLGF_FFT_PLAN(32, 8, 4, 8)
+NSLGF_FFT_PLAN(48, 12, 3, 4, 4)
+NSLGF_FFT_PLAN(64, 8, 8, 8)
+NSLGF_FFT_PLAN(80, 20, 5, 4, 4)
+NSLGF_FFT_PLAN(96, 24, 3, 4, 8)
+NSLGF_FFT_PLAN(128, 8, 2, 8, 8)
+NSLGF_FFT_PLAN(160, 20, 5, 2, 4, 4)
+NSLGF_FFT_PLAN(192, 24, 3, 8, 8)
+NSLGF_FFT_PLAN(256, 8, 4, 8, 8)
+NSLGF_FFT_PLAN(320, 20, 5, 4, 4, 4)
+NSLGF_FFT_PLAN(384, 24, 3, 2, 8, 8)
+NSLGF_FFT_PLAN(512, 16, 8, 8, 8)
+#undef NSLGF_FFT_PLAN
+
+// Columns per workgroup of the strided (column-tile) kernels: one 128-byte row segment at least,
+// and at least one wavefront per workgroup.
+template <typename T>
+__host__ __device__ constexpr int col_tb(int tp) {
+    const int base = (int)(128 / (2 * sizeof(T)));
+    return (tp * base >= 64) ? base : 64 / tp;
+}
+// Rows per workgroup of the contiguous-row kernels.
+__host__ __device__ constexpr int row_rpw(int tp) { return tp >= 256 ? 1 : 256 / tp; }
+
+// ---- length-R DFTs on registers -------------------------------------------------------------
+template <typename T, int R, bool INV> struct DFT;
+
+template <typename T, bool INV> struct DFT<T, 2, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        cplx<T> a = v[0], b = v[1];
+        v[0] = cadd<T>(a, b);
+        v[1] = csub<T>(a, b);
+    }
+};
+
+template <typename T, bool INV> struct DFT<T, 4, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        cplx<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
+        cplx<T> t2 = cadd<T>(v[1], v[3]), t3 = csub<T>(v[1], v[3]);
+        // forward: X1 = t1 - i t3, X3 = t1 + i t3; inverse swaps the sign of i
+        cplx<T> it3 = INV ? cmul_i<T>(t3) : cmul_mi<T>(t3);
+        v[0] = cadd<T>(t0, t2);
+        v[2] = csub<T>(t0, t2);
+        v[1] = cadd<T>(t1, it3);
+        v[3] = csub<T>(t1, it3);
+    }
+};
+
+template <typename T, bool INV> struct DFT<T, 8, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        // even / odd split into two length-4 DFTs, then X[k] = E[k] +- W8^k O[k]
+        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        DFT<T, 4, INV>::run(e);
+        DFT<T, 4, INV>::run(o);
+        const T c = (T)0.70710678118654752440084436210484903928;
+        // W8^1 = c (1 - i) forward, c (1 + i) inverse; W8^2 = -i / +i; W8^3 = -c (1 + i) / c (-1 + i)
+        cplx<T> o1 = INV ? mk<T>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                         : mk<T>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+        cplx<T> o2 = INV ? cmul_i<T>(o[2]) : cmul_mi<T>(o[2]);
+        cplx<T> o3 = INV ? mk<T>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                         : mk<T>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+        v[0] = cadd<T>(e[0], o[0]);
+        v[4] = csub<T>(e[0], o[0]);
+        v[1] = cadd<T>(e[1], o1);
+        v[5] = csub<T>(e[1], o1);
+        v[2] = cadd<T>(e[2], o2);
+        v[6] = csub<T>(e[2], o2);
+        v[3] = cadd<T>(e[3], o3);
+        v[7] = csub<T>(e[3], o3);
+    }
+};
+
+template <typename T, bool INV> struct DFT<T, 3, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        const T h = (T)0.86602540378443864676372317075293618347;  // sin(2 pi / 3)
+        cplx<T> s = cadd<T>(v[1], v[2]), d = csub<T>(v[1], v[2]);
+        cplx<T> m = mk<T>(v[0].x - (T)0.5 * s.x, v[0].y - (T)0.5 * s.y);
+        // forward: X1 = m - i h d, X2 = m + i h d
+        cplx<T> ihd = INV ? cmul_i<T>(cscale<T>(d, h)) : cmul_mi<T>(cscale<T>(d, h));
+        v[0] = cadd<T>(v[0], s);
+        v[1] = cadd<T>(m, ihd);
+        v[2] = csub<T>(m, ihd);
+    }
+};
+
+template <typename T, bool INV> struct DFT<T, 5, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        const T c1 = (T)0.30901699437494742410229341718281905886;   // cos(2 pi / 5)
+        const T c2 = (T)-0.80901699437494742410229341718281905886;  // cos(4 pi / 5)
+        const T s1 = (T)0.95105651629515357211643933337938214340;   // sin(2 pi / 5)
+        const T s2 = (T)0.58778525229247312916870595463907276860;   // sin(4 pi / 5)
+        cplx<T> t1 = cadd<T>(v[1], v[4]), t2 = cadd<T>(v[2], v[3]);
+        cplx<T> d1 = csub<T>(v[1], v[4]), d2 = csub<T>(v[2], v[3]);
+        cplx<T> a1 = mk<T>(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+        cplx<T> a2 = mk<T>(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+        cplx<T> b1 = mk<T>(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+        cplx<T> b2 = mk<T>(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+        // forward: X1 = a1 - i b1, X4 = a1 + i b1, X2 = a2 - i b2, X3 = a2 + i b2
+        cplx<T> ib1 = INV ? cmul_i<T>(b1) : cmul_mi<T>(b1);
+        cplx<T> ib2 = INV ? cmul_i<T>(b2) : cmul_mi<T>(b2);
+        v[0] = cadd<T>(v[0], cadd<T>(t1, t2));
+        v[1] = cadd<T>(a1, ib1);
+        v[4] = csub<T>(a1, ib1);
+        v[2] = cadd<T>(a2, ib2);
+        v[3] = csub<T>(a2, ib2);
+    }
+};
+
+// ---- passes -----------------------------------------------------------------------------------
+// tw: root table tw[m] = exp(-2 pi i m / L), m < L (forward); the inverse conjugates it.
+template <typename T, int L, int E, int TP, bool INV, int NS, int R>
+__device__ __forceinline__ void pass_compute(cplx<T>* v, int t, const cplx<T>* __restrict__ tw) {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        if constexpr (NS > 1) {
+            const int j = t + b * TP;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const cplx<T> w = tw[r * k * (L / (NS * R))];
+                v[b * R + r] = INV ? cmulc<T>(v[b * R + r], w) : cmul<T>(v[b * R + r], w);
+            }
+        }
+        DFT<T, R, INV>::run(v + b * R);
+    }
+}
+
+template <typename T, int L, int E, int TP, int NS, int R, class Acc>
+__device__ __forceinline__ void pass_store(const cplx<T>* v, int t, Acc& acc) {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = t + b * TP;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc(base + r * NS) = v[b * R + r];
+    }
+}
+
+template <typename T, int L, int E, int TP, int R, class Acc>
+__device__ __forceinline__ void pass_load(cplx<T>* v, int t, Acc& acc) {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b * R + r] = acc(j + r * (L / R));
+    }
+}
+
+template <typename T, int L, int E, int TP, bool INV, int NS, class RL> struct Runner;
+
+template <typename T, int L, int E, int TP, bool INV, int NS, int R>
+struct Runner<T, L, E, TP, INV, NS, RList<R>> {
+    template <class Acc>
+    __device__ __forceinline__ static void run(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc&) {
+        pass_compute<T, L, E, TP, INV, NS, R>(v, t, tw);
+    }
+};
+
+template <typename T, int L, int E, int TP, bool INV, int NS, int R, int R2, int... Rest>
+struct Runner<T, L, E, TP, INV, NS, RList<R, R2, Rest...>> {
+    template <class Acc>
+    __device__ __forceinline__ static void run(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
+        pass_compute<T, L, E, TP, INV, NS, R>(v, t, tw);
+        __syncthreads();
+        pass_store<T, L, E, TP, NS, R>(v, t, acc);
+        __syncthreads();
+        pass_load<T, L, E, TP, R2>(v, t, acc);
+        Runner<T, L, E, TP, INV, NS * R, RList<R2, Rest...>>::run(v, t, tw, acc);
+    }
+};
+
+// Full transform on registers: input v[b R1 + r] = x[t + b TP + r L/R1] (R1 = first radix of the
+// list), output v[b Rl + r] = X[t + b TP + r L/Rl] (Rl = last radix).
+template <typename T, int L, bool INV, class RL, class Acc>
+__device__ __forceinline__ void fft_regs(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
+    constexpr int E = Plan1D<L>::E;
+    Runner<T, L, E, L / E, INV, 1, RL>::run(v, t, tw, acc);
+}
+
+// LDS accessor of the column-tile kernels: element pos of column c, columns interleaved.
+template <typename T, int TB>
+struct ColAcc {
+    cplx<T>* base;
+    int c;
+    __device__ __forceinline__ cplx<T>& operator()(int pos) { return base[(pos + (pos >> 4)) * TB + c]; }
+};
+template <int L> __host__ __device__ constexpr int col_lds_len() { return L + L / 16 + 1; }
+
+// LDS accessor of the row kernels: one contiguous (padded) segment per row.
+template <typename T>
+struct RowAcc {
+    cplx<T>* base;
+    __device__ __forceinline__ cplx<T>& operator()(int pos) { return base[pos + (pos >> 4)]; }
+};
+template <int L> __host__ __device__ constexpr int row_lds_len() { return L + 1 + (L + 1) / 16 + 1; }
+
+}  // namespace nslgf

@@ -1,0 +1,103 @@
+// Host-side launchers of the library's kernels (internal interface between the C-ABI layer and the
+// kernel translation units).  Every launcher enqueues on `stream` and returns an nslgf status.
+#pragma once
+
+#include "common.h"
+
+namespace nslgf {
+
+// ---- FFT passes (lgf_conv.hip) ----------------------------------------------------------------
+// Supported padded lengths P (2,3,5-smooth, even) of the zero-padded convolution.
+bool fft_length_supported(int P);
+int next_supported_length(int n);  // smallest supported P >= n, or -1
+
+// Columns per workgroup of the column-tile kernel of length L for dtype (used for spectrum layout).
+int col_tile_width(int L, int dtype);
+
+// Root twiddle table exp(-2 pi i m / L), m < L, of the dtype (owned by the caller; filled by host).
+int make_twiddles(int L, int dtype, void** dev_out);
+
+struct RowPass {
+    const void* in;
+    void* out;
+    long long nrows;      // rows per component
+    long long in_row;     // element stride between rows (real elements for R2C input, complex for C2R input)
+    long long out_row;
+    long long in_comp, out_comp;  // component strides in elements
+    int ncomp;
+    int n_io;             // R2C: real inputs per row (rest zero); C2R: real outputs kept per row
+    const void* tw_half;  // root table of length P/2 (complex FFT)
+    const void* tw_full;  // root table of length P (real pre/post processing)
+};
+int launch_row_r2c(int P, int dtype, const RowPass& a, hipStream_t s);
+int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s);
+
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_CONV = 2 };
+struct ColPass {
+    const void* in;
+    void* out;
+    int ncols;            // valid columns (complex elements contiguous in memory)
+    int nouter;           // independent column groups (grid y)
+    long long in_outer, out_outer;  // element stride between groups
+    long long in_row, out_row;      // element stride between transform elements
+    long long in_comp, out_comp;
+    int ncomp;
+    int n_in, n_out;      // nonzero inputs / kept outputs along the transform
+    const void* tw;       // root table of length L
+    // COL_CONV only: real spectrum laid out [Py/2+1][tiles][L/2+1][TB]; outer index ky folds to
+    // min(ky, outer_period - ky).
+    const void* khat;
+    int khat_tiles;
+    int outer_period;
+    double scale;
+};
+int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s);
+
+// ---- LGF table (lgf_table.hip) ------------------------------------------------------------------
+// Host evaluation of g(n) with the same method as the device table builder.
+double lgf_value_host(int n1, int n2, int n3);
+// Builds the real FP64 even kernel g on the Px*Py*Pz padded lattice into dev_kernel (caller allocates
+// Px*Py*Pz doubles).
+int build_padded_lgf(int Px, int Py, int Pz, double* dev_kernel, hipStream_t s);
+// Extracts the real spectrum (times `scale`) from the complex FFT of the kernel (layout
+// [Pz][Py][XP] complex double) into the column-tile layout used by COL_CONV, in dtype.
+int extract_spectrum(const void* spec, int Px, int Py, int Pz, long long XP, double scale, int tb, int tiles,
+                     int dtype, void* khat, hipStream_t s);
+
+// ---- integrating factor (intfac.hip) ------------------------------------------------------------
+// Host: w[k] = e^{-2 alpha} I_k(2 alpha), k = 0..r (returns r, the truncation radius for the dtype).
+int if_weights(double alpha, int dtype, double* w, int wmax);
+constexpr int kIfMaxRadius = 63;
+int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz,
+                   const double* w, int radius, hipStream_t s);
+
+// ---- stencils (stencils.hip) --------------------------------------------------------------------
+int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
+                   hipStream_t s);
+
+// Fused IF-HERK stage kernels (herk.hip)
+struct StageCoef {
+    double c_q;          // coefficient of q in r (1)
+    double c_w1, c_w2;   // dt * a~_{i1}, dt * a~_{i2}
+    double c_g;          // -a~_{ii} dt
+    int nbuf;            // the nonlinear term is restricted to the box shrunk by nbuf cells
+    int copy_q;          // 1: copy u into q first and use it as q (stage 1: q^1 = u_k)
+};
+// r = c_q q + c_w1 w1 + c_w2 w2 + c_g M_soln Ntilde(u); (w pointers may be null)
+int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, const void* w2, void* r,
+                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s);
+// s = M_supp Dbar r
+int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, int ny, int nz, double dx,
+                      hipStream_t s);
+// y = r - G dhat (in place into r); w_new = (y - base) * inv  where base = c_q q + c_w1 w1 + c_w2 w2 (optional)
+int launch_stage_project(int dtype, void* r, const void* dhat, const void* q, const void* w1, const void* w2,
+                         double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny, int nz,
+                         double dx, hipStream_t s);
+// out = a*x + b*y + c*z (elementwise over n elements; y, z may be null)
+int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
+                 long long n, hipStream_t s);
+// max over cells of the cell-centred speed
+int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
+                     hipStream_t s);
+
+}  // namespace nslgf

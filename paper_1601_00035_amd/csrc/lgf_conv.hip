@@ -1,0 +1,355 @@
+// Zero-padded FFT convolution passes of the LGF solve (Sec. 2.2, Eq. dpoisson_conv).
+//
+// The box convolution y = dx^2 g * s equals, on the box, the cyclic convolution of the zero-padded
+// source with the LGF wrapped onto a padded lattice of P >= 2n - 1 points per axis.  One scalar
+// solve is five passes over HBM:
+//   1. rows along x: real -> half spectrum (P/2 + 1 complex), n_x inputs, the rest implicit zeros;
+//   2. columns along y: forward, n_y nonzero inputs -> P outputs;
+//   3. columns along z: forward (n_z nonzero inputs), times the real even kernel spectrum,
+//      inverse, keeping the n_z box outputs -- all in registers, one HBM round trip;
+//   4. columns along y: inverse, keeping the n_y box outputs;
+//   5. rows along x: half spectrum -> real, keeping the n_x box outputs.
+// Rows are contiguous; the column passes work on tiles of TB adjacent columns (one 128-byte
+// segment per transform element) so that every global access is coalesced without transposes.
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "fft.h"
+#include "kernels.h"
+
+namespace nslgf {
+
+// ---------------------------------------------------------------------------------------------------
+template <typename T, int LH>
+__global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
+    using P = Plan1D<LH>;
+    constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
+    using RL = typename P::Fwd;
+    constexpr int LD = row_lds_len<LH>();
+    __shared__ cplx<T> lds[RPW * LD];
+    const int tid = threadIdx.x;
+    const int rl = tid / TP, t = tid % TP;
+    const long long row = (long long)blockIdx.x * RPW + rl;
+    const int comp = blockIdx.y;
+    const bool valid = row < a.nrows;
+    const T* in = (const T*)a.in + comp * a.in_comp + (valid ? row : 0) * a.in_row;
+    cplx<T>* out = (cplx<T>*)a.out + comp * a.out_comp + (valid ? row : 0) * a.out_row;
+    const cplx<T>* twh = (const cplx<T>*)a.tw_half;
+    const cplx<T>* twf = (const cplx<T>*)a.tw_full;
+    RowAcc<T> acc{lds + rl * LD};
+    cplx<T> v[E];
+    constexpr int R1 = First<RL>::value;
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int m = 2 * (j + r * (LH / R1));  // z[n] = x[2n] + i x[2n+1]
+            const T re = (valid && m < a.n_io) ? in[m] : (T)0;
+            const T im = (valid && m + 1 < a.n_io) ? in[m + 1] : (T)0;
+            v[b * R1 + r] = mk<T>(re, im);
+        }
+    }
+    fft_regs<T, LH, false, RL>(v, t, twh, acc);
+    constexpr int RLs = Last<RL>::value;
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / RLs; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < RLs; ++r) acc(j + r * (LH / RLs)) = v[b * RLs + r];
+    }
+    __syncthreads();
+    if (valid) {
+        // X[k] = E[k] + W_P^k O[k], E = (Z[k] + conj Z[-k]) / 2, O = -i (Z[k] - conj Z[-k]) / 2
+        for (int k = t; k < LH; k += TP) {
+            const cplx<T> zk = acc(k);
+            const cplx<T> zm = acc(k == 0 ? 0 : LH - k);
+            const T ex = (T)0.5 * (zk.x + zm.x), ey = (T)0.5 * (zk.y - zm.y);
+            const cplx<T> o = mk<T>((T)0.5 * (zk.y + zm.y), (T)-0.5 * (zk.x - zm.x));
+            const cplx<T> wo = cmul<T>(twf[k], o);
+            out[k] = mk<T>(ex + wo.x, ey + wo.y);
+        }
+        if (t == 0) {
+            const cplx<T> z0 = acc(0);
+            out[LH] = mk<T>(z0.x - z0.y, (T)0);
+        }
+    }
+}
+
+template <typename T, int LH>
+__global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
+    using P = Plan1D<LH>;
+    constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
+    using RL = Reverse<typename P::Fwd>;
+    constexpr int LD = row_lds_len<LH>();
+    __shared__ cplx<T> lds[RPW * LD];
+    const int tid = threadIdx.x;
+    const int rl = tid / TP, t = tid % TP;
+    const long long row = (long long)blockIdx.x * RPW + rl;
+    const int comp = blockIdx.y;
+    const bool valid = row < a.nrows;
+    const cplx<T>* in = (const cplx<T>*)a.in + comp * a.in_comp + (valid ? row : 0) * a.in_row;
+    T* out = (T*)a.out + comp * a.out_comp + (valid ? row : 0) * a.out_row;
+    const cplx<T>* twh = (const cplx<T>*)a.tw_half;
+    const cplx<T>* twf = (const cplx<T>*)a.tw_full;
+    RowAcc<T> acc{lds + rl * LD};
+    for (int k = t; k <= LH; k += TP) acc(k) = valid ? in[k] : mk<T>((T)0, (T)0);
+    __syncthreads();
+    cplx<T> v[E];
+    constexpr int R1 = First<RL>::value;
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int k = j + r * (LH / R1);
+            const cplx<T> xk = acc(k), xm = acc(LH - k);
+            // Z = (X[k] + conj X[LH-k]) + i W_P^{-k} (X[k] - conj X[LH-k])
+            const cplx<T> d = mk<T>(xk.x - xm.x, xk.y + xm.y);
+            const cplx<T> o = cmulc<T>(d, twf[k]);
+            v[b * R1 + r] = mk<T>(xk.x + xm.x - o.y, xk.y - xm.y + o.x);
+        }
+    }
+    fft_regs<T, LH, true, RL>(v, t, twh, acc);
+    constexpr int RLs = Last<RL>::value;
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RLs; ++b) {
+            const int j = t + b * TP;
+#pragma unroll
+            for (int r = 0; r < RLs; ++r) {
+                const int m = 2 * (j + r * (LH / RLs));
+                if (m < a.n_io) out[m] = v[b * RLs + r].x;
+                if (m + 1 < a.n_io) out[m + 1] = v[b * RLs + r].y;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------
+template <typename T, int L, int MODE>
+__global__ void __launch_bounds__(512) k_col(ColPass a) {
+    using P = Plan1D<L>;
+    constexpr int E = P::E, TP = L / E, TB = col_tb<T>(TP);
+    using RF = typename P::Fwd;
+    using RI = Reverse<RF>;
+    constexpr int LD = col_lds_len<L>();
+    __shared__ cplx<T> lds[TB * LD];
+    const int tid = threadIdx.x;
+    const int c = tid % TB, t = tid / TB;
+    const int col = blockIdx.x * TB + c;
+    const bool valid = col < a.ncols;
+    const int outer = blockIdx.y, comp = blockIdx.z;
+    const cplx<T>* in = (const cplx<T>*)a.in + comp * a.in_comp + (long long)outer * a.in_outer + (valid ? col : 0);
+    cplx<T>* out = (cplx<T>*)a.out + comp * a.out_comp + (long long)outer * a.out_outer + (valid ? col : 0);
+    const cplx<T>* tw = (const cplx<T>*)a.tw;
+    ColAcc<T, TB> acc{lds, c};
+    cplx<T> v[E];
+    constexpr int R1 = (MODE == COL_INV) ? First<RI>::value : First<RF>::value;
+#pragma unroll
+    for (int b = 0; b < E / R1; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int row = j + r * (L / R1);
+            v[b * R1 + r] = (valid && row < a.n_in) ? in[(long long)row * a.in_row] : mk<T>((T)0, (T)0);
+        }
+    }
+    if constexpr (MODE == COL_INV) {
+        fft_regs<T, L, true, RI>(v, t, tw, acc);
+    } else {
+        fft_regs<T, L, false, RF>(v, t, tw, acc);
+    }
+    if constexpr (MODE == COL_CONV) {
+        constexpr int RLf = Last<RF>::value;
+        const int kyf = min(outer, a.outer_period - outer);
+        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + blockIdx.x) * (L / 2 + 1) * TB + c;
+        const T sc = (T)a.scale;
+#pragma unroll
+        for (int b = 0; b < E / RLf; ++b) {
+            const int j = t + b * TP;
+#pragma unroll
+            for (int r = 0; r < RLf; ++r) {
+                const int kz = j + r * (L / RLf);
+                const int kzf = min(kz, L - kz);
+                const T k = kh[kzf * TB] * sc;
+                v[b * RLf + r] = cscale<T>(v[b * RLf + r], k);
+            }
+        }
+        fft_regs<T, L, true, RI>(v, t, tw, acc);
+    }
+    using ROut = typename std::conditional<MODE == COL_FWD, RF, RI>::type;
+    constexpr int RO = Last<ROut>::value;
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < E / RO; ++b) {
+            const int j = t + b * TP;
+#pragma unroll
+            for (int r = 0; r < RO; ++r) {
+                const int row = j + r * (L / RO);
+                if (row < a.n_out) out[(long long)row * a.out_row] = v[b * RO + r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------
+static const int kLengths[] = {16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 512};
+
+bool fft_length_supported(int P) {
+    for (int L : kLengths)
+        if (L == P) return true;
+    return false;
+}
+
+int next_supported_length(int n) {
+    for (int L : kLengths)
+        if (L >= n) return L;
+    return -1;
+}
+
+template <int L> static int tb_of(int dtype) {
+    constexpr int TP = L / Plan1D<L>::E;
+    return dtype == NSLGF_F32 ? col_tb<float>(TP) : col_tb<double>(TP);
+}
+
+int col_tile_width(int L, int dtype) {
+    switch (L) {
+#define NSLGF_CASE(L_) case L_: return tb_of<L_>(dtype);
+        NSLGF_CASE(16) NSLGF_CASE(32) NSLGF_CASE(48) NSLGF_CASE(64) NSLGF_CASE(96) NSLGF_CASE(128)
+        NSLGF_CASE(160) NSLGF_CASE(192) NSLGF_CASE(256) NSLGF_CASE(320) NSLGF_CASE(384) NSLGF_CASE(512)
+#undef NSLGF_CASE
+    }
+    return -1;
+}
+
+int make_twiddles(int L, int dtype, void** dev_out) {
+    const size_t esz = 2 * dtype_size(dtype);
+    std::vector<unsigned char> host(esz * L);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (int m = 0; m < L; ++m) {
+        // exp(-2 pi i m / L) evaluated in extended precision and rounded once to the dtype
+        // (accurately rounded twiddles); the exact quarter-period values are set directly
+        const long double ang = two_pi * (long double)m / (long double)L;
+        long double c = cosl(ang), s = sinl(ang);
+        if (m == 0) { c = 1; s = 0; }
+        if (4 * m == L) { c = 0; s = 1; }
+        if (2 * m == L) { c = -1; s = 0; }
+        if (4 * m == 3 * L) { c = 0; s = -1; }
+        if (dtype == NSLGF_F32) {
+            float* p = (float*)host.data();
+            p[2 * m] = (float)c;
+            p[2 * m + 1] = (float)-s;
+        } else {
+            double* p = (double*)host.data();
+            p[2 * m] = (double)c;
+            p[2 * m + 1] = (double)-s;
+        }
+    }
+    void* d = nullptr;
+    if (hipMalloc(&d, host.size()) != hipSuccess) {
+        set_error("hipMalloc(twiddles) failed");
+        return NSLGF_ENOMEM;
+    }
+    NSLGF_HIP_CHECK(hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice));
+    *dev_out = d;
+    return NSLGF_OK;
+}
+
+template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s) {
+    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
+    dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
+    hipLaunchKernelGGL((k_row_r2c<T, LH>), grid, dim3(RPW * TP), 0, s, a);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s) {
+    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
+    dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
+    hipLaunchKernelGGL((k_row_c2r<T, LH>), grid, dim3(RPW * TP), 0, s, a);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int L, int MODE> static int do_col(const ColPass& a, hipStream_t s) {
+    constexpr int TP = L / Plan1D<L>::E, TB = col_tb<T>(TP);
+    if (a.nouter > 65535 || a.ncomp > 65535) {
+        set_error("column pass grid too large");
+        return NSLGF_EINVAL;
+    }
+    dim3 grid(ceil_div(a.ncols, TB), a.nouter, a.ncomp);
+    hipLaunchKernelGGL((k_col<T, L, MODE>), grid, dim3(TB * TP), 0, s, a);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+#define NSLGF_ROW_SWITCH(FN, T)                                                                    \
+    switch (P) {                                                                                   \
+        case 16: return FN<T, 8>(a, s);                                                            \
+        case 32: return FN<T, 16>(a, s);                                                           \
+        case 48: return FN<T, 24>(a, s);                                                           \
+        case 64: return FN<T, 32>(a, s);                                                           \
+        case 96: return FN<T, 48>(a, s);                                                           \
+        case 128: return FN<T, 64>(a, s);                                                          \
+        case 160: return FN<T, 80>(a, s);                                                          \
+        case 192: return FN<T, 96>(a, s);                                                          \
+        case 256: return FN<T, 128>(a, s);                                                         \
+        case 320: return FN<T, 160>(a, s);                                                         \
+        case 384: return FN<T, 192>(a, s);                                                         \
+        case 512: return FN<T, 256>(a, s);                                                         \
+    }
+
+int launch_row_r2c(int P, int dtype, const RowPass& a, hipStream_t s) {
+    if (dtype == NSLGF_F32) {
+        NSLGF_ROW_SWITCH(do_r2c, float)
+    } else {
+        NSLGF_ROW_SWITCH(do_r2c, double)
+    }
+    set_error("unsupported padded length " + std::to_string(P));
+    return NSLGF_EUNSUPPORTED;
+}
+
+int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s) {
+    if (dtype == NSLGF_F32) {
+        NSLGF_ROW_SWITCH(do_c2r, float)
+    } else {
+        NSLGF_ROW_SWITCH(do_c2r, double)
+    }
+    set_error("unsupported padded length " + std::to_string(P));
+    return NSLGF_EUNSUPPORTED;
+}
+
+#define NSLGF_COL_SWITCH(T, MODE)                                                                  \
+    switch (L) {                                                                                   \
+        case 16: return do_col<T, 16, MODE>(a, s);                                                 \
+        case 32: return do_col<T, 32, MODE>(a, s);                                                 \
+        case 48: return do_col<T, 48, MODE>(a, s);                                                 \
+        case 64: return do_col<T, 64, MODE>(a, s);                                                 \
+        case 96: return do_col<T, 96, MODE>(a, s);                                                 \
+        case 128: return do_col<T, 128, MODE>(a, s);                                               \
+        case 160: return do_col<T, 160, MODE>(a, s);                                               \
+        case 192: return do_col<T, 192, MODE>(a, s);                                               \
+        case 256: return do_col<T, 256, MODE>(a, s);                                               \
+        case 320: return do_col<T, 320, MODE>(a, s);                                               \
+        case 384: return do_col<T, 384, MODE>(a, s);                                               \
+        case 512: return do_col<T, 512, MODE>(a, s);                                               \
+    }
+
+template <typename T> static int col_dispatch(int L, ColMode mode, const ColPass& a, hipStream_t s) {
+    if (mode == COL_FWD) {
+        NSLGF_COL_SWITCH(T, COL_FWD)
+    } else if (mode == COL_INV) {
+        NSLGF_COL_SWITCH(T, COL_INV)
+    } else {
+        NSLGF_COL_SWITCH(T, COL_CONV)
+    }
+    set_error("unsupported transform length " + std::to_string(L));
+    return NSLGF_EUNSUPPORTED;
+}
+
+int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s) {
+    return dtype == NSLGF_F32 ? col_dispatch<float>(L, mode, a, s) : col_dispatch<double>(L, mode, a, s);
+}
+
+}  // namespace nslgf

@@ -1,0 +1,305 @@
+// Staggered-grid point operators of Appendix A on one box, and the fused IF-HERK stage kernels.
+//
+// Every input is read with zero extension outside the box and every output is produced on the box
+// only (the mask operators of Sec. 4.1).  Components (2) and (3) of each printed operator follow from
+// component (1) by the cyclic permutation (component, axis): 1 -> 2 -> 3 -> 1 with x -> y -> z -> x.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace nslgf {
+
+template <typename T> struct Fld {
+    const T* p;
+    int nx, ny, nz;
+    __device__ __forceinline__ T operator()(int i, int j, int k) const {
+        return (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) ? p[((long long)k * ny + j) * nx + i] : (T)0;
+    }
+};
+
+template <typename T> struct Vec3 {
+    Fld<T> c[3];
+};
+
+template <typename T>
+__device__ __forceinline__ Vec3<T> vec3(const T* p, int nx, int ny, int nz) {
+    const long long n = (long long)nx * ny * nz;
+    Vec3<T> v;
+    for (int q = 0; q < 3; ++q) v.c[q] = Fld<T>{p + q * n, nx, ny, nz};
+    return v;
+}
+
+// e = C f at edge (i, j, k), component q (0-based); the curl of the zero-extended face field, so
+// it is also defined one layer outside the box.
+template <typename T>
+__device__ __forceinline__ T curl_at(const Vec3<T>& f, int q, int i, int j, int k, T idx) {
+    if (q == 0) return (f.c[1](i, j, k) - f.c[1](i, j, k + 1) + f.c[2](i, j + 1, k) - f.c[2](i, j, k)) * idx;
+    if (q == 1) return (f.c[2](i, j, k) - f.c[2](i + 1, j, k) + f.c[0](i, j, k + 1) - f.c[0](i, j, k)) * idx;
+    return (f.c[0](i, j, k) - f.c[0](i, j + 1, k) + f.c[1](i + 1, j, k) - f.c[1](i, j, k)) * idx;
+}
+
+// Ntilde(f) at face (i, j, k), all three components (Eq. opr_def_nonlin and its cyclic images).
+template <typename T>
+__device__ __forceinline__ void nonlinear_at(const Vec3<T>& f, int i, int j, int k, T idx, T out[3]) {
+    T n1 = 0, n2 = 0, n3 = 0;
+#pragma unroll
+    for (int q = -1; q <= 0; ++q) {
+        n1 += curl_at(f, 1, i, j, k + q, idx) * (f.c[2](i, j, k + q) + f.c[2](i + 1, j, k + q)) -
+              curl_at(f, 2, i, j + q, k, idx) * (f.c[1](i, j + q, k) + f.c[1](i + 1, j + q, k));
+        n2 += curl_at(f, 2, i + q, j, k, idx) * (f.c[0](i + q, j, k) + f.c[0](i + q, j + 1, k)) -
+              curl_at(f, 0, i, j, k + q, idx) * (f.c[2](i, j, k + q) + f.c[2](i, j + 1, k + q));
+        n3 += curl_at(f, 0, i, j + q, k, idx) * (f.c[1](i, j + q, k) + f.c[1](i, j + q, k + 1)) -
+              curl_at(f, 1, i + q, j, k, idx) * (f.c[0](i + q, j, k) + f.c[0](i + q, j, k + 1));
+    }
+    out[0] = (T)0.25 * n1;
+    out[1] = (T)0.25 * n2;
+    out[2] = (T)0.25 * n3;
+}
+
+#define NSLGF_CELL_INDEX                                                                           \
+    const long long n = (long long)nx * ny * nz;                                                   \
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;                        \
+    if (idx >= n) return;                                                                          \
+    const int i = (int)(idx % nx);                                                                 \
+    const int j = (int)((idx / nx) % ny);                                                          \
+    const int k = (int)(idx / ((long long)nx * ny));
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(const T* c, T* f, int nx, int ny, int nz, T idx_) {
+    NSLGF_CELL_INDEX
+    Fld<T> C{c, nx, ny, nz};
+    const T v = C(i, j, k);
+    f[idx] = (C(i + 1, j, k) - v) * idx_;
+    f[n + idx] = (C(i, j + 1, k) - v) * idx_;
+    f[2 * n + idx] = (C(i, j, k + 1) - v) * idx_;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_div(const T* f, T* c, int nx, int ny, int nz, T idx_, int nbuf) {
+    NSLGF_CELL_INDEX
+    Vec3<T> F = vec3(f, nx, ny, nz);
+    const bool in_supp = i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf;
+    T v = (F.c[0](i, j, k) + F.c[1](i, j, k) + F.c[2](i, j, k) - F.c[0](i - 1, j, k) - F.c[1](i, j - 1, k) -
+           F.c[2](i, j, k - 1)) * idx_;
+    c[idx] = in_supp ? v : (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_curl(const T* f, T* e, int nx, int ny, int nz, T idx_) {
+    NSLGF_CELL_INDEX
+    Vec3<T> F = vec3(f, nx, ny, nz);
+    for (int q = 0; q < 3; ++q) e[q * n + idx] = curl_at(F, q, i, j, k, idx_);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_curl_bar(const T* e, T* f, int nx, int ny, int nz, T idx_) {
+    NSLGF_CELL_INDEX
+    Vec3<T> Ed = vec3(e, nx, ny, nz);
+    f[idx] = (Ed.c[1](i, j, k - 1) - Ed.c[1](i, j, k) + Ed.c[2](i, j, k) - Ed.c[2](i, j - 1, k)) * idx_;
+    f[n + idx] = (Ed.c[2](i - 1, j, k) - Ed.c[2](i, j, k) + Ed.c[0](i, j, k) - Ed.c[0](i, j, k - 1)) * idx_;
+    f[2 * n + idx] = (Ed.c[0](i, j - 1, k) - Ed.c[0](i, j, k) + Ed.c[1](i, j, k) - Ed.c[1](i - 1, j, k)) * idx_;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_nonlinear(const T* f, T* out, int nx, int ny, int nz, T idx_) {
+    NSLGF_CELL_INDEX
+    Vec3<T> F = vec3(f, nx, ny, nz);
+    T r[3];
+    nonlinear_at(F, i, j, k, idx_, r);
+    out[idx] = r[0];
+    out[n + idx] = r[1];
+    out[2 * n + idx] = r[2];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_laplacian(const T* a, T* out, int nx, int ny, int nz, T idx2) {
+    NSLGF_CELL_INDEX
+    const int comp = blockIdx.y;
+    Fld<T> A{a + comp * n, nx, ny, nz};
+    out[comp * n + idx] = (-(T)6 * A(i, j, k) + A(i + 1, j, k) + A(i - 1, j, k) + A(i, j + 1, k) + A(i, j - 1, k) +
+                           A(i, j, k + 1) + A(i, j, k - 1)) * idx2;
+}
+
+// r = c_q q + c_w1 w1 + c_w2 w2 + c_g M_soln Ntilde(u); optionally also copies u into q first
+// (stage 1 starts the step with q^1 = u_k).
+template <typename T>
+__global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1, const T* w2, T* r, T idx_,
+                                                   StageCoef c, int copy_q, int nx, int ny, int nz) {
+    NSLGF_CELL_INDEX
+    Vec3<T> U = vec3(u, nx, ny, nz);
+    const bool in_soln = i >= c.nbuf && i < nx - c.nbuf && j >= c.nbuf && j < ny - c.nbuf && k >= c.nbuf &&
+                         k < nz - c.nbuf;
+    T nl[3] = {0, 0, 0};
+    if (in_soln) nonlinear_at(U, i, j, k, idx_, nl);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long p = a * n + idx;
+        T qv;
+        if (copy_q) {
+            qv = u[p];
+            q[p] = qv;
+        } else {
+            qv = q[p];
+        }
+        double v = c.c_q * (double)qv + c.c_g * (double)nl[a];
+        if (w1) v += c.c_w1 * (double)w1[p];
+        if (w2) v += c.c_w2 * (double)w2[p];
+        r[p] = (T)v;
+    }
+}
+
+// y = r - G dhat (into r); if wnew: wnew = (y - (c_q q + c_w1 w1 + c_w2 w2)) * inv
+template <typename T>
+__global__ void __launch_bounds__(256) k_stage_project(T* r, const T* dhat, const T* q, const T* w1, const T* w2,
+                                                       double c_q, double c_w1, double c_w2, T* wnew, double inv,
+                                                       int nx, int ny, int nz, T idx_) {
+    NSLGF_CELL_INDEX
+    Fld<T> D{dhat, nx, ny, nz};
+    const T d0 = D(i, j, k);
+    const T g[3] = {(D(i + 1, j, k) - d0) * idx_, (D(i, j + 1, k) - d0) * idx_, (D(i, j, k + 1) - d0) * idx_};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long p = a * n + idx;
+        const T y = r[p] - g[a];
+        r[p] = y;
+        if (wnew) {
+            double base = c_q * (double)q[p];
+            if (w1) base += c_w1 * (double)w1[p];
+            if (w2) base += c_w2 * (double)w2[p];
+            wnew[p] = (T)(((double)y - base) * inv);
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_axpby(T* out, const T* x, double a, const T* y, double b, const T* z, double c,
+                                               long long n) {
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double v = a * (double)x[idx];
+    if (y) v += b * (double)y[idx];
+    if (z) v += c * (double)z[idx];
+    out[idx] = (T)v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_max_speed(const T* u, int nx, int ny, int nz, double* partial) {
+    const long long n = (long long)nx * ny * nz;
+    __shared__ double red[256];
+    double m = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int k = (int)(idx / ((long long)nx * ny));
+        Vec3<T> U = vec3(u, nx, ny, nz);
+        const double a = 0.5 * ((double)U.c[0](i, j, k) + (double)U.c[0](i - 1, j, k));
+        const double b = 0.5 * ((double)U.c[1](i, j, k) + (double)U.c[1](i, j - 1, k));
+        const double c = 0.5 * ((double)U.c[2](i, j, k) + (double)U.c[2](i, j, k - 1));
+        m = fmax(m, sqrt(a * a + b * b + c * c));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------------------------------
+template <typename T>
+static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    const T idx_ = (T)(1.0 / dx);
+    dim3 grid(ceil_div(n, 256)), block(256);
+    switch (op) {
+        case NSLGF_OP_GRAD: hipLaunchKernelGGL(k_grad<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
+        case NSLGF_OP_DIV: hipLaunchKernelGGL(k_div<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
+        case NSLGF_OP_CURL: hipLaunchKernelGGL(k_curl<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
+        case NSLGF_OP_CURL_BAR: hipLaunchKernelGGL(k_curl_bar<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
+        case NSLGF_OP_NONLINEAR: hipLaunchKernelGGL(k_nonlinear<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
+        case NSLGF_OP_LAPLACIAN:
+            hipLaunchKernelGGL(k_laplacian<T>, dim3(ceil_div(n, 256), ncomp), block, 0, s, (const T*)src, (T*)dst, nx, ny,
+                               nz, (T)(1.0 / (dx * dx)));
+            break;
+        default: set_error("stencil_apply: unknown operator"); return NSLGF_EINVAL;
+    }
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
+                   hipStream_t s) {
+    if (dtype == NSLGF_F32) return stencil_t<float>(op, src, dst, ncomp, nx, ny, nz, dx, s);
+    return stencil_t<double>(op, src, dst, ncomp, nx, ny, nz, dx, s);
+}
+
+int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, const void* w2, void* r,
+                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    const int copy_q = c.copy_q;
+    const StageCoef cc = c;
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_stage_rhs<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)u, (float*)q,
+                           (const float*)w1, (const float*)w2, (float*)r, (float)(1.0 / dx), cc, copy_q, nx, ny, nz);
+    else
+        hipLaunchKernelGGL(k_stage_rhs<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)u, (double*)q,
+                           (const double*)w1, (const double*)w2, (double*)r, 1.0 / dx, cc, copy_q, nx, ny, nz);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, int ny, int nz, double dx,
+                      hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_div<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)r, (float*)sdiv, nx,
+                           ny, nz, (float)(1.0 / dx), nbuf);
+    else
+        hipLaunchKernelGGL(k_div<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)r, (double*)sdiv, nx,
+                           ny, nz, 1.0 / dx, nbuf);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_stage_project(int dtype, void* r, const void* dhat, const void* q, const void* w1, const void* w2,
+                         double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny, int nz,
+                         double dx, hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_stage_project<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (float*)r,
+                           (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
+                           (float*)wnew, inv, nx, ny, nz, (float)(1.0 / dx));
+    else
+        hipLaunchKernelGGL(k_stage_project<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (double*)r,
+                           (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
+                           c_w2, (double*)wnew, inv, nx, ny, nz, 1.0 / dx);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
+                 long long n, hipStream_t s) {
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_axpby<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (float*)out, (const float*)x, a,
+                           (const float*)y, b, (const float*)z, c, n);
+    else
+        hipLaunchKernelGGL(k_axpby<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (double*)out, (const double*)x, a,
+                           (const double*)y, b, (const double*)z, c, n);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
+                     hipStream_t s) {
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_max_speed<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, dev_partial);
+    else
+        hipLaunchKernelGGL(k_max_speed<double>, dim3(nblocks), dim3(256), 0, s, (const double*)u, nx, ny, nz,
+                           dev_partial);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+}  // namespace nslgf

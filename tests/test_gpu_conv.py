@@ -1,0 +1,111 @@
+"""GPU parity of the LGF convolution (Sec. 2.2, Eq. dpoisson_conv) against the oracle's direct
+lattice sum, through the C ABI.  FP64 within 1e-12 and FP32 within 1e-6, relative to max|oracle|."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_00035_amd as nslgf
+import workloads
+from oracle import native
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def gpu_conv(src_np, dx, dtype=torch.float64):
+    t = torch.from_numpy(src_np).to(DEV, dtype)
+    return nslgf.lgf_convolve(t, dx).double().cpu().numpy()
+
+
+def test_compact_sphere_32_fp64_fp32():
+    s = workloads.compact_random_source(32, 12.0, seed=0)
+    ref = native.lgf_direct(s, 1.0)
+    assert rel(gpu_conv(s, 1.0), ref) < 1e-12
+    assert rel(gpu_conv(s, 1.0, torch.float32), ref) < 1e-6
+
+
+@pytest.mark.parametrize("shape", [(9, 13, 20), (33, 24, 40), (8, 12, 70), (5, 6, 150), (6, 150, 5), (150, 5, 6),
+                                   (1, 1, 1), (2, 3, 1), (17, 17, 17)])
+def test_ragged_boxes_fp64(shape):
+    """Non-cubic boxes whose padded sizes exercise radix 2, 3, 4, 5 and 8, several column tiles and a
+    ragged last tile."""
+    rng = np.random.default_rng(sum(shape))
+    s = rng.standard_normal(shape)
+    dx = 0.37
+    ref = native.lgf_direct(s, dx)
+    assert rel(gpu_conv(s, dx), ref) < 1e-12, shape
+    assert rel(gpu_conv(s, dx, torch.float32), ref) < 2e-6, shape
+
+
+def test_three_components_and_delta():
+    n = 24
+    s = np.zeros((3, n, n, n))
+    s[0, 3, 5, 7] = 1.0
+    s[1] = workloads.compact_random_source(n, 9.0, seed=4)
+    s[2, 20, 1, 2] = -2.0
+    dx = 0.5
+    ref = np.stack([native.lgf_direct(s[q], dx) for q in range(3)])
+    out = gpu_conv(s, dx)
+    assert rel(out, ref) < 1e-12
+    for q in range(3):
+        assert rel(out[q], ref[q]) < 1e-12
+
+
+def test_zero_source_and_linearity():
+    n = 20
+    z = np.zeros((n, n, n))
+    assert not gpu_conv(z, 1.0).any()
+    rng = np.random.default_rng(9)
+    a, b = rng.standard_normal((2, n, n, n))
+    ya, yb, yab = gpu_conv(a, 1.0), gpu_conv(b, 1.0), gpu_conv(2 * a - 3 * b, 1.0)
+    assert rel(yab, 2 * ya - 3 * yb) < 1e-13
+
+
+def test_laplacian_returns_source_128():
+    """At 128^3 (the IF-HERK step size) the 7-point Laplacian of the result equals the source
+    away from the box faces (where the stencil would need values outside the box)."""
+    n = 128
+    s = workloads.compact_random_source(n, 40.0, seed=2)
+    y = torch.from_numpy(gpu_conv(s, 1.0)).to(DEV)
+    lap = nslgf.stencil("laplacian", y, 1.0).cpu().numpy()
+    inner = (slice(1, -1),) * 3
+    assert np.abs(lap[inner] - s[inner]).max() < 1e-12 * np.abs(s).max()
+
+
+@pytest.mark.parametrize("n,dtype,tol", [(128, torch.float64, 1e-12), (256, torch.float64, 1e-12),
+                                         (256, torch.float32, 1e-6)])
+def test_ring_vorticity_sampled(n, dtype, tol):
+    """Full-size boxes in the benchmark's launch configuration (three vorticity components at once),
+    checked at seeded sample points against direct sums at those points."""
+    if n == 256:
+        _, dx, ring, _, _ = workloads.ring_case("conv256")
+    else:
+        _, dx, ring, _, _ = workloads.ring_case("step128")
+    w = workloads.ring_edge_vorticity(n, dx, ring)
+    out = nslgf.lgf_convolve(torch.from_numpy(w).to(DEV, dtype), dx).double().cpu().numpy()
+    tg = workloads.sample_targets(n, 64, seed=n)
+    tg = np.concatenate([tg, np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [n // 2, n // 2, n // 2]])])
+    for q in (0, 1):
+        ref = native.lgf_direct_targets(w[q], dx, tg)
+        got = out[q][tg[:, 0], tg[:, 1], tg[:, 2]]
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() < tol * scale, (q, np.abs(got - ref).max() / scale)
+    assert not out[2].any()  # omega_z = 0 convolves to exactly 0
+
+
+def test_invalid_arguments():
+    t = torch.zeros((4, 4, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.lgf_convolve(t, -1.0)
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.lgf_convolve(t, 1.0, out=t)
+    big = torch.zeros((1, 1, 300), dtype=torch.float64, device=DEV)
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.lgf_convolve(big, 1.0)
+    with pytest.raises(ValueError):
+        nslgf.lgf_convolve(torch.zeros((4, 4, 4), dtype=torch.float64), 1.0)

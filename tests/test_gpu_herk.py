@@ -1,0 +1,117 @@
+"""GPU parity of Vor2Vel and the IF-HERK step (Sec. 3.2, 3.3, 4.1, 5) against the oracle's plain
+recursion (the GPU uses the final-stage shortcut of the footnote of Sec. 3.2, equal up to rounding),
+plus properties that hold at any size for the 128^3 step."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_00035_amd as nslgf
+import workloads
+from oracle import ifherk, intfac, stencils
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _case(n, seed=1):
+    n, dx, ring, re, cfl = workloads.small_ring_case(n, seed)
+    w = workloads.ring_edge_vorticity(n, dx, ring)
+    return n, dx, w, re, cfl
+
+
+def test_vor2vel():
+    n, dx, w, _, _ = _case(28)
+    ref = ifherk.vor2vel(w, dx)
+    out = nslgf.vor2vel(torch.from_numpy(w).to(DEV), dx).cpu().numpy()
+    assert rel(out, ref) < 1e-12
+    out32 = nslgf.vor2vel(torch.from_numpy(w).to(DEV, torch.float32), dx).double().cpu().numpy()
+    assert rel(out32, ref) < 1e-6
+
+
+@pytest.mark.parametrize("scheme,n_buf", [("A", 0), ("A", 3), ("B", 2), ("C", 2)])
+def test_step_parity(scheme, n_buf):
+    n, dx, w, re, cfl = _case(24)
+    u0 = ifherk.vor2vel(w, dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    u_ref, d_ref = ifherk.step(u0, dt, dx, re, scheme, n_buf=n_buf)
+    u = torch.from_numpy(u0).to(DEV)
+    st = nslgf.HerkState(u, dx, dt, re, scheme, n_buf=n_buf)
+    st.step()
+    assert rel(u.cpu().numpy(), u_ref) < 1e-12
+    assert rel(st.d.cpu().numpy(), d_ref) < 1e-12
+    assert abs(st.t - dt) < 1e-15
+
+
+def test_two_steps_and_fp32():
+    n, dx, w, re, cfl = _case(20, seed=3)
+    u0 = ifherk.vor2vel(w, dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    u1, _ = ifherk.step(u0, dt, dx, re, "A", n_buf=2)
+    u2, d2 = ifherk.step(u1, dt, dx, re, "A", n_buf=2)
+    u = torch.from_numpy(u0).to(DEV)
+    st = nslgf.HerkState(u, dx, dt, re, "A", n_buf=2)
+    st.step()
+    st.step()
+    assert rel(u.cpu().numpy(), u2) < 1e-12
+    u32 = torch.from_numpy(u0).to(DEV, torch.float32)
+    st32 = nslgf.HerkState(u32, dx, dt, re, "A", n_buf=2)
+    st32.step()
+    st32.step()
+    assert rel(u32.double().cpu().numpy(), u2) < 1e-5
+
+
+def test_stage_order_enforced():
+    n = 8
+    u = torch.zeros((3, n, n, n), dtype=torch.float64, device=DEV)
+    st = nslgf.HerkState(u, 0.1, 0.01, 100.0)
+    with pytest.raises(nslgf.NslgfError):
+        st.stage(2)
+    st.stage(1)
+    with pytest.raises(nslgf.NslgfError):
+        st.stage(3)
+    st.stage(2)
+    st.stage(3)
+    assert not u.any()
+
+
+def test_stokes_case_gpu():
+    """Without vorticity-induced nonlinear terms (a field with Ntilde = 0 is not available, so this
+    checks the linear part): a compact divergence-free field of tiny amplitude advances by
+    E(beta) to first order in the amplitude."""
+    n, dx, re, dt = 40, 0.5, 50.0, 0.3
+    beta = dt / (dx * dx * re)
+    R = len(intfac.weights(beta)) - 1
+    a = np.zeros((3, n, n, n))
+    inner = R + 3
+    a[:, inner:-inner, inner:-inner, inner:-inner] = workloads.random_field((3,) + (n - 2 * inner,) * 3, 8)
+    u0 = stencils.curl_bar(a, dx) * 1e-9
+    u = torch.from_numpy(u0).to(DEV)
+    st = nslgf.HerkState(u, dx, dt, re, "A")
+    st.step()
+    expect = np.stack([intfac.apply(u0[q], beta) for q in range(3)])
+    assert rel(u.cpu().numpy(), expect) < 1e-7
+
+
+def test_step128_properties():
+    """The 128^3 step (Gaussian ring R = 1, sigma = 0.2, dx = 1/24, Re = 500, CFL 0.5, 1e-4
+    azimuthal perturbation): velocity divergence-free to rounding inside the support domain, the
+    ring keeps moving in +z, and the step is finite."""
+    n, dx, ring, re, cfl = workloads.ring_case("step128")
+    w = workloads.ring_edge_vorticity(n, dx, ring)
+    wt = torch.from_numpy(w).to(DEV)
+    u = nslgf.vor2vel(wt, dx)
+    dt = cfl * dx / nslgf.max_cell_speed(u)
+    st = nslgf.HerkState(u, dx, dt, re, "A", n_buf=16)
+    st.step()
+    un = u.cpu().numpy()
+    assert np.isfinite(un).all()
+    dv = nslgf.stencil("div", u, dx).cpu().numpy()
+    inner = (slice(17, -17),) * 3
+    assert np.abs(dv[inner]).max() < 1e-10 * np.abs(un).max() / dx
+    c = n // 2
+    assert un[2, c, c, c] > 0
