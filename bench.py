@@ -1,0 +1,281 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast-LGF Navier-Stokes hot path on one MI355X.
+
+Workload: the vortex ring of the 256^3 LGF-solve case (R = 1, sigma = 0.1 R, dx = R/48, Gamma = 1,
+Re = 500, CFL 0.5), FP64.  One timed step is one pass of the whole hot path:
+  Vor2Vel (the three-component LGF solve of the edge vorticity, then Cbar) followed by one
+  Scheme A IF-HERK step (three scalar LGF pressure solves, five vector integrating factors, three
+  nonlinear terms, divergence, gradient and bookkeeping).
+The LGF spectrum is built once before timing (preprocessing).  `value` is the LGF-solve throughput
+of the step: 6 scalar 256^3 solves per step, in points per second.
+
+Also reported (outside the timed steps): the three-component LGF solve alone in FP64 and FP32 with
+the FP32 error against FP64, per-kernel event times with algorithmic bytes, the roofline of the
+dominant kernel, and the oracle (plain C direct lattice sum) timed on a bounded sample of the same
+solve on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def alg_bytes_per_step(N: int, P: int, es: int) -> dict:
+    """Algorithmic HBM bytes per timed step for each kernel name (FP64 es = 8): every kernel counted
+    as reading its inputs once and writing its outputs once."""
+    n3 = N ** 3
+    nh = P // 2 + 1
+    ce = 2 * es
+    C = 6  # scalar LGF solves per step: 3 (Vor2Vel) + 3 (pressure)
+    return {
+        "conv_x_r2c": C * (n3 * es + N * N * nh * ce),
+        "conv_y_fwd": C * (N * N * nh * ce + N * P * nh * ce),
+        "conv_z_fused": C * (2 * N * P * nh * ce + nh ** 3 * es),
+        "conv_y_inv": C * (N * P * nh * ce + N * N * nh * ce),
+        "conv_x_c2r": C * (N * N * nh * ce + n3 * es),
+        "if_x": 15 * 2 * n3 * es,
+        "if_y": 15 * 2 * n3 * es,
+        "if_z": 15 * 2 * n3 * es,
+        "curl_bar": 6 * n3 * es,
+        "stage_rhs": 30 * n3 * es,
+        "stage_div": 12 * n3 * es,
+        "stage_project": 36 * n3 * es,
+        "axpby": 14 * n3 * es,
+    }
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1601_00035_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(w, dx, seconds: float):
+    """The oracle's direct lattice sum on a bounded sample of target points of the same solve."""
+    import numpy as np
+
+    import workloads
+    from oracle import lgf as olgf
+    from oracle import native
+
+    n = w.shape[-1]
+    t0 = time.perf_counter()
+    olgf.lgf_cube(n - 1)
+    table_s = time.perf_counter() - t0
+    native.load()
+    comps = [q for q in range(3) if w[q].any()]
+    # grow the sample until it takes about `seconds` (each call also scans the source box once)
+    count = 64
+    while True:
+        tg = workloads.sample_targets(n, count, seed=12)
+        t0 = time.perf_counter()
+        for q in comps:
+            native.lgf_direct_targets(w[q], dx, tg)
+        el = time.perf_counter() - t0
+        if el >= 0.5 * seconds or count >= 200000:
+            break
+        count = int(count * min(8.0, max(1.5, seconds / max(el, 1e-3))))
+    pts = len(tg) * len(comps)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": pts / el / 1e6,
+        "unit": "Mpts/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(tg)} seeded target points x {len(comps)} nonzero vorticity components of the 256^3 "
+                  f"LGF solve, direct O(N_src N_tgt) sum in FP64 ({el:.1f} s; table build {table_s:.1f} s not included)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is design-only)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1601_00035_amd as nslgf
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, dx, ring, re, cfl = workloads.ring_case("conv256")
+    t0 = time.perf_counter()
+    w_np = workloads.ring_edge_vorticity(n, dx, ring)
+    log(f"input: ring vorticity {n}^3 generated in {time.perf_counter() - t0:.1f} s")
+    w = torch.from_numpy(w_np).to(dev)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.perf_counter()
+    nslgf.lgf_table(n, n, n, torch.float64)
+    torch.cuda.synchronize()
+    table_s = time.perf_counter() - t0
+    log(f"LGF table + spectrum (FP64) built in {table_s:.2f} s")
+
+    u = nslgf.vor2vel(w, dx)
+    dt = cfl * dx / nslgf.max_cell_speed(u)
+    st = nslgf.HerkState(u, dx, dt, re, "A", n_buf=16)
+
+    def step():
+        nslgf.vor2vel(w, dx, out=u)
+        st.step()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done (dt = {dt:.4e})")
+
+    nslgf.profile_enable(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    prof = nslgf.profile_read()
+    nslgf.profile_enable(False)
+    ms = ev0.elapsed_time(ev1) / args.steps
+    assert torch.isfinite(u).all().item(), "non-finite velocity"
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall:.2f} s)")
+
+    N, P = n, 512
+    lgf_pts = 6 * N ** 3
+    value = lgf_pts / (ms * 1e-3) / 1e6
+
+    # per-kernel achieved bandwidth from the event timings and the algorithmic bytes
+    alg = alg_bytes_per_step(N, P, 8)
+    kern = {}
+    for name, (calls, tot) in prof.items():
+        per_step_ms = tot / args.steps
+        b = alg.get(name)
+        kern[name] = {"launches_per_step": calls / args.steps, "ms_per_step": round(per_step_ms, 4)}
+        if b is not None and tot > 0:
+            kern[name]["alg_GBps"] = round(b / (per_step_ms * 1e-3) / 1e9, 1)
+    dom = max((k for k in prof if k in alg), key=lambda k: prof[k][1])
+    calls, tot = prof[dom]
+    launches = calls / args.steps
+    avg_ms = tot / calls
+    bytes_per_launch = alg[dom] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    workload = "ns_lgf_step_256_ring_fp64"
+    traffic = load_traffic(dom, workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 5)}
+
+    secondary = {}
+    if not args.no_secondary:
+        # the three-component LGF solve alone, FP64 and FP32, with the FP32 error against FP64
+        def time_conv(src, reps=10):
+            out = nslgf.lgf_convolve(src, dx)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                nslgf.lgf_convolve(src, dx, out=out)
+            b.record(stream)
+            torch.cuda.synchronize()
+            return out, a.elapsed_time(b) / reps
+
+        y64, ms64 = time_conv(w)
+        w32 = w.float()
+        nslgf.lgf_table(n, n, n, torch.float32)
+        y32, ms32 = time_conv(w32)
+        d = (y32.double() - y64)
+        rel_l2 = (d.norm() / y64.norm()).item()
+        rel_linf = (d.abs().max() / y64.abs().max()).item()
+        secondary["lgf_solve_3comp"] = {
+            "fp64": {"ms": round(ms64, 4), "Mpts_per_s": round(3 * N ** 3 / (ms64 * 1e-3) / 1e6, 1)},
+            "fp32": {"ms": round(ms32, 4), "Mpts_per_s": round(3 * N ** 3 / (ms32 * 1e-3) / 1e6, 1),
+                     "rel_l2_vs_fp64": rel_l2, "rel_linf_vs_fp64": rel_linf},
+        }
+        del w32, y32, y64
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host cores ...")
+        cpu = cpu_baseline(w_np, dx, args.cpu_seconds)
+
+    line = {
+        "metric": "LGF solve Mpts/s & %HBM peak at 256^3; FP32/batched vs FP64 at stated rel err",
+        "value": round(value, 2),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "grid": [N, N, N],
+            "step": "Vor2Vel (3-component LGF solve + Cbar) + one Scheme A IF-HERK step",
+            "lgf_points_per_step": lgf_pts,
+            "ring": {"R": 1.0, "sigma_over_R": 0.1, "dx_over_R": 1 / 48, "Re": re, "cfl": cfl, "dt": dt},
+            "n_buf": 16,
+            "padded": [P, P, P],
+            "table_build_s": round(table_s, 3),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kern,
+        "secondary": secondary,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -170,6 +170,19 @@ int stencil_apply(nslgf_t h, int op, const void *src, void *dst, int ncomp, int 
  */
 int max_cell_speed(nslgf_t h, const void *u, int nx, int ny, int nz, int dtype, double *out, void *stream);
 
+/*
+ * Per-kernel timing.  While enabled, every kernel the handle launches is bracketed by two HIP events
+ * recorded on its launch stream; nslgf_profile_read reports, per kernel name, the number of launches
+ * and their summed event-to-event duration in milliseconds (it waits for the recorded events).
+ * enable = 1 starts (and clears) collection, 0 stops it.  index runs over the kernel names seen so
+ * far; NSLGF_EINVAL past the last one.  name receives at most name_cap bytes, NUL-terminated.
+ */
+int nslgf_profile_enable(nslgf_t h, int enable);
+/* Plain streaming copy of n elements of dtype (device pointers, no overlap); the reference kernel
+ * whose hardware byte counters calibrate those of the other kernels.  Profiled as "copy". */
+int nslgf_copy(nslgf_t h, const void *src, void *dst, size_t n, int dtype, void *stream);
+int nslgf_profile_read(nslgf_t h, int index, char *name, int name_cap, long long *calls, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,10 @@ def lib():
                     "vor2vel": [vp, vp, vp, i, i, i, d, i, vp],
                     "stencil_apply": [vp, i, vp, vp, i, i, i, i, d, i, vp],
                     "max_cell_speed": [vp, vp, i, i, i, i, ctypes.POINTER(d), vp],
+                    "nslgf_profile_enable": [vp, i],
+                    "nslgf_profile_read": [vp, i, ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_longlong),
+                                           ctypes.POINTER(d)],
+                    "nslgf_copy": [vp, vp, vp, ctypes.c_size_t, i, vp],
                 }
                 for name, args in sig.items():
                     f = getattr(L, name)
@@ -211,6 +215,35 @@ def max_cell_speed(u: torch.Tensor) -> float:
     _check("max_cell_speed", lib().max_cell_speed(handle(u.device.index), u.data_ptr(), nx, ny, nz, _dtype(u),
                                                   ctypes.byref(out), _stream(u)))
     return out.value
+
+
+def profile_enable(on: bool = True, device: int | None = None):
+    """Start (and clear) or stop per-kernel event timing inside the library."""
+    _check("nslgf_profile_enable", lib().nslgf_profile_enable(handle(device), 1 if on else 0))
+
+
+def profile_read(device: int | None = None) -> dict:
+    """{kernel name: (launches, total ms)} collected since profile_enable(True)."""
+    out = {}
+    h = handle(device)
+    i = 0
+    buf = ctypes.create_string_buffer(64)
+    calls = ctypes.c_longlong()
+    ms = ctypes.c_double()
+    while lib().nslgf_profile_read(h, i, buf, 64, ctypes.byref(calls), ctypes.byref(ms)) == 0:
+        out[buf.value.decode()] = (calls.value, ms.value)
+        i += 1
+    return out
+
+
+def copy(src: torch.Tensor, dst: torch.Tensor):
+    """Plain device copy through the library's streaming kernel (byte-counter calibration)."""
+    _dev(src, "src")
+    _dev(dst, "dst")
+    if src.numel() != dst.numel() or src.dtype != dst.dtype:
+        raise ValueError("copy: size/dtype mismatch")
+    _check("nslgf_copy", lib().nslgf_copy(handle(src.device.index), src.data_ptr(), dst.data_ptr(), src.numel(),
+                                          _dtype(src), _stream(src)))
 
 
 class HerkState:

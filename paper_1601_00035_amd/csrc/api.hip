@@ -49,8 +49,58 @@ struct ConvPlan {
 
 }  // namespace nslgf
 
+namespace nslgf {
+// Event pairs around kernel launches, resolved lazily.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<long long, double>> totals;
+    std::vector<std::string> order;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void resolve() {
+        for (auto& r : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto it = totals.find(r.name);
+                if (it == totals.end()) {
+                    order.push_back(r.name);
+                    it = totals.emplace(r.name, std::make_pair(0LL, 0.0)).first;
+                }
+                it->second.first += 1;
+                it->second.second += ms;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    ~Profiler() {
+        for (auto& r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+}  // namespace nslgf
+
 struct nslgf_ctx {
     int device = 0;
+    nslgf::Profiler prof;
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
@@ -72,6 +122,36 @@ static int get_twiddles(nslgf_ctx* h, int L, int dtype, const void** out) {
     *out = it->second->p;
     return NSLGF_OK;
 }
+
+// Brackets one launch with profiling events when collection is on.
+struct ProfScope {
+    nslgf_ctx* h;
+    const char* name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(nslgf_ctx* h_, const char* n, hipStream_t s_) : h(h_), name(n), s(s_) {
+        if (h && h->prof.on) {
+            a = h->prof.get();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = h->prof.get();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                h->prof.pending.push_back({name, a, b});
+            } else {
+                h->prof.pool.push_back(a);
+            }
+        }
+    }
+};
+#define NSLGF_PROF(h, name, s, expr)                                                               \
+    do {                                                                                           \
+        ProfScope ps_(h, name, s);                                                                 \
+        NSLGF_TRY(expr);                                                                           \
+    } while (0)
 
 static int check_box(int nx, int ny, int nz) {
     NSLGF_CHECK_ARG(nx >= 1 && ny >= 1 && nz >= 1 && nx <= 256 && ny <= 256 && nz <= 256,
@@ -187,7 +267,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     r.n_io = p.nx;
     r.tw_half = twh;
     r.tw_full = twf;
-    NSLGF_TRY(launch_row_r2c(p.Px, dt, r, s));
+    NSLGF_PROF(h, "conv_x_r2c", s, launch_row_r2c(p.Px, dt, r, s));
     ColPass c{};
     c.in = p.A1.p;
     c.out = p.A2.p;
@@ -202,7 +282,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     c.n_in = p.ny;
     c.n_out = p.Py;
     c.tw = twy;
-    NSLGF_TRY(launch_col(p.Py, dt, COL_FWD, c, s));
+    NSLGF_PROF(h, "conv_y_fwd", s, launch_col(p.Py, dt, COL_FWD, c, s));
     ColPass z{};
     z.in = p.A2.p;
     z.out = p.A2.p;
@@ -218,7 +298,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     z.khat_tiles = p.tiles;
     z.outer_period = p.Py;
     z.scale = scale;
-    NSLGF_TRY(launch_col(p.Pz, dt, COL_CONV, z, s));
+    NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s));
     ColPass y{};
     y.in = p.A2.p;
     y.out = p.A1.p;
@@ -233,7 +313,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     y.n_in = p.Py;
     y.n_out = p.ny;
     y.tw = twy;
-    NSLGF_TRY(launch_col(p.Py, dt, COL_INV, y, s));
+    NSLGF_PROF(h, "conv_y_inv", s, launch_col(p.Py, dt, COL_INV, y, s));
     RowPass o{};
     o.in = p.A1.p;
     o.out = dst;
@@ -246,7 +326,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     o.n_io = p.nx;
     o.tw_half = twh;
     o.tw_full = twf;
-    NSLGF_TRY(launch_row_c2r(p.Px, dt, o, s));
+    NSLGF_PROF(h, "conv_x_c2r", s, launch_row_c2r(p.Px, dt, o, s));
     return NSLGF_OK;
 }
 
@@ -264,9 +344,9 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
     if (r < 0) return NSLGF_EINVAL;
     NSLGF_TRY(h->if_tmp1.ensure(bytes));
     NSLGF_TRY(h->if_tmp2.ensure(bytes));
-    NSLGF_TRY(launch_if_axis(0, dtype, src, h->if_tmp1.p, ncomp, nx, ny, nz, w, r, s));
-    NSLGF_TRY(launch_if_axis(1, dtype, h->if_tmp1.p, h->if_tmp2.p, ncomp, nx, ny, nz, w, r, s));
-    NSLGF_TRY(launch_if_axis(2, dtype, h->if_tmp2.p, dst, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_PROF(h, "if_x", s, launch_if_axis(0, dtype, src, h->if_tmp1.p, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, h->if_tmp1.p, h->if_tmp2.p, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, h->if_tmp2.p, dst, ncomp, nx, ny, nz, w, r, s));
     return NSLGF_OK;
 }
 
@@ -430,35 +510,35 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     if (stage == 1) {
         c.c_q = 1.0;
         c.copy_q = 1;
-        NSLGF_TRY(launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     } else if (stage == 2) {
         const double a_prev = (ct[1] - ct[0]) * beta;
         NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s));  // q and w1 are adjacent
         c.c_q = 1.0;
         c.c_w1 = dt * at[2][1];
-        NSLGF_TRY(launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s));
     } else {
         // final-stage form: r^3 = H^2 (q^2 + dt (a~31 w^{2,1} + a~32 w^{2,2})) + g^3
         const double a_prev = (ct[2] - ct[1]) * beta;
-        NSLGF_TRY(launch_axpby(dt_, r, q, 1.0, w1, dt * at[3][1], w2, dt * at[3][2], 3 * M, s));
+        NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, r, q, 1.0, w1, dt * at[3][1], w2, dt * at[3][2], 3 * M, s));
         NSLGF_TRY(run_if(h, r, r, 3, nx, ny, nz, a_prev, dt_, s));
         c.c_q = 1.0;
-        NSLGF_TRY(launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     }
-    NSLGF_TRY(launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
+    NSLGF_PROF(h, "stage_div", s, launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
     NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s));
     if (stage == 1) {
-        NSLGF_TRY(launch_stage_project(dt_, r, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz, st->dx, s));
     } else if (stage == 2) {
-        NSLGF_TRY(launch_stage_project(dt_, r, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny, nz,
+        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny, nz,
                                        st->dx, s));
     } else {
-        NSLGF_TRY(launch_stage_project(dt_, r, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx, ny, nz,
+        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx, ny, nz,
                                        st->dx, s));
     }
     NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s));
     if (stage == 3) {
-        NSLGF_TRY(launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
+        NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
         st->t += dt;
     }
     st->stage_done = stage;
@@ -482,7 +562,8 @@ int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx
     const long long M = (long long)nx * ny * nz;
     NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
     NSLGF_TRY(run_conv(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
-    return launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s);
+    NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s));
+    return NSLGF_OK;
 }
 
 int stencil_apply(nslgf_t h, int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
@@ -511,6 +592,41 @@ int max_cell_speed(nslgf_t h, const void* u, int nx, int ny, int nz, int dtype, 
     double m = 0.0;
     for (double v : host) m = v > m ? v : m;
     *out = m;
+    return NSLGF_OK;
+}
+
+int nslgf_profile_enable(nslgf_t h, int enable) {
+    NSLGF_ENTER(h);
+    h->prof.resolve();
+    if (enable) {
+        h->prof.totals.clear();
+        h->prof.order.clear();
+    }
+    h->prof.on = enable != 0;
+    return NSLGF_OK;
+}
+
+int nslgf_copy(nslgf_t h, const void* src, void* dst, size_t n, int dtype, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(src && dst && src != dst, "nslgf_copy: null or aliased pointers");
+    hipStream_t s = (hipStream_t)stream;
+    NSLGF_PROF(h, "copy", s, launch_axpby(dtype, dst, src, 1.0, nullptr, 0.0, nullptr, 0.0, (long long)n, s));
+    return NSLGF_OK;
+}
+
+int nslgf_profile_read(nslgf_t h, int index, char* name, int name_cap, long long* calls, double* total_ms) {
+    NSLGF_ENTER(h);
+    h->prof.resolve();
+    NSLGF_CHECK_ARG(index >= 0 && index < (int)h->prof.order.size(), "nslgf_profile_read: index out of range");
+    const std::string& n = h->prof.order[index];
+    const auto& v = h->prof.totals[n];
+    if (name && name_cap > 0) {
+        std::strncpy(name, n.c_str(), (size_t)name_cap - 1);
+        name[name_cap - 1] = 0;
+    }
+    if (calls) *calls = v.first;
+    if (total_ms) *total_ms = v.second;
     return NSLGF_OK;
 }
 
