@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first copy 1 GiB with the library's plain copy kernel (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is design-only)",
@@ -145,6 +147,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate:
+        a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        nslgf.copy(a, b)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read + 1 GiB written")
     n, dx, ring, re, cfl = workloads.ring_case("conv256")
     t0 = time.perf_counter()
     w_np = workloads.ring_edge_vorticity(n, dx, ring)

@@ -178,8 +178,9 @@ int max_cell_speed(nslgf_t h, const void *u, int nx, int ny, int nz, int dtype, 
  * far; NSLGF_EINVAL past the last one.  name receives at most name_cap bytes, NUL-terminated.
  */
 int nslgf_profile_enable(nslgf_t h, int enable);
-/* Plain streaming copy of n elements of dtype (device pointers, no overlap); the reference kernel
- * whose hardware byte counters calibrate those of the other kernels.  Profiled as "copy". */
+/* Plain streaming copy of n elements of dtype (device pointers, no overlap, n * size a multiple of
+ * 16 bytes, 16-byte aligned); the reference kernel whose hardware byte counters calibrate those of
+ * the other kernels.  Profiled as "copy". */
 int nslgf_copy(nslgf_t h, const void *src, void *dst, size_t n, int dtype, void *stream);
 int nslgf_profile_read(nslgf_t h, int index, char *name, int name_cap, long long *calls, double *total_ms);
 

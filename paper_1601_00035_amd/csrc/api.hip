@@ -611,7 +611,7 @@ int nslgf_copy(nslgf_t h, const void* src, void* dst, size_t n, int dtype, void*
     NSLGF_TRY(check_dtype(dtype));
     NSLGF_CHECK_ARG(src && dst && src != dst, "nslgf_copy: null or aliased pointers");
     hipStream_t s = (hipStream_t)stream;
-    NSLGF_PROF(h, "copy", s, launch_axpby(dtype, dst, src, 1.0, nullptr, 0.0, nullptr, 0.0, (long long)n, s));
+    NSLGF_PROF(h, "copy", s, launch_copy(src, dst, n * dtype_size(dtype), s));
     return NSLGF_OK;
 }
 

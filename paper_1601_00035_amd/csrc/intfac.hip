@@ -1,7 +1,9 @@
 // Integrating factor E(alpha) (Sec. 2.3): the kernel of the discrete heat semigroup is the product
 // of three 1D factors w[k] = e^{-2 alpha} I_k(2 alpha) (Appendix B, Eq. lgf_intfac), so
 // M E(alpha) M is applied as three masked 1D convolutions, one per axis, each reading its input
-// with zero extension outside the box.
+// with zero extension outside the box.  Each pass stages whole lines in LDS so that every element
+// is read from and written to HBM once, with coalesced accesses (rows for x, tiles of adjacent
+// x-columns for y and z).
 #include <cmath>
 
 #include "kernels.h"
@@ -55,33 +57,144 @@ struct IfWeights {
     double w[kIfMaxRadius + 1];
 };
 
-// One masked 1D convolution along `axis` (0 = x, 1 = y, 2 = z); one thread per output element.
-template <typename T, int AXIS>
-__global__ void __launch_bounds__(256) k_if_axis(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz,
-                                                 IfWeights wts, int radius) {
-    const long long n = (long long)nx * ny * nz;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n) return;
+// x pass: whole rows staged in LDS (RPW rows of length nx per workgroup), each output summing its
+// 2r+1 row neighbours from LDS; global reads and writes are contiguous.
+constexpr int kIfRowElems = 2048;  // LDS elements per workgroup for the row pass
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_if_rows(const T* __restrict__ in, T* __restrict__ out, int nx,
+                                                 long long nrows, IfWeights wts, int radius) {
+    __shared__ T lds[kIfRowElems];
+    const int rpw = kIfRowElems / nx;
+    const long long row0 = (long long)blockIdx.x * rpw;
     const int comp = blockIdx.y;
-    in += comp * n;
-    out += comp * n;
-    const int i = (int)(idx % nx);
-    const int j = (int)((idx / nx) % ny);
-    const int k = (int)(idx / ((long long)nx * ny));
-    const int pos = AXIS == 0 ? i : (AXIS == 1 ? j : k);
-    const int len = AXIS == 0 ? nx : (AXIS == 1 ? ny : nz);
-    const long long stride = AXIS == 0 ? 1 : (AXIS == 1 ? (long long)nx : (long long)nx * ny);
-    const int lo = max(-radius, -pos), hi = min(radius, len - 1 - pos);
-    // sum from the outer offsets inwards (smallest weights first)
-    double acc = 0.0;
-    for (int d = max(-lo, hi); d >= 1; --d) {
-        T s = 0;
-        if (-d >= lo) s += in[idx - d * stride];
-        if (d <= hi) s += in[idx + d * stride];
-        acc += wts.w[d] * (double)s;
+    const long long nrow_here = min((long long)rpw, nrows - row0);
+    const long long base = comp * nrows * nx + row0 * nx;
+    const int cnt = (int)(nrow_here * nx);
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) lds[e] = in[base + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        const int i = e % nx;
+        const int lo = max(-radius, -i), hi = min(radius, nx - 1 - i);
+        double acc = 0.0;
+        for (int d = max(-lo, hi); d >= 1; --d) {
+            T s = 0;
+            if (-d >= lo) s += lds[e - d];
+            if (d <= hi) s += lds[e + d];
+            acc += wts.w[d] * (double)s;
+        }
+        acc += wts.w[0] * (double)lds[e];
+        out[base + e] = (T)acc;
     }
-    acc += wts.w[0] * (double)in[idx];
-    out[idx] = (T)acc;
+}
+
+// y or z pass: a tile of TB adjacent x-columns times the full length along the axis is staged in
+// LDS; each output sums its 2r+1 neighbours along the axis.  `stride` is the element distance
+// between consecutive points along the axis, `outer_stride` between the tile groups of grid y.
+template <typename T, int TB>
+__global__ void __launch_bounds__(256) k_if_cols(const T* __restrict__ in, T* __restrict__ out, int nx, int len,
+                                                 long long stride, long long outer_stride, long long comp_stride,
+                                                 IfWeights wts, int radius) {
+    extern __shared__ unsigned char smem[];
+    T* lds = (T*)smem;  // [len][TB]
+    const int c = threadIdx.x % TB;
+    const int t = threadIdx.x / TB;
+    constexpr int TPC = 256 / TB;  // threads per column
+    const int col = blockIdx.x * TB + c;
+    const bool valid = col < nx;
+    const long long base = blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride + (valid ? col : 0);
+    for (int k = t; k < len; k += TPC) lds[k * TB + c] = valid ? in[base + k * stride] : (T)0;
+    __syncthreads();
+    if (!valid) return;
+    for (int k = t; k < len; k += TPC) {
+        const int lo = max(-radius, -k), hi = min(radius, len - 1 - k);
+        double acc = 0.0;
+        for (int d = max(-lo, hi); d >= 1; --d) {
+            T s = 0;
+            if (-d >= lo) s += lds[(k - d) * TB + c];
+            if (d <= hi) s += lds[(k + d) * TB + c];
+            acc += wts.w[d] * (double)s;
+        }
+        acc += wts.w[0] * (double)lds[k * TB + c];
+        out[base + k * stride] = (T)acc;
+    }
+}
+
+// Fixed-radius variant for every axis: a workgroup owns TB lines (adjacent x-columns for the y and
+// z passes, rows for the x pass), staged in LDS as [position][line] with R zeros at both ends, so
+// that consecutive lanes touch consecutive lines (no bank conflicts) while each line's global
+// accesses stay contiguous across its threads.  Each thread then loads a window of S + 2R values of
+// its line into registers and produces S consecutive outputs with no bounds tests.
+// Line l of grid column group starts at comp * comp_stride + outer * outer_stride + l * line_stride
+// and its points are `stride` apart.
+template <typename T, int TB, int R, int S>
+__global__ void __launch_bounds__(256) k_if_lines(const T* __restrict__ in, T* __restrict__ out, int nlines, int len,
+                                                  long long stride, long long line_stride, long long outer_stride,
+                                                  long long comp_stride, IfWeights wts) {
+    extern __shared__ unsigned char smem[];
+    T* lds = (T*)smem;  // [TPC * S + 2R][TB]
+    constexpr int TPC = 256 / TB;
+    constexpr int ROWS = TPC * S + 2 * R;
+    const int c = threadIdx.x % TB;
+    const int t = threadIdx.x / TB;
+    const int line = blockIdx.x * TB + c;
+    const bool valid = line < nlines;
+    const long long base =
+        blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride + (valid ? (long long)line * line_stride : 0);
+    for (int k = t; k < ROWS; k += TPC) {
+        const int kk = k - R;
+        lds[k * TB + c] = (valid && kk >= 0 && kk < len) ? in[base + kk * stride] : (T)0;
+    }
+    __syncthreads();
+    if (!valid || t * S >= len) return;
+    T v[S + 2 * R];
+#pragma unroll
+    for (int j = 0; j < S + 2 * R; ++j) v[j] = lds[(t * S + j) * TB + c];
+#pragma unroll
+    for (int m = 0; m < S; ++m) {
+        double acc = wts.w[0] * (double)v[m + R];
+#pragma unroll
+        for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
+        const int k = t * S + m;
+        if (k < len) out[base + k * stride] = (T)acc;
+    }
+}
+
+template <typename T, int R>
+static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
+                         hipStream_t s) {
+    const long long n = (long long)nx * ny * nz;
+    constexpr int TB = (int)(128 / sizeof(T));
+    constexpr int TPC = 256 / TB;
+    constexpr int S = 256 / TPC;  // the longest line (256 points) split over the threads of a line
+    const size_t lds = (size_t)(TPC * S + 2 * R) * TB * sizeof(T);
+    int nlines, len, nouter;
+    long long stride, line_stride, outer_stride;
+    if (axis == 0) {  // rows: lines are (y, z) rows of nx points
+        nlines = ny * nz;
+        len = nx;
+        stride = 1;
+        line_stride = nx;
+        nouter = 1;
+        outer_stride = 0;
+    } else if (axis == 1) {  // lines along y: x-columns of each z-plane
+        nlines = nx;
+        len = ny;
+        stride = nx;
+        line_stride = 1;
+        nouter = nz;
+        outer_stride = (long long)nx * ny;
+    } else {  // lines along z: x-columns of each y-row
+        nlines = nx;
+        len = nz;
+        stride = (long long)nx * ny;
+        line_stride = 1;
+        nouter = ny;
+        outer_stride = nx;
+    }
+    dim3 grid(ceil_div(nlines, TB), nouter, ncomp);
+    hipLaunchKernelGGL((k_if_lines<T, TB, R, S>), grid, dim3(256), lds, s, in, out, nlines, len, stride, line_stride,
+                       outer_stride, n, wts);
 }
 
 template <typename T>
@@ -90,13 +203,36 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
     IfWeights wts;
     for (int k = 0; k <= kIfMaxRadius; ++k) wts.w[k] = k <= radius ? w[k] : 0.0;
     const long long n = (long long)nx * ny * nz;
-    dim3 grid(ceil_div(n, 256), ncomp);
-    if (axis == 0)
-        hipLaunchKernelGGL((k_if_axis<T, 0>), grid, dim3(256), 0, s, (const T*)in, (T*)out, nx, ny, nz, wts, radius);
-    else if (axis == 1)
-        hipLaunchKernelGGL((k_if_axis<T, 1>), grid, dim3(256), 0, s, (const T*)in, (T*)out, nx, ny, nz, wts, radius);
-    else
-        hipLaunchKernelGGL((k_if_axis<T, 2>), grid, dim3(256), 0, s, (const T*)in, (T*)out, nx, ny, nz, wts, radius);
+    const T* src = (const T*)in;
+    T* dst = (T*)out;
+    switch (radius) {
+#define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(axis, src, dst, ncomp, nx, ny, nz, wts, s); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
+        NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
+        NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
+#undef NSLGF_IF_R
+        default: break;
+    }
+    // larger radii: runtime-radius passes
+    if (axis == 0) {
+        if (nx > kIfRowElems) {
+            set_error("if_apply: rows longer than the LDS row buffer");
+            return NSLGF_EUNSUPPORTED;
+        }
+        const long long nrows = (long long)ny * nz;
+        const int rpw = kIfRowElems / nx;
+        dim3 grid(ceil_div(nrows, rpw), ncomp);
+        hipLaunchKernelGGL((k_if_rows<T>), grid, dim3(256), 0, s, src, dst, nx, nrows, wts, radius);
+    } else {
+        constexpr int TB = (int)(128 / sizeof(T));
+        const int len = axis == 1 ? ny : nz;
+        const long long stride = axis == 1 ? (long long)nx : (long long)nx * ny;
+        const int nouter = axis == 1 ? nz : ny;
+        const long long outer_stride = axis == 1 ? (long long)nx * ny : (long long)nx;
+        const size_t lds = (size_t)len * TB * sizeof(T);
+        dim3 grid(ceil_div(nx, TB), nouter, ncomp);
+        hipLaunchKernelGGL((k_if_cols<T, TB>), grid, dim3(256), lds, s, src, dst, nx, len, stride, outer_stride, n,
+                           wts, radius);
+    }
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

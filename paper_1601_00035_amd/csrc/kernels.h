@@ -96,6 +96,8 @@ int launch_stage_project(int dtype, void* r, const void* dhat, const void* q, co
 // out = a*x + b*y + c*z (elementwise over n elements; y, z may be null)
 int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
                  long long n, hipStream_t s);
+// plain 16-byte-vector copy of `bytes` (multiple of 16)
+int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);

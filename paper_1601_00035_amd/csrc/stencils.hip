@@ -182,6 +182,23 @@ __global__ void __launch_bounds__(256) k_axpby(T* out, const T* x, double a, con
     out[idx] = (T)v;
 }
 
+// Plain streaming copy (16-byte vectors), the reference for hardware byte counters.
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ in, uint4* __restrict__ out, long long n16) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x)
+        out[i] = in[i];
+}
+
+int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
+    if (bytes % 16 != 0 || ((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0) {
+        set_error("copy: size and pointers must be multiples of 16 bytes");
+        return NSLGF_EINVAL;
+    }
+    const long long n16 = (long long)(bytes / 16);
+    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, (const uint4*)in, (uint4*)out, n16);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_max_speed(const T* u, int nx, int ny, int nz, double* partial) {
     const long long n = (long long)nx * ny * nz;
