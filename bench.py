@@ -123,6 +123,54 @@ def cpu_baseline(w, dx, seconds: float):
     }
 
 
+def batched_measure(nslgf, torch, dtype, reps=3):
+    """32 uneven Scheme A steps (n ~ U{48..192}, seeded rings): one captured graph per batch against
+    the same steps issued one state after another on one stream."""
+    import workloads
+
+    dev = torch.device("cuda:0")
+    specs = workloads.batch_specs(32, seed=0)
+    solo, batch = [], []
+    cells = 0
+    for (n, dx, ring, re, cfl) in specs:
+        w = torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring, quad=2)).to(dev)
+        u = nslgf.vor2vel(w, dx)
+        dt = cfl * dx / nslgf.max_cell_speed(u)
+        u = u.to(dtype)
+        a = nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=8)
+        b = nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=8)
+        b.work = a.work  # the two sets never run at the same time
+        b.c.work = a.work.data_ptr()
+        solo.append(a)
+        batch.append(b)
+        cells += n ** 3
+        del w
+    stream = torch.cuda.current_stream()
+    # correctness: one step each way from identical states
+    for st in solo:
+        st.step()
+    nslgf.herk_step_batched(batch)
+    torch.cuda.synchronize()
+    equal = all(torch.equal(a.u, b.u) and torch.equal(a.d, b.d) for a, b in zip(solo, batch))
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_solo = timed(lambda: [st.step() for st in solo])
+    ms_batch = timed(lambda: nslgf.herk_step_batched(batch))
+    sizes = sorted(set(sp[0] for sp in specs))
+    return {"problems": len(specs), "sizes": sizes, "cells": cells, "ms_one_by_one": round(ms_solo, 3),
+            "ms_batched_graph": round(ms_batch, 3), "speedup": round(ms_solo / ms_batch, 3),
+            "Mcells_per_s": round(cells / (ms_batch * 1e-3) / 1e6, 1), "bitwise_equal_to_one_by_one": equal}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +296,10 @@ def main():
                      "rel_l2_vs_fp64": rel_l2, "rel_linf_vs_fp64": rel_linf},
         }
         del w32, y32, y64
+        torch.cuda.empty_cache()
+        log("batched form: 32 uneven steps, FP64 and FP32 ...")
+        secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
+                                "fp32": batched_measure(nslgf, torch, torch.float32)}
         torch.cuda.empty_cache()
 
     cpu = None

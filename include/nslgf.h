@@ -140,6 +140,15 @@ int herk_stage(nslgf_t h, nslgf_state *st, int stage, void *stream);
 int herk_step(nslgf_t h, nslgf_state *st, void *stream);
 
 /*
+ * One IF-HERK step of each of n independent states (boxes of any supported sizes and dtypes, each
+ * with its own u, d and work; none may share them), as one launch: the first call captures the n
+ * steps into a HIP graph with one branch per state (up to 16 concurrent branches) and later calls
+ * with the same states and step parameters replay it.  Results equal n herk_step calls bit for bit.
+ * Advances every st->t by its dt.  Builds missing LGF spectra first (synchronising the stream).
+ */
+int herk_step_batched(nslgf_t h, nslgf_state *const *sts, int n, void *stream);
+
+/*
  * Vor2Vel (Sec. 4.1, Eqs. vel_vor and vel_refresh): a = -L^{-1} w per component, u = Cbar a.
  * w: edge vorticity [3][nz][ny][nx]; u: face velocity [3][nz][ny][nx] (must not overlap w).
  */

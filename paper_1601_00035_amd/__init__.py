@@ -61,6 +61,7 @@ def lib():
                     "if_apply": [vp, vp, vp, i, i, i, i, d, i, vp],
                     "herk_stage": [vp, ctypes.POINTER(_State), i, vp],
                     "herk_step": [vp, ctypes.POINTER(_State), vp],
+                    "herk_step_batched": [vp, ctypes.POINTER(ctypes.POINTER(_State)), i, vp],
                     "vor2vel": [vp, vp, vp, i, i, i, d, i, vp],
                     "stencil_apply": [vp, i, vp, vp, i, i, i, i, d, i, vp],
                     "max_cell_speed": [vp, vp, i, i, i, i, ctypes.POINTER(d), vp],
@@ -275,3 +276,13 @@ class HerkState:
 
     def step(self):
         _check("herk_step", lib().herk_step(handle(self.u.device.index), ctypes.byref(self.c), _stream(self.u)))
+
+
+def herk_step_batched(states: list) -> None:
+    """One step of every state, captured once into a HIP graph and replayed while the batch is
+    unchanged (same boxes, pointers and step parameters)."""
+    if not states:
+        return
+    dev = states[0].u.device
+    arr = (ctypes.POINTER(_State) * len(states))(*[ctypes.pointer(st.c) for st in states])
+    _check("herk_step_batched", lib().herk_step_batched(handle(dev.index), arr, len(states), _stream(states[0].u)))

@@ -1,7 +1,9 @@
 // C-ABI of the library: handle lifecycle, per-box convolution plans (LGF spectrum, twiddles,
 // workspaces), the integrating factor, the IF-HERK stage driver and Vor2Vel.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -98,9 +100,29 @@ struct Profiler {
 };
 }  // namespace nslgf
 
+namespace nslgf {
+// One captured batch step, reused while the batch (boxes, pointers, step parameters) is unchanged.
+struct BatchGraph {
+    std::vector<unsigned long long> key;
+    hipGraphExec_t exec = nullptr;
+    ~BatchGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+}  // namespace nslgf
+
 struct nslgf_ctx {
     int device = 0;
     nslgf::Profiler prof;
+    std::unique_ptr<nslgf::BatchGraph> batch;
+    std::vector<hipStream_t> branches;
+    std::vector<hipEvent_t> batch_events;
+    hipStream_t capture = nullptr;
+    ~nslgf_ctx() {
+        for (auto s : branches) (void)hipStreamDestroy(s);
+        for (auto e : batch_events) (void)hipEventDestroy(e);
+        if (capture) (void)hipStreamDestroy(capture);
+    }
     std::map<std::tuple<int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
@@ -170,7 +192,11 @@ static int padded(int n) {
 }
 
 // Five-pass convolution of ncomp scalar fields with a plan's spectrum times `scale`.
-static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s);
+static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s,
+                    void* A1, void* A2);
+// Twiddle tables of a plan's lengths for a dtype (built on first use; call before any capture).
+static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** twh, const void** twf, const void** twy,
+                         const void** twz);
 
 static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, ConvPlan** out) {
     auto key = std::make_tuple(nx, ny, nz, dtype);
@@ -243,21 +269,29 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
     return NSLGF_OK;
 }
 
-static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s) {
+static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** twh, const void** twf, const void** twy,
+                         const void** twz) {
+    NSLGF_TRY(get_twiddles(h, p.Px / 2, dt, twh));
+    NSLGF_TRY(get_twiddles(h, p.Px, dt, twf));
+    NSLGF_TRY(get_twiddles(h, p.Py, dt, twy));
+    NSLGF_TRY(get_twiddles(h, p.Pz, dt, twz));
+    return NSLGF_OK;
+}
+
+// Workspaces of one convolution of up to 3 components: A1 [nz][ny][XP] and A2 [nz][Py][XP] complex.
+static size_t conv_ws_elems_a1(const ConvPlan& p) { return (size_t)p.nz * p.ny * p.XP * 2; }
+static size_t conv_ws_elems_a2(const ConvPlan& p) { return (size_t)p.nz * p.Py * p.XP * 2; }
+
+static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s,
+                    void* A1, void* A2) {
     const int dt = p.dtype;
-    const size_t cs = 2 * dtype_size(dt);
     const long long a1c = (long long)p.nz * p.ny * p.XP, a2c = (long long)p.nz * p.Py * p.XP;
-    NSLGF_TRY(p.A1.ensure((size_t)3 * a1c * cs));
-    NSLGF_TRY(p.A2.ensure((size_t)3 * a2c * cs));
     const void *twh, *twf, *twy, *twz;
-    NSLGF_TRY(get_twiddles(h, p.Px / 2, dt, &twh));
-    NSLGF_TRY(get_twiddles(h, p.Px, dt, &twf));
-    NSLGF_TRY(get_twiddles(h, p.Py, dt, &twy));
-    NSLGF_TRY(get_twiddles(h, p.Pz, dt, &twz));
+    NSLGF_TRY(plan_twiddles(h, p, dt, &twh, &twf, &twy, &twz));
     const long long box = (long long)p.nx * p.ny * p.nz;
     RowPass r{};
     r.in = src;
-    r.out = p.A1.p;
+    r.out = A1;
     r.nrows = (long long)p.nz * p.ny;
     r.in_row = p.nx;
     r.out_row = p.XP;
@@ -269,8 +303,8 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     r.tw_full = twf;
     NSLGF_PROF(h, "conv_x_r2c", s, launch_row_r2c(p.Px, dt, r, s));
     ColPass c{};
-    c.in = p.A1.p;
-    c.out = p.A2.p;
+    c.in = A1;
+    c.out = A2;
     c.ncols = p.Px / 2 + 1;
     c.nouter = p.nz;
     c.in_outer = (long long)p.ny * p.XP;
@@ -284,8 +318,8 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     c.tw = twy;
     NSLGF_PROF(h, "conv_y_fwd", s, launch_col(p.Py, dt, COL_FWD, c, s));
     ColPass z{};
-    z.in = p.A2.p;
-    z.out = p.A2.p;
+    z.in = A2;
+    z.out = A2;
     z.ncols = p.Px / 2 + 1;
     z.nouter = p.Py;
     z.in_outer = z.out_outer = p.XP;
@@ -300,8 +334,8 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     z.scale = scale;
     NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s));
     ColPass y{};
-    y.in = p.A2.p;
-    y.out = p.A1.p;
+    y.in = A2;
+    y.out = A1;
     y.ncols = p.Px / 2 + 1;
     y.nouter = p.nz;
     y.in_outer = (long long)p.Py * p.XP;
@@ -315,7 +349,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     y.tw = twy;
     NSLGF_PROF(h, "conv_y_inv", s, launch_col(p.Py, dt, COL_INV, y, s));
     RowPass o{};
-    o.in = p.A1.p;
+    o.in = A1;
     o.out = dst;
     o.nrows = (long long)p.nz * p.ny;
     o.in_row = p.XP;
@@ -330,24 +364,64 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     return NSLGF_OK;
 }
 
+// Convolution on the plan's own workspaces (handle-level calls; not for concurrent streams).
+static int run_conv_shared(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale,
+                           hipStream_t s) {
+    const size_t es = dtype_size(p.dtype);
+    NSLGF_TRY(p.A1.ensure(3 * conv_ws_elems_a1(p) * es));
+    NSLGF_TRY(p.A2.ensure(3 * conv_ws_elems_a2(p) * es));
+    return run_conv(h, p, src, dst, ncomp, scale, s, p.A1.p, p.A2.p);
+}
+
 // IF application through two temporaries (x: src -> t1, y: t1 -> t2, z: t2 -> dst); src == dst allowed.
 static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
-                  hipStream_t s) {
+                  hipStream_t s, void* t1, void* t2) {
     const long long n = (long long)nx * ny * nz;
-    const size_t bytes = (size_t)ncomp * n * dtype_size(dtype);
     if (alpha == 0.0) {
-        if (src != dst) NSLGF_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        // identity: an elementwise kernel copy (no memory-copy nodes when the caller captures a graph)
+        if (src != dst)
+            NSLGF_PROF(h, "copy", s, launch_axpby(dtype, dst, src, 1.0, nullptr, 0.0, nullptr, 0.0, ncomp * n, s));
         return NSLGF_OK;
     }
     double w[kIfMaxRadius + 1];
     const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
     if (r < 0) return NSLGF_EINVAL;
+    NSLGF_PROF(h, "if_x", s, launch_if_axis(0, dtype, src, t1, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, t1, t2, ncomp, nx, ny, nz, w, r, s));
+    NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t2, dst, ncomp, nx, ny, nz, w, r, s));
+    return NSLGF_OK;
+}
+
+static int run_if_shared(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha,
+                         int dtype, hipStream_t s) {
+    const size_t bytes = (size_t)ncomp * nx * ny * nz * dtype_size(dtype);
     NSLGF_TRY(h->if_tmp1.ensure(bytes));
     NSLGF_TRY(h->if_tmp2.ensure(bytes));
-    NSLGF_PROF(h, "if_x", s, launch_if_axis(0, dtype, src, h->if_tmp1.p, ncomp, nx, ny, nz, w, r, s));
-    NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, h->if_tmp1.p, h->if_tmp2.p, ncomp, nx, ny, nz, w, r, s));
-    NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, h->if_tmp2.p, dst, ncomp, nx, ny, nz, w, r, s));
-    return NSLGF_OK;
+    return run_if(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, s, h->if_tmp1.p, h->if_tmp2.p);
+}
+
+// Layout of an IF-HERK state's workspace, in elements of its dtype.
+struct StateLayout {
+    size_t q, w1, w2, r, sdiv, dhat, t1, t2, a1, a2, total;
+};
+static StateLayout state_layout(int nx, int ny, int nz) {
+    const size_t M = (size_t)nx * ny * nz;
+    const int Py = padded(ny);
+    const int Px = padded(nx);
+    const size_t XP = (size_t)(((Px / 2 + 1 + 7) / 8) * 8);
+    StateLayout L{};
+    L.q = 0;
+    L.w1 = 3 * M;   // w1 directly after q: stage 2 applies H^1 to both as one 6-component field
+    L.w2 = 6 * M;
+    L.r = 9 * M;
+    L.sdiv = 12 * M;
+    L.dhat = 13 * M;
+    L.t1 = 14 * M;  // IF temporaries, 6 components each
+    L.t2 = 20 * M;
+    L.a1 = 26 * M;  // one-component convolution workspaces (complex)
+    L.a2 = L.a1 + (size_t)nz * ny * XP * 2;
+    L.total = L.a2 + (size_t)nz * Py * XP * 2;
+    return L;
 }
 
 // Shifted tableau a~, c~ (1-based, c~_0 = 0) of the three-stage schemes (Sec. 3.1, 3.2).
@@ -451,7 +525,7 @@ int lgf_convolve(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int n
     NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "lgf_convolve: dx must be > 0");
     ConvPlan* p = nullptr;
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p));
-    return run_conv(h, *p, src, dst, ncomp, dx * dx, (hipStream_t)stream);
+    return run_conv_shared(h, *p, src, dst, ncomp, dx * dx, (hipStream_t)stream);
 }
 
 int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
@@ -462,12 +536,12 @@ int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, i
     NSLGF_CHECK_ARG(src && dst, "if_apply: null pointer");
     NSLGF_CHECK_ARG(ncomp >= 1 && ncomp <= 6, "if_apply: ncomp must be 1..6");
     NSLGF_CHECK_ARG(std::isfinite(alpha) && alpha >= 0.0, "if_apply: alpha must be >= 0");
-    return run_if(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, (hipStream_t)stream);
+    return run_if_shared(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, (hipStream_t)stream);
 }
 
 size_t nslgf_state_bytes(int nx, int ny, int nz, int dtype) {
-    if (nx < 1 || ny < 1 || nz < 1) return 0;
-    return (size_t)14 * nx * ny * nz * dtype_size(dtype);
+    if (nx < 1 || ny < 1 || nz < 1 || nx > 256 || ny > 256 || nz > 256) return 0;
+    return state_layout(nx, ny, nz).total * dtype_size(dtype);
 }
 
 int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
@@ -491,12 +565,17 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     const long long M = (long long)nx * ny * nz;
     const size_t es = dtype_size(dt_);
     char* w = (char*)st->work;
-    void* q = w;
-    void* w1 = w + 3 * M * es;
-    void* w2 = w + 6 * M * es;
-    void* r = w + 9 * M * es;
-    void* sdiv = w + 12 * M * es;
-    void* dhat = w + 13 * M * es;
+    const StateLayout L = state_layout(nx, ny, nz);
+    void* q = w + L.q * es;
+    void* w1 = w + L.w1 * es;
+    void* w2 = w + L.w2 * es;
+    void* r = w + L.r * es;
+    void* sdiv = w + L.sdiv * es;
+    void* dhat = w + L.dhat * es;
+    void* t1 = w + L.t1 * es;
+    void* t2 = w + L.t2 * es;
+    void* a1 = w + L.a1 * es;
+    void* a2 = w + L.a2 * es;
     double at[4][4], ct[4];
     tableau(st->scheme, at, ct);
     const double dt = st->dt, beta = dt / (st->dx * st->dx * st->re);
@@ -513,7 +592,7 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     } else if (stage == 2) {
         const double a_prev = (ct[1] - ct[0]) * beta;
-        NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s));  // q and w1 are adjacent
+        NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s, t1, t2));  // q and w1 are adjacent
         c.c_q = 1.0;
         c.c_w1 = dt * at[2][1];
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s));
@@ -521,12 +600,12 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         // final-stage form: r^3 = H^2 (q^2 + dt (a~31 w^{2,1} + a~32 w^{2,2})) + g^3
         const double a_prev = (ct[2] - ct[1]) * beta;
         NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, r, q, 1.0, w1, dt * at[3][1], w2, dt * at[3][2], 3 * M, s));
-        NSLGF_TRY(run_if(h, r, r, 3, nx, ny, nz, a_prev, dt_, s));
+        NSLGF_TRY(run_if(h, r, r, 3, nx, ny, nz, a_prev, dt_, s, t1, t2));
         c.c_q = 1.0;
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     }
     NSLGF_PROF(h, "stage_div", s, launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
-    NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s));
+    NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s, a1, a2));
     if (stage == 1) {
         NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz, st->dx, s));
     } else if (stage == 2) {
@@ -536,7 +615,7 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx, ny, nz,
                                        st->dx, s));
     }
-    NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s));
+    NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s, t1, t2));
     if (stage == 3) {
         NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
         st->t += dt;
@@ -547,6 +626,103 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
 
 int herk_step(nslgf_t h, nslgf_state* st, void* stream) {
     for (int i = 1; i <= 3; ++i) NSLGF_TRY(herk_stage(h, st, i, stream));
+    return NSLGF_OK;
+}
+
+int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(sts != nullptr && n >= 1 && n <= 4096, "herk_step_batched: need 1..4096 states");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<unsigned long long> key;
+    key.reserve((size_t)n * 16);
+    auto bits = [](double v) {
+        unsigned long long b;
+        std::memcpy(&b, &v, sizeof b);
+        return b;
+    };
+    for (int i = 0; i < n; ++i) {
+        const nslgf_state* st = sts[i];
+        NSLGF_CHECK_ARG(st != nullptr, "herk_step_batched: null state");
+        NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+        NSLGF_TRY(check_dtype(st->dtype));
+        NSLGF_CHECK_ARG(st->u && st->d && st->work, "herk_step_batched: null u, d or work");
+        for (int j = 0; j < i; ++j)
+            NSLGF_CHECK_ARG(sts[j]->work != st->work && sts[j]->u != st->u,
+                            "herk_step_batched: states must not share u or work");
+        // plans and twiddles exist before any capture
+        ConvPlan* p = nullptr;
+        NSLGF_TRY(build_plan(h, st->nx, st->ny, st->nz, st->dtype, s, &p));
+        const void *a, *b, *c, *d;
+        NSLGF_TRY(plan_twiddles(h, *p, st->dtype, &a, &b, &c, &d));
+        const unsigned long long k[] = {(unsigned long long)st->nx, (unsigned long long)st->ny,
+                                        (unsigned long long)st->nz, (unsigned long long)st->dtype,
+                                        (unsigned long long)st->scheme, (unsigned long long)st->n_buf,
+                                        bits(st->dx), bits(st->dt), bits(st->re),
+                                        (unsigned long long)(uintptr_t)st->u, (unsigned long long)(uintptr_t)st->d,
+                                        (unsigned long long)(uintptr_t)st->work};
+        key.insert(key.end(), std::begin(k), std::end(k));
+    }
+    if (!h->batch || h->batch->key != key) {
+        h->batch.reset();
+        const int nb = std::min(n, 16);
+        while ((int)h->branches.size() < nb) {
+            hipStream_t bs;
+            NSLGF_HIP_CHECK(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+            h->branches.push_back(bs);
+        }
+        while ((int)h->batch_events.size() < nb + 1) {
+            hipEvent_t e;
+            NSLGF_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            h->batch_events.push_back(e);
+        }
+        if (!h->capture) NSLGF_HIP_CHECK(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+        const bool prof_was = h->prof.on;
+        h->prof.on = false;
+        std::vector<nslgf_state> saved(n);
+        for (int i = 0; i < n; ++i) saved[i] = *sts[i];
+        hipGraph_t graph = nullptr;
+        int rc = NSLGF_OK;
+        if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            set_error("herk_step_batched: stream capture could not start");
+            rc = NSLGF_EHIP;
+        }
+        if (rc == NSLGF_OK && hipEventRecord(h->batch_events[0], h->capture) != hipSuccess) rc = NSLGF_EHIP;
+        for (int b = 0; rc == NSLGF_OK && b < nb; ++b)
+            if (hipStreamWaitEvent(h->branches[b], h->batch_events[0], 0) != hipSuccess) rc = NSLGF_EHIP;
+        for (int i = 0; rc == NSLGF_OK && i < n; ++i) rc = herk_step(h, sts[i], h->branches[i % nb]);
+        for (int b = 0; rc == NSLGF_OK && b < nb; ++b) {
+            if (hipEventRecord(h->batch_events[b + 1], h->branches[b]) != hipSuccess ||
+                hipStreamWaitEvent(h->capture, h->batch_events[b + 1], 0) != hipSuccess)
+                rc = NSLGF_EHIP;
+        }
+        const hipError_t ec = hipStreamEndCapture(h->capture, &graph);
+        if (rc == NSLGF_OK && ec != hipSuccess) {
+            set_error(std::string("herk_step_batched: capture failed: ") + hipGetErrorString(ec));
+            rc = NSLGF_EHIP;
+        }
+        for (int i = 0; i < n; ++i) *sts[i] = saved[i];
+        h->prof.on = prof_was;
+        auto g = std::make_unique<BatchGraph>();
+        if (rc == NSLGF_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            set_error("herk_step_batched: graph instantiation failed");
+            rc = NSLGF_EHIP;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc != NSLGF_OK) {
+            (void)hipGetLastError();
+            return rc;
+        }
+        g->key = std::move(key);
+        h->batch = std::move(g);
+    }
+    {
+        ProfScope ps(h, "batch_graph", s);
+        NSLGF_HIP_CHECK(hipGraphLaunch(h->batch->exec, s));
+    }
+    for (int i = 0; i < n; ++i) {
+        sts[i]->t += sts[i]->dt;
+        sts[i]->stage_done = 3;
+    }
     return NSLGF_OK;
 }
 
@@ -561,7 +737,7 @@ int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
     const long long M = (long long)nx * ny * nz;
     NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
-    NSLGF_TRY(run_conv(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
+    NSLGF_TRY(run_conv_shared(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
     NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s));
     return NSLGF_OK;
 }

@@ -45,6 +45,9 @@ def test_host_lgf_value_matches_oracle():
 
 def test_state_bytes():
     L = nslgf.lib()
-    assert L.nslgf_state_bytes(8, 8, 8, 0) == 14 * 512 * 8
-    assert L.nslgf_state_bytes(8, 8, 8, 1) == 14 * 512 * 4
+    # 26 fields of the box (q, w1, w2, r, divergence, pressure, two 6-component IF temporaries) plus
+    # the one-component convolution workspaces
+    b64, b32 = L.nslgf_state_bytes(8, 8, 8, 0), L.nslgf_state_bytes(8, 8, 8, 1)
+    assert b64 >= 26 * 512 * 8 and b64 == 2 * b32
     assert L.nslgf_state_bytes(0, 8, 8, 0) == 0
+    assert L.nslgf_state_bytes(8, 300, 8, 0) == 0
