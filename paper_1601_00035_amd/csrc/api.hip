@@ -468,6 +468,13 @@ using namespace nslgf;
         NSLGF_HIP_CHECK(hipSetDevice((h)->device));                                                \
     } while (0)
 
+namespace nslgf {
+int enter_handle(nslgf_t h) {
+    NSLGF_ENTER(h);
+    return NSLGF_OK;
+}
+}  // namespace nslgf
+
 extern "C" {
 
 const char* nslgf_last_error(void) { return g_last_error.c_str(); }

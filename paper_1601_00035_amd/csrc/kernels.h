@@ -6,6 +6,9 @@
 
 namespace nslgf {
 
+// Validates a handle and makes its device current (used by entry points outside api.hip).
+int enter_handle(nslgf_t h);
+
 // ---- FFT passes (lgf_conv.hip) ----------------------------------------------------------------
 // Supported padded lengths P (2,3,5-smooth, even) of the zero-padded convolution.
 bool fft_length_supported(int P);

@@ -1,0 +1,508 @@
+// Layers of the learned surrogate (a 3D convolutional U-Net) on CDNA4 matrix cores.
+//
+// The 3x3x3 convolutions are implicit GEMMs on v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32
+// accumulation).  One wavefront owns a 32 x 32 output tile and walks the 27 taps and the input
+// channels in steps of 16, gathering its A operand straight from the channels-last activation (the
+// 8 BF16 values a lane supplies are contiguous channels of one voxel) and its B operand from the
+// weight rows.  Operand layout of the instruction (wave64), checked by sur_mfma_selftest:
+//   A (32 x 16): lane l supplies A[l % 32][8 (l / 32) + j], j < 8
+//   B (16 x 32): lane l supplies B[8 (l / 32) + j][l % 32]
+//   D (32 x 32): lane l holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in accumulator i < 16
+// The weight gradient reduces over voxels in fixed chunks followed by a fixed-order sum, so every
+// result is deterministic.
+#include <cmath>
+
+#include "../../include/nslgf_surrogate.h"
+#include "kernels.h"
+
+namespace nslgf {
+
+typedef unsigned short bf16_t;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ __forceinline__ bf16x8 load8(const bf16_t* p) {
+    const uint4 q = *(const uint4*)p;
+    return __builtin_bit_cast(bf16x8, q);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+__device__ __forceinline__ bf16x8 pack8(const bf16_t v[8]) {
+    uint4 q;
+    q.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+    q.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+    q.z = (unsigned)v[4] | ((unsigned)v[5] << 16);
+    q.w = (unsigned)v[6] | ((unsigned)v[7] << 16);
+    return __builtin_bit_cast(bf16x8, q);
+}
+
+__device__ __forceinline__ int tap_dz(int t) { return t / 9 - 1; }
+__device__ __forceinline__ int tap_dy(int t) { return (t / 3) % 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+// Y[v][n] = act(sum_tap sum_k X[v + SIGN off(tap)][k] Wn[tap][n][k]);  K % 16 == 0, N % 32 == 0.
+template <bool RELU, int SIGN>
+__global__ void __launch_bounds__(256) k_conv_mfma(const bf16_t* __restrict__ X, const bf16_t* __restrict__ Wn,
+                                                   float* __restrict__ Y, int D, int H, int W, int K, int N) {
+    const int wave = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const long long nvox = (long long)D * H * W;
+    const int mtiles = (int)(nvox / 32), ntiles = N / 32;
+    if (wave >= mtiles * ntiles) return;
+    const int mt = wave % mtiles, nt = wave / mtiles;
+    const long long v0 = (long long)mt * 32;
+    const int n0 = nt * 32;
+    const int m = lane % 32, half = lane / 32;
+    const long long v = v0 + m;
+    const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long long)W * H));
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    for (int tap = 0; tap < 27; ++tap) {
+        const int zz = z + SIGN * tap_dz(tap), yy = y + SIGN * tap_dy(tap), xx = x + SIGN * tap_dx(tap);
+        const bool valid = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const long long vn = valid ? ((long long)zz * H + yy) * W + xx : 0;
+        const bf16_t* xrow = X + vn * K + half * 8;
+        const bf16_t* wrow = Wn + ((long long)tap * N + n0 + m) * K + half * 8;
+        for (int kc = 0; kc < K; kc += 16) {
+            const bf16x8 a = valid ? load8(xrow + kc) : zero8();
+            const bf16x8 b = load8(wrow + kc);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int row = 8 * (i / 4) + 4 * half + (i % 4);
+        float val = acc[i];
+        if (RELU) val = fmaxf(val, 0.f);
+        Y[(v0 + row) * N + n0 + m] = val;
+    }
+}
+
+// Partial weight gradient of one voxel chunk: P[chunk][tap][co][ci] = sum_{v in chunk} dY[v][co] X[v+off][ci]
+__global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ dY, const bf16_t* __restrict__ X,
+                                                    float* __restrict__ P, int D, int H, int W, int cin, int cout,
+                                                    int chunk_len, int nchunks) {
+    const int wave = blockIdx.x * 4 + threadIdx.x / 64;
+    const int lane = threadIdx.x % 64;
+    const int cotiles = cout / 32, citiles = (cin + 31) / 32;
+    const int total = nchunks * 27 * cotiles * citiles;
+    if (wave >= total) return;
+    int r = wave;
+    const int cit = r % citiles;
+    r /= citiles;
+    const int cot = r % cotiles;
+    r /= cotiles;
+    const int tap = r % 27;
+    const int chunk = r / 27;
+    const int m = lane % 32, half = lane / 32;
+    const int co = cot * 32 + m;   // A row
+    const int ci = cit * 32 + m;   // B column
+    const bool ci_ok = ci < cin;
+    const int dz = tap_dz(tap), dy = tap_dy(tap), dx = tap_dx(tap);
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    const long long vstart = (long long)chunk * chunk_len;
+    for (long long vb = vstart; vb < vstart + chunk_len; vb += 16) {
+        bf16_t av[8], bv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long v = vb + 8 * half + j;
+            av[j] = dY[v * cout + co];
+            const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long long)W * H));
+            const int zz = z + dz, yy = y + dy, xx = x + dx;
+            const bool ok = ci_ok && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            bv[j] = ok ? X[(((long long)zz * H + yy) * W + xx) * cin + ci] : (bf16_t)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pack8(av), pack8(bv), acc, 0, 0, 0);
+    }
+    if (!ci_ok) return;
+    float* out = P + ((long long)chunk * 27 + tap) * cout * cin;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int row = cot * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+        out[(long long)row * cin + ci] = acc[i];
+    }
+}
+
+__global__ void k_sum_chunks(const float* __restrict__ P, float* __restrict__ dW, long long n, int nchunks) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += P[(long long)c * n + i];
+    dW[i] = s;
+}
+
+__global__ void k_wtranspose(const bf16_t* __restrict__ w, bf16_t* __restrict__ wt, int cin, int cout) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = 27LL * cin * cout;
+    if (i >= n) return;
+    const int ci = (int)(i % cin);
+    const int co = (int)((i / cin) % cout);
+    const int tap = (int)(i / ((long long)cin * cout));
+    wt[((long long)tap * cin + ci) * cout + co] = w[i];
+}
+
+__global__ void k_cast_bf16(const float* __restrict__ x, bf16_t* __restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+__global__ void k_relu_bwd(const float* __restrict__ y, float* __restrict__ g, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(y[i] > 0.f)) g[i] = 0.f;
+}
+__global__ void k_add(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ o, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = a[i] + b[i];
+}
+
+// coarse voxel index of fine (z, y, x)
+__device__ __forceinline__ long long coarse_of(long long v, int D, int H, int W) {
+    const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long long)W * H));
+    return ((long long)(z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2;
+}
+
+__global__ void k_pool2_fwd(const float* __restrict__ x, float* __restrict__ y, int D, int H, int W, int c) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nc = (long long)(D / 2) * (H / 2) * (W / 2) * c;
+    if (i >= nc) return;
+    const int ch = (int)(i % c);
+    const long long vc = i / c;
+    const int X = (int)(vc % (W / 2)), Y = (int)((vc / (W / 2)) % (H / 2)), Z = (int)(vc / ((long long)(W / 2) * (H / 2)));
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d) s += x[((((long long)(2 * Z + a) * H + 2 * Y + b) * W) + 2 * X + d) * c + ch];
+    y[i] = 0.125f * s;
+}
+__global__ void k_pool2_bwd(const float* __restrict__ gy, float* __restrict__ gx, int D, int H, int W, int c) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)D * H * W * c;
+    if (i >= nf) return;
+    const int ch = (int)(i % c);
+    gx[i] = 0.125f * gy[coarse_of(i / c, D, H, W) * c + ch];
+}
+__global__ void k_up2_fwd(const float* __restrict__ x, float* __restrict__ y, int D, int H, int W, int c) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nf = (long long)D * H * W * c;
+    if (i >= nf) return;
+    const int ch = (int)(i % c);
+    y[i] = x[coarse_of(i / c, D, H, W) * c + ch];
+}
+__global__ void k_up2_bwd(const float* __restrict__ gy, float* __restrict__ gx, int D, int H, int W, int c) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long nc = (long long)(D / 2) * (H / 2) * (W / 2) * c;
+    if (i >= nc) return;
+    const int ch = (int)(i % c);
+    const long long vc = i / c;
+    const int X = (int)(vc % (W / 2)), Y = (int)((vc / (W / 2)) % (H / 2)), Z = (int)(vc / ((long long)(W / 2) * (H / 2)));
+    float s = 0.f;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 2; ++d) s += gy[((((long long)(2 * Z + a) * H + 2 * Y + b) * W) + 2 * X + d) * c + ch];
+    gx[i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ pred, const float* __restrict__ tgt,
+                                             float* __restrict__ grad, double* __restrict__ partial, long long nvox,
+                                             int c, int used) {
+    __shared__ double red[256];
+    const long long n = nvox * c;
+    const double inv = 2.0 / ((double)nvox * used);
+    double s = 0.0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int ch = (int)(i % c);
+        if (ch < used) {
+            const double d = (double)pred[i] - (double)tgt[(i / c) * used + ch];
+            s += d * d;
+            grad[i] = (float)(inv * d);
+        } else {
+            grad[i] = 0.f;
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(float* __restrict__ w, bf16_t* __restrict__ wb, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+}
+
+__global__ void k_pack_input(const double* __restrict__ om, bf16_t* __restrict__ x, long long nvox, double scale,
+                             double feat) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    bf16_t out[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) out[k] = 0;
+    for (int q = 0; q < 3; ++q) out[q] = f2bf((float)(om[q * nvox + v] * scale));
+    out[3] = f2bf((float)feat);
+    uint4* dst = (uint4*)(x + v * 16);
+    dst[0] = __builtin_bit_cast(uint4, pack8(out));
+    dst[1] = __builtin_bit_cast(uint4, pack8(out + 8));
+}
+__global__ void k_pack_target(const double* __restrict__ f, float* __restrict__ t, long long nvox, double scale) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    for (int q = 0; q < 3; ++q) t[v * 3 + q] = (float)(f[q * nvox + v] * scale);
+}
+__global__ void k_unpack_update(const double* __restrict__ base, const float* __restrict__ y, double* __restrict__ out,
+                                long long nvox, int c, double inv_scale) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    for (int q = 0; q < 3; ++q) out[q * nvox + v] = base[q * nvox + v] + (double)y[v * c + q] * inv_scale;
+}
+
+__global__ void k_mfma_selftest(const bf16_t* A, const bf16_t* B, float* C) {
+    const int l = threadIdx.x;
+    const int m = l % 32, half = l / 32;
+    bf16_t av[8], bv[8];
+    for (int j = 0; j < 8; ++j) {
+        av[j] = A[m * 16 + 8 * half + j];
+        bv[j] = B[(8 * half + j) * 32 + m];
+    }
+    f32x16 acc;
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(pack8(av), pack8(bv), acc, 0, 0, 0);
+    for (int i = 0; i < 16; ++i) C[(8 * (i / 4) + 4 * half + (i % 4)) * 32 + m] = acc[i];
+}
+
+static int grid1(long long n) { return ceil_div(n, 256); }
+
+static int wgrad_chunks(long long nvox) {
+    // voxel chunks of at least 512 (a multiple of 16), at most 64 chunks
+    int nch = 1;
+    while (nch < 64 && nvox / (nch * 2) >= 512 && (nvox / (nch * 2)) % 16 == 0 && nvox % (nch * 2) == 0) nch *= 2;
+    return nch;
+}
+
+}  // namespace nslgf
+
+using namespace nslgf;
+
+#define SUR_ENTER(h)                                                                               \
+    do {                                                                                           \
+        int rc_ = enter_handle(h);                                                                 \
+        if (rc_ != NSLGF_OK) return rc_;                                                           \
+    } while (0)
+
+static int conv_shape_ok(int D, int H, int W, int cin, int cout) {
+    NSLGF_CHECK_ARG(D >= 1 && H >= 1 && W >= 1 && (long long)D * H * W % 32 == 0, "surrogate: D*H*W must be a multiple of 32");
+    NSLGF_CHECK_ARG(cin >= 16 && cin % 16 == 0 && cin <= 1024, "surrogate: cin must be a multiple of 16");
+    NSLGF_CHECK_ARG(cout >= 32 && cout % 32 == 0 && cout <= 1024, "surrogate: cout must be a multiple of 32");
+    return NSLGF_OK;
+}
+
+extern "C" {
+
+int sur_conv3d_fwd(nslgf_t h, const void* x, const void* w, void* y, int D, int H, int W, int cin, int cout, int relu,
+                   void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
+    NSLGF_CHECK_ARG(x && w && y, "sur_conv3d_fwd: null pointer");
+    const long long waves = (long long)D * H * W / 32 * (cout / 32);
+    hipStream_t s = (hipStream_t)stream;
+    if (relu)
+        hipLaunchKernelGGL((k_conv_mfma<true, 1>), dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)x,
+                           (const bf16_t*)w, (float*)y, D, H, W, cin, cout);
+    else
+        hipLaunchKernelGGL((k_conv_mfma<false, 1>), dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)x,
+                           (const bf16_t*)w, (float*)y, D, H, W, cin, cout);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_conv3d_bwd_data(nslgf_t h, const void* dy, const void* wt, void* dx, int D, int H, int W, int cin, int cout,
+                        void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
+    NSLGF_CHECK_ARG(cin % 32 == 0, "sur_conv3d_bwd_data: cin must be a multiple of 32");
+    NSLGF_CHECK_ARG(dy && wt && dx, "sur_conv3d_bwd_data: null pointer");
+    // GEMM with K = cout (inner) and N = cin (outputs), gathering dy at v - off
+    const long long waves = (long long)D * H * W / 32 * (cin / 32);
+    hipLaunchKernelGGL((k_conv_mfma<false, -1>), dim3(ceil_div(waves, 4)), dim3(256), 0, (hipStream_t)stream,
+                       (const bf16_t*)dy, (const bf16_t*)wt, (float*)dx, D, H, W, cout, cin);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+size_t sur_bwd_weight_work_bytes(int D, int H, int W, int cin, int cout) {
+    if (D < 1 || H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
+    return (size_t)wgrad_chunks((long long)D * H * W) * 27 * cin * cout * sizeof(float);
+}
+
+int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, void* work, int D, int H, int W, int cin,
+                          int cout, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
+    NSLGF_CHECK_ARG(dy && x && dw && work, "sur_conv3d_bwd_weight: null pointer");
+    const long long nvox = (long long)D * H * W;
+    const int nch = wgrad_chunks(nvox);
+    const int chunk_len = (int)(nvox / nch);
+    const long long waves = (long long)nch * 27 * (cout / 32) * ((cin + 31) / 32);
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)dy, (const bf16_t*)x,
+                       (float*)work, D, H, W, cin, cout, chunk_len, nch);
+    const long long n = 27LL * cin * cout;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)work, (float*)dw, n, nch);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_weight_transpose(nslgf_t h, const void* w, void* wt, int cin, int cout, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(w && wt && w != wt && cin > 0 && cout > 0, "sur_weight_transpose: bad arguments");
+    const long long n = 27LL * cin * cout;
+    hipLaunchKernelGGL(k_wtranspose, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const bf16_t*)w, (bf16_t*)wt,
+                       cin, cout);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+#define SUR_ELEMWISE(call)                                                                         \
+    SUR_ENTER(h);                                                                                  \
+    NSLGF_CHECK_ARG(n >= 0, "surrogate: negative size");                                           \
+    if (n == 0) return NSLGF_OK;                                                                   \
+    call;                                                                                          \
+    NSLGF_LAUNCH_CHECK();                                                                          \
+    return NSLGF_OK;
+
+int sur_cast_bf16(nslgf_t h, const void* x, void* y, long long n, void* stream) {
+    SUR_ELEMWISE(hipLaunchKernelGGL(k_cast_bf16, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)x,
+                                    (bf16_t*)y, n))
+}
+int sur_relu_bwd(nslgf_t h, const void* y, void* g, long long n, void* stream) {
+    SUR_ELEMWISE(hipLaunchKernelGGL(k_relu_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)y,
+                                    (float*)g, n))
+}
+int sur_add(nslgf_t h, const void* a, const void* b, void* o, long long n, void* stream) {
+    SUR_ELEMWISE(hipLaunchKernelGGL(k_add, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)a,
+                                    (const float*)b, (float*)o, n))
+}
+
+static int resample_ok(int D, int H, int W, int c) {
+    NSLGF_CHECK_ARG(D >= 2 && H >= 2 && W >= 2 && D % 2 == 0 && H % 2 == 0 && W % 2 == 0 && c >= 1,
+                    "surrogate: resampling needs even fine sizes");
+    return NSLGF_OK;
+}
+
+int sur_pool2_fwd(nslgf_t h, const void* x, void* y, int D, int H, int W, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(resample_ok(D, H, W, c));
+    const long long n = (long long)(D / 2) * (H / 2) * (W / 2) * c;
+    hipLaunchKernelGGL(k_pool2_fwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)x, (float*)y, D, H,
+                       W, c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_pool2_bwd(nslgf_t h, const void* gy, void* gx, int D, int H, int W, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(resample_ok(D, H, W, c));
+    const long long n = (long long)D * H * W * c;
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)gy, (float*)gx, D,
+                       H, W, c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_up2_fwd(nslgf_t h, const void* x, void* y, int D, int H, int W, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(resample_ok(D, H, W, c));
+    const long long n = (long long)D * H * W * c;
+    hipLaunchKernelGGL(k_up2_fwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)x, (float*)y, D, H, W,
+                       c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_up2_bwd(nslgf_t h, const void* gy, void* gx, int D, int H, int W, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(resample_ok(D, H, W, c));
+    const long long n = (long long)(D / 2) * (H / 2) * (W / 2) * c;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const float*)gy, (float*)gx, D, H,
+                       W, c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_mse(nslgf_t h, const void* pred, const void* target, void* grad, void* partial, long long nvox, int c, int used,
+            void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(pred && target && grad && partial && nvox > 0 && used >= 1 && used <= c, "sur_mse: bad arguments");
+    hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred, (const float*)target,
+                       (float*)grad, (double*)partial, nvox, c, used);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_adam(nslgf_t h, void* w, void* wb, const void* g, void* m, void* v, long long n, float lr, float b1, float b2,
+             float eps, int t, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(w && wb && g && m && v && n > 0 && t >= 1, "sur_adam: bad arguments");
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (float*)w, (bf16_t*)wb, (const float*)g,
+                       (float*)m, (float*)v, n, lr, b1, b2, eps, c1, c2);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_pack_input(nslgf_t h, const void* om, void* x, int D, int H, int W, double scale, double feat, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(om && x && D > 0 && H > 0 && W > 0, "sur_pack_input: bad arguments");
+    const long long nvox = (long long)D * H * W;
+    hipLaunchKernelGGL(k_pack_input, dim3(grid1(nvox)), dim3(256), 0, (hipStream_t)stream, (const double*)om,
+                       (bf16_t*)x, nvox, scale, feat);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_pack_target(nslgf_t h, const void* f, void* t, int D, int H, int W, double scale, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(f && t && D > 0 && H > 0 && W > 0, "sur_pack_target: bad arguments");
+    const long long nvox = (long long)D * H * W;
+    hipLaunchKernelGGL(k_pack_target, dim3(grid1(nvox)), dim3(256), 0, (hipStream_t)stream, (const double*)f, (float*)t,
+                       nvox, scale);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_unpack_update(nslgf_t h, const void* base, const void* y, void* out, int D, int H, int W, int c, double scale,
+                      void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(base && y && out && c >= 3 && scale != 0.0, "sur_unpack_update: bad arguments");
+    const long long nvox = (long long)D * H * W;
+    hipLaunchKernelGGL(k_unpack_update, dim3(grid1(nvox)), dim3(256), 0, (hipStream_t)stream, (const double*)base,
+                       (const float*)y, (double*)out, nvox, c, 1.0 / scale);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_mfma_selftest(nslgf_t h, const void* a, const void* b, void* c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(a && b && c, "sur_mfma_selftest: null pointer");
+    hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, (hipStream_t)stream, (const bf16_t*)a, (const bf16_t*)b,
+                       (float*)c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+}  // extern "C"

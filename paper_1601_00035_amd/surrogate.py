@@ -1,0 +1,305 @@
+"""Learned surrogate of the IF-HERK step (not part of the paper): a 3D convolutional U-Net.
+
+The network maps the edge vorticity w_k (3 channels, scaled) and a Reynolds-number feature to the
+change w_{k+S} - w_k over S steps; a proposal is w_k plus that change.  The plain step of the library
+judges every proposal (Vor2Vel + S IF-HERK steps from the same state) and replaces it when its error
+exceeds the tolerance.  This module only wires layers together: every layer, forward and backward,
+and every optimiser update runs in the library's kernels (include/nslgf_surrogate.h), on BF16 matrix
+cores with FP32 accumulation.
+
+Architecture (4 levels, 32-128 channels, 3x3x3 convolutions, ReLU, average pooling, nearest
+upsampling, additive skips):
+  R:   conv 16->32, conv 32->32 (e1) | R/2: conv 32->64 (e2) | R/4: conv 64->96 (e3)
+  R/8: conv 96->128, conv 128->96 | up + e3 -> conv 96->64 | up + e2 -> conv 64->32
+  up + e1 -> conv 32->32 -> conv 32->32 (linear; channels 0..2 are the output)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from . import _check, _stream, handle, lib
+
+IN_CH = 16
+OUT_CH = 32
+USED = 3
+LAYERS = [(16, 32), (32, 32), (32, 64), (64, 96), (96, 128), (128, 96), (96, 64), (64, 32), (32, 32), (32, 32)]
+LEVEL = [0, 0, 1, 2, 3, 3, 2, 1, 0, 0]
+RELU = [1, 1, 1, 1, 1, 1, 1, 1, 1, 0]
+
+_bound = False
+
+
+def _bind():
+    global _bound
+    if _bound:
+        return
+    L = lib()
+    vp, i, d, f, ll = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_float, ctypes.c_longlong
+    sig = {
+        "sur_conv3d_fwd": [vp, vp, vp, vp, i, i, i, i, i, i, vp],
+        "sur_conv3d_bwd_data": [vp, vp, vp, vp, i, i, i, i, i, vp],
+        "sur_conv3d_bwd_weight": [vp, vp, vp, vp, vp, i, i, i, i, i, vp],
+        "sur_weight_transpose": [vp, vp, vp, i, i, vp],
+        "sur_cast_bf16": [vp, vp, vp, ll, vp],
+        "sur_relu_bwd": [vp, vp, vp, ll, vp],
+        "sur_add": [vp, vp, vp, vp, ll, vp],
+        "sur_pool2_fwd": [vp, vp, vp, i, i, i, i, vp],
+        "sur_pool2_bwd": [vp, vp, vp, i, i, i, i, vp],
+        "sur_up2_fwd": [vp, vp, vp, i, i, i, i, vp],
+        "sur_up2_bwd": [vp, vp, vp, i, i, i, i, vp],
+        "sur_mse": [vp, vp, vp, vp, vp, ll, i, i, vp],
+        "sur_adam": [vp, vp, vp, vp, vp, vp, ll, f, f, f, f, i, vp],
+        "sur_pack_input": [vp, vp, vp, i, i, i, d, d, vp],
+        "sur_pack_target": [vp, vp, vp, i, i, i, d, vp],
+        "sur_unpack_update": [vp, vp, vp, vp, i, i, i, i, d, vp],
+        "sur_mfma_selftest": [vp, vp, vp, vp, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = i
+    L.sur_bwd_weight_work_bytes.argtypes = [i, i, i, i, i]
+    L.sur_bwd_weight_work_bytes.restype = ctypes.c_size_t
+    _bound = True
+
+
+def call(name: str, *args):
+    """Call one surrogate entry point on the current device and stream (tensors -> pointers)."""
+    _bind()
+    dev = torch.cuda.current_device()
+    conv = []
+    for a in args:
+        conv.append(a.data_ptr() if isinstance(a, torch.Tensor) else a)
+    s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(name, getattr(lib(), name)(handle(dev), *conv, s))
+
+
+def bf16_empty(n: int, device) -> torch.Tensor:
+    """Raw BF16 storage (16-bit words) for the kernels."""
+    return torch.empty(n, dtype=torch.int16, device=device)
+
+
+def mfma_selftest(a_bf16: torch.Tensor, b_bf16: torch.Tensor) -> torch.Tensor:
+    c = torch.empty((32, 32), dtype=torch.float32, device=a_bf16.device)
+    call("sur_mfma_selftest", a_bf16, b_bf16, c)
+    return c
+
+
+class UNet:
+    """Weights, optimiser state and activation buffers of the surrogate network."""
+
+    def __init__(self, device="cuda:0", seed: int = 0, out_scale: float = 0.1):
+        self.device = torch.device(device)
+        g = torch.Generator().manual_seed(seed)
+        self.w, self.wb, self.wt, self.gw, self.m, self.v = [], [], [], [], [], []
+        for li, (ci, co) in enumerate(LAYERS):
+            fan_in = 27 * (4 if li == 0 else ci)
+            std = math.sqrt(2.0 / fan_in) * (out_scale if li == len(LAYERS) - 1 else 1.0)
+            w = torch.randn((27, co, ci), generator=g) * std
+            if li == 0:
+                w[:, :, 4:] = 0.0  # only 4 real input channels
+            w = w.to(self.device, torch.float32).contiguous()
+            self.w.append(w)
+            wb = bf16_empty(w.numel(), self.device)
+            call("sur_cast_bf16", w, wb, w.numel())
+            self.wb.append(wb)
+            self.wt.append(bf16_empty(w.numel(), self.device))
+            self.gw.append(torch.zeros_like(w))
+            self.m.append(torch.zeros_like(w))
+            self.v.append(torch.zeros_like(w))
+        self.t = 0
+        self.bufs = {}
+
+    # ---- buffers ------------------------------------------------------------------------------
+    def _buf(self, key, n, bf16=False):
+        b = self.bufs.get(key)
+        if b is None or b.numel() < n:
+            b = bf16_empty(n, self.device) if bf16 else torch.empty(n, dtype=torch.float32, device=self.device)
+            self.bufs[key] = b
+        return b
+
+    def _cast(self, src, key, n):
+        dst = self._buf(key + "_b", n, bf16=True)
+        call("sur_cast_bf16", src, dst, n)
+        return dst
+
+    # ---- forward ------------------------------------------------------------------------------
+    def forward(self, xb: torch.Tensor, R: int) -> torch.Tensor:
+        """xb: BF16 input [R^3][16]; returns the FP32 output [R^3][32] (channels 0..2 meaningful)."""
+        assert R % 16 == 0 and R >= 32
+        r = [R >> l for l in range(4)]
+        nv = [x ** 3 for x in r]
+        A = {}
+        self.R = R
+        A["x_b"] = xb
+
+        def conv(li, src_b, key):
+            ci, co = LAYERS[li]
+            lv = LEVEL[li]
+            out = self._buf(key, nv[lv] * co)
+            call("sur_conv3d_fwd", src_b, self.wb[li], out, r[lv], r[lv], r[lv], ci, co, RELU[li])
+            return out
+
+        A["a0"] = conv(0, xb, "a0")
+        A["a0_b"] = self._cast(A["a0"], "a0", nv[0] * 32)
+        A["e1"] = conv(1, A["a0_b"], "e1")
+        A["p1"] = self._buf("p1", nv[1] * 32)
+        call("sur_pool2_fwd", A["e1"], A["p1"], r[0], r[0], r[0], 32)
+        A["p1_b"] = self._cast(A["p1"], "p1", nv[1] * 32)
+        A["e2"] = conv(2, A["p1_b"], "e2")
+        A["p2"] = self._buf("p2", nv[2] * 64)
+        call("sur_pool2_fwd", A["e2"], A["p2"], r[1], r[1], r[1], 64)
+        A["p2_b"] = self._cast(A["p2"], "p2", nv[2] * 64)
+        A["e3"] = conv(3, A["p2_b"], "e3")
+        A["p3"] = self._buf("p3", nv[3] * 96)
+        call("sur_pool2_fwd", A["e3"], A["p3"], r[2], r[2], r[2], 96)
+        A["p3_b"] = self._cast(A["p3"], "p3", nv[3] * 96)
+        A["b4"] = conv(4, A["p3_b"], "b4")
+        A["b4_b"] = self._cast(A["b4"], "b4", nv[3] * 128)
+        A["b5"] = conv(5, A["b4_b"], "b5")
+        A["u3"] = self._buf("u3", nv[2] * 96)
+        call("sur_up2_fwd", A["b5"], A["u3"], r[2], r[2], r[2], 96)
+        call("sur_add", A["u3"], A["e3"], A["u3"], nv[2] * 96)
+        A["u3_b"] = self._cast(A["u3"], "u3", nv[2] * 96)
+        A["d3"] = conv(6, A["u3_b"], "d3")
+        A["u2"] = self._buf("u2", nv[1] * 64)
+        call("sur_up2_fwd", A["d3"], A["u2"], r[1], r[1], r[1], 64)
+        call("sur_add", A["u2"], A["e2"], A["u2"], nv[1] * 64)
+        A["u2_b"] = self._cast(A["u2"], "u2", nv[1] * 64)
+        A["d2"] = conv(7, A["u2_b"], "d2")
+        A["u1"] = self._buf("u1", nv[0] * 32)
+        call("sur_up2_fwd", A["d2"], A["u1"], r[0], r[0], r[0], 32)
+        call("sur_add", A["u1"], A["e1"], A["u1"], nv[0] * 32)
+        A["u1_b"] = self._cast(A["u1"], "u1", nv[0] * 32)
+        A["d1"] = conv(8, A["u1_b"], "d1")
+        A["d1_b"] = self._cast(A["d1"], "d1", nv[0] * 32)
+        A["y"] = conv(9, A["d1_b"], "y")
+        self.A = A
+        return A["y"][: nv[0] * OUT_CH]
+
+    # ---- backward -----------------------------------------------------------------------------
+    def backward(self, gy: torch.Tensor):
+        """gy: FP32 gradient of the loss w.r.t. the output [R^3][32]; fills self.gw."""
+        A = self.A
+        R = self.R
+        r = [R >> l for l in range(4)]
+        nv = [x ** 3 for x in r]
+
+        def wgrad(li, g_b, x_b):
+            ci, co = LAYERS[li]
+            lv = LEVEL[li]
+            nbytes = lib().sur_bwd_weight_work_bytes(r[lv], r[lv], r[lv], ci, co)
+            work = self._buf("wgrad_work", nbytes // 4 + 1)
+            call("sur_conv3d_bwd_weight", g_b, x_b, self.gw[li], work, r[lv], r[lv], r[lv], ci, co)
+
+        def dgrad(li, g_b, key):
+            ci, co = LAYERS[li]
+            lv = LEVEL[li]
+            call("sur_weight_transpose", self.wb[li], self.wt[li], ci, co)
+            out = self._buf(key, nv[lv] * ci)
+            call("sur_conv3d_bwd_data", g_b, self.wt[li], out, r[lv], r[lv], r[lv], ci, co)
+            return out
+
+        def relu_bwd(act, g, n):
+            call("sur_relu_bwd", act, g, n)
+
+        gy_b = self._cast(gy, "gy", nv[0] * 32)
+        wgrad(9, gy_b, A["d1_b"])
+        gd1 = dgrad(9, gy_b, "gd1")
+        relu_bwd(A["d1"], gd1, nv[0] * 32)
+        gd1_b = self._cast(gd1, "gd1", nv[0] * 32)
+        wgrad(8, gd1_b, A["u1_b"])
+        gu1 = dgrad(8, gd1_b, "gu1")                       # also the gradient of e1 through the skip
+        gd2 = self._buf("gd2", nv[1] * 32)
+        call("sur_up2_bwd", gu1, gd2, r[0], r[0], r[0], 32)
+        relu_bwd(A["d2"], gd2, nv[1] * 32)
+        gd2_b = self._cast(gd2, "gd2", nv[1] * 32)
+        wgrad(7, gd2_b, A["u2_b"])
+        gu2 = dgrad(7, gd2_b, "gu2")
+        gd3 = self._buf("gd3", nv[2] * 64)
+        call("sur_up2_bwd", gu2, gd3, r[1], r[1], r[1], 64)
+        relu_bwd(A["d3"], gd3, nv[2] * 64)
+        gd3_b = self._cast(gd3, "gd3", nv[2] * 64)
+        wgrad(6, gd3_b, A["u3_b"])
+        gu3 = dgrad(6, gd3_b, "gu3")
+        gb5 = self._buf("gb5", nv[3] * 96)
+        call("sur_up2_bwd", gu3, gb5, r[2], r[2], r[2], 96)
+        relu_bwd(A["b5"], gb5, nv[3] * 96)
+        gb5_b = self._cast(gb5, "gb5", nv[3] * 96)
+        wgrad(5, gb5_b, A["b4_b"])
+        gb4 = dgrad(5, gb5_b, "gb4")
+        relu_bwd(A["b4"], gb4, nv[3] * 128)
+        gb4_b = self._cast(gb4, "gb4", nv[3] * 128)
+        wgrad(4, gb4_b, A["p3_b"])
+        gp3 = dgrad(4, gb4_b, "gp3")
+        ge3 = self._buf("ge3", nv[2] * 96)
+        call("sur_pool2_bwd", gp3, ge3, r[2], r[2], r[2], 96)
+        call("sur_add", ge3, gu3, ge3, nv[2] * 96)
+        relu_bwd(A["e3"], ge3, nv[2] * 96)
+        ge3_b = self._cast(ge3, "ge3", nv[2] * 96)
+        wgrad(3, ge3_b, A["p2_b"])
+        gp2 = dgrad(3, ge3_b, "gp2")
+        ge2 = self._buf("ge2", nv[1] * 64)
+        call("sur_pool2_bwd", gp2, ge2, r[1], r[1], r[1], 64)
+        call("sur_add", ge2, gu2, ge2, nv[1] * 64)
+        relu_bwd(A["e2"], ge2, nv[1] * 64)
+        ge2_b = self._cast(ge2, "ge2", nv[1] * 64)
+        wgrad(2, ge2_b, A["p1_b"])
+        gp1 = dgrad(2, ge2_b, "gp1")
+        ge1 = self._buf("ge1", nv[0] * 32)
+        call("sur_pool2_bwd", gp1, ge1, r[0], r[0], r[0], 32)
+        call("sur_add", ge1, gu1, ge1, nv[0] * 32)
+        relu_bwd(A["e1"], ge1, nv[0] * 32)
+        ge1_b = self._cast(ge1, "ge1", nv[0] * 32)
+        wgrad(1, ge1_b, A["a0_b"])
+        ga0 = dgrad(1, ge1_b, "ga0")
+        relu_bwd(A["a0"], ga0, nv[0] * 32)
+        ga0_b = self._cast(ga0, "ga0", nv[0] * 32)
+        wgrad(0, ga0_b, A["x_b"])
+
+    def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.t += 1
+        for li in range(len(LAYERS)):
+            call("sur_adam", self.w[li], self.wb[li], self.gw[li], self.m[li], self.v[li], self.w[li].numel(),
+                 lr, b1, b2, eps, self.t)
+
+    def loss_and_grad(self, y: torch.Tensor, target: torch.Tensor, nvox: int):
+        grad = self._buf("gy_f", nvox * OUT_CH)
+        part = torch.empty(1024, dtype=torch.float64, device=self.device)
+        call("sur_mse", y, target, grad, part, nvox, OUT_CH, USED)
+        return part, grad
+
+    def state_dict(self):
+        return {"w": [w.cpu() for w in self.w], "t": self.t}
+
+
+# ---- fields <-> network tensors -------------------------------------------------------------------
+def re_feature(re: float) -> float:
+    return math.log(re / 500.0)
+
+
+def pack_input(omega: torch.Tensor, scale: float, re: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """omega: planar FP64 [3][R][R][R] -> BF16 network input [R^3][16]."""
+    R = omega.shape[-1]
+    if out is None:
+        out = bf16_empty(R ** 3 * IN_CH, omega.device)
+    call("sur_pack_input", omega, out, R, R, R, float(scale), float(re_feature(re)))
+    return out
+
+
+def pack_target(delta: torch.Tensor, scale: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    R = delta.shape[-1]
+    if out is None:
+        out = torch.empty(R ** 3 * USED, dtype=torch.float32, device=delta.device)
+    call("sur_pack_target", delta, out, R, R, R, float(scale))
+    return out
+
+
+def unpack_update(base: torch.Tensor, y: torch.Tensor, scale: float) -> torch.Tensor:
+    R = base.shape[-1]
+    out = torch.empty_like(base)
+    call("sur_unpack_update", base, y, out, R, R, R, OUT_CH, float(scale))
+    return out

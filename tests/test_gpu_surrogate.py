@@ -1,0 +1,139 @@
+"""GPU parity of the surrogate's BF16 matrix-core layers against the FP64 oracle (on BF16-exact
+inputs the FP32-accumulated results must agree to ~1e-5), the whole U-Net forward and backward
+against the oracle network, and training that lowers the loss."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_00035_amd.surrogate as S
+from oracle import conv3d as C
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_bf16_bits(a: np.ndarray) -> torch.Tensor:
+    """float64 values that are exactly BF16 -> int16 storage on the GPU."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    bits = (f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return torch.from_numpy(bits.copy()).to(DEV)
+
+
+def rand_bf16(shape, seed, scale=1.0):
+    return C.bf16_round(np.random.default_rng(seed).standard_normal(shape) * scale)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+def test_mfma_operand_layout():
+    A = rand_bf16((32, 16), 1)
+    B = rand_bf16((16, 32), 2)
+    got = S.mfma_selftest(to_bf16_bits(A), to_bf16_bits(B)).double().cpu().numpy()
+    assert rel(got, A @ B) < 1e-6
+
+
+@pytest.mark.parametrize("dims,cin,cout", [((8, 8, 8), 32, 64), ((4, 8, 12), 16, 32), ((8, 4, 4), 96, 128)])
+def test_conv_layers(dims, cin, cout):
+    D, H, W = dims
+    x = rand_bf16((D, H, W, cin), 3)
+    w = rand_bf16((27, cout, cin), 4, 0.1)
+    gy = rand_bf16((D, H, W, cout), 5)
+    xb, wb, gyb = to_bf16_bits(x), to_bf16_bits(w), to_bf16_bits(gy)
+    nv = D * H * W
+    y = torch.empty(nv * cout, dtype=torch.float32, device=DEV)
+    S.call("sur_conv3d_fwd", xb, wb, y, D, H, W, cin, cout, 0)
+    ref = C.conv_fwd(x, w)
+    assert rel(y.double().cpu().numpy().reshape(ref.shape), ref) < 1e-5
+    S.call("sur_conv3d_fwd", xb, wb, y, D, H, W, cin, cout, 1)
+    assert rel(y.double().cpu().numpy().reshape(ref.shape), np.maximum(ref, 0)) < 1e-5
+    # weight gradient
+    nbytes = S.lib().sur_bwd_weight_work_bytes(D, H, W, cin, cout)
+    work = torch.empty(nbytes // 4 + 1, dtype=torch.float32, device=DEV)
+    gw = torch.empty(27 * cout * cin, dtype=torch.float32, device=DEV)
+    S.call("sur_conv3d_bwd_weight", gyb, xb, gw, work, D, H, W, cin, cout)
+    refw = C.conv_bwd_weight(gy, x)
+    assert rel(gw.double().cpu().numpy().reshape(refw.shape), refw) < 1e-5
+    if cin % 32 == 0:
+        wt = S.bf16_empty(w.size, DEV)
+        S.call("sur_weight_transpose", wb, wt, cin, cout)
+        gx = torch.empty(nv * cin, dtype=torch.float32, device=DEV)
+        S.call("sur_conv3d_bwd_data", gyb, wt, gx, D, H, W, cin, cout)
+        refx = C.conv_bwd_data(gy, w)
+        assert rel(gx.double().cpu().numpy().reshape(refx.shape), refx) < 1e-5
+
+
+def test_resampling_and_elementwise():
+    rng = np.random.default_rng(6)
+    D, H, W, c = 4, 6, 8, 5
+    x = rng.standard_normal((D, H, W, c)).astype(np.float32)
+    g = rng.standard_normal((D // 2, H // 2, W // 2, c)).astype(np.float32)
+    xt, gt = torch.from_numpy(x).to(DEV), torch.from_numpy(g).to(DEV)
+    out_c = torch.empty(g.size, dtype=torch.float32, device=DEV)
+    out_f = torch.empty(x.size, dtype=torch.float32, device=DEV)
+    S.call("sur_pool2_fwd", xt, out_c, D, H, W, c)
+    assert rel(out_c.cpu().numpy().reshape(g.shape), C.pool2(x.astype(np.float64))) < 1e-6
+    S.call("sur_pool2_bwd", gt, out_f, D, H, W, c)
+    assert rel(out_f.cpu().numpy().reshape(x.shape), C.pool2_adj(g.astype(np.float64))) < 1e-6
+    S.call("sur_up2_fwd", gt, out_f, D, H, W, c)
+    assert rel(out_f.cpu().numpy().reshape(x.shape), C.up2(g.astype(np.float64))) < 1e-7
+    S.call("sur_up2_bwd", xt, out_c, D, H, W, c)
+    assert rel(out_c.cpu().numpy().reshape(g.shape), C.up2_adj(x.astype(np.float64))) < 1e-6
+    y = xt.clone()
+    gg = torch.ones_like(xt)
+    S.call("sur_relu_bwd", y, gg, y.numel())
+    assert torch.equal(gg, (y > 0).float())
+    # squared error: gradient 2 (p - t) / (nvox used) on the used channels
+    nvox, cc, used = 64, 32, 3
+    p = torch.randn(nvox * cc, device=DEV)
+    t = torch.randn(nvox * used, device=DEV)
+    grad = torch.empty_like(p)
+    part = torch.empty(1024, dtype=torch.float64, device=DEV)
+    S.call("sur_mse", p, t, grad, part, nvox, cc, used)
+    pn, tn = p.double().cpu().numpy().reshape(nvox, cc), t.double().cpu().numpy().reshape(nvox, used)
+    assert abs(part.sum().item() - ((pn[:, :used] - tn) ** 2).sum()) < 1e-9
+    gref = np.zeros_like(pn)
+    gref[:, :used] = 2 * (pn[:, :used] - tn) / (nvox * used)
+    assert rel(grad.double().cpu().numpy().reshape(nvox, cc), gref) < 1e-6
+
+
+def test_unet_forward_backward_vs_oracle():
+    R = 32
+    net = S.UNet(DEV, seed=1, out_scale=1.0)
+    ws = [w.double().cpu().numpy() for w in net.w]
+    wsb = [C.bf16_round(w) for w in ws]  # the matrix cores see the BF16 copies
+    rng = np.random.default_rng(7)
+    x = np.zeros((R, R, R, 16))
+    x[..., :4] = C.bf16_round(rng.standard_normal((R, R, R, 4)))
+    y = net.forward(to_bf16_bits(x).reshape(-1), R)
+    A = C.unet_forward(x, wsb, bf16=True)
+    yref = A["y"]
+    assert rel(y.double().cpu().numpy().reshape(yref.shape), yref) < 2e-2
+    gy = rng.standard_normal(yref.shape)
+    net.backward(torch.from_numpy(gy.astype(np.float32).reshape(-1)).to(DEV))
+    gref = C.unet_backward(A, wsb, gy, bf16=True)
+    for li in range(10):
+        got = net.gw[li].double().cpu().numpy()
+        assert rel(got, gref[li]) < 5e-2, li
+
+
+def test_training_lowers_loss():
+    """Fit a fixed smooth target from a fixed input with Adam: the loss must fall."""
+    R = 32
+    net = S.UNet(DEV, seed=2)
+    z, y, x = np.meshgrid(*(np.linspace(-1, 1, R),) * 3, indexing="ij")
+    om = np.stack([np.exp(-4 * (x * x + y * y + z * z)), np.sin(2 * x) * np.exp(-y * y), z * np.exp(-x * x)])
+    omt = torch.from_numpy(om).to(DEV)
+    xb = S.pack_input(omt, 1.0, 500.0)
+    tgt = S.pack_target(0.3 * omt * omt, 1.0)
+    losses = []
+    for it in range(60):
+        out = net.forward(xb, R)
+        part, grad = net.loss_and_grad(out, tgt, R ** 3)
+        losses.append(part.sum().item() / (R ** 3 * 3))
+        net.backward(grad)
+        net.adam(lr=2e-3)
+    assert np.isfinite(losses).all()
+    assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
