@@ -303,3 +303,107 @@ def unpack_update(base: torch.Tensor, y: torch.Tensor, scale: float) -> torch.Te
     out = torch.empty_like(base)
     call("sur_unpack_update", base, y, out, R, R, R, OUT_CH, float(scale))
     return out
+
+
+# ---- data, training, judged roll-out ------------------------------------------------------------
+def vorticity(u: torch.Tensor, dx: float) -> torch.Tensor:
+    from . import stencil
+
+    return stencil("curl", u, dx)
+
+
+def make_trajectory(n: int, dx: float, sigma: float, re: float, seed: int, steps: int, cfl: float = 0.5,
+                    n_buf: int = 8, zc: float = -0.5):
+    """Vorticity snapshots w_0..w_steps (FP32, planar [3][n][n][n], on the GPU) of one ring advanced by
+    the plain FP64 IF-HERK step, and the step size."""
+    import workloads
+
+    from . import HerkState, max_cell_speed, vor2vel
+
+    ring = workloads.Ring(R=1.0, sigma=sigma, gamma=1.0, eps=1e-4, seed=seed, zc=zc)
+    w0 = torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring, quad=2)).to("cuda")
+    u = vor2vel(w0, dx)
+    dt = cfl * dx / max_cell_speed(u)
+    st = HerkState(u, dx, dt, re, "A", n_buf=n_buf)
+    snaps = [vorticity(u, dx).float()]
+    for _ in range(steps):
+        st.step()
+        snaps.append(vorticity(u, dx).float())
+    return torch.stack(snaps), dt
+
+
+def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float = 1e-3, gain: float = 5.0,
+          seed: int = 0, log_every: int = 0):
+    """Adam on random (w_k, w_{k+horizon}) pairs: input w_k * s, target (w_{k+h} - w_k) * s * gain with
+    s = 1 / max|w_0| of the trajectory.  trajs[i]: snapshots [T][3][n][n][n]; res[i]: Re."""
+    g = torch.Generator().manual_seed(seed)
+    R = trajs[0].shape[-1]
+    nvox = R ** 3
+    xb = bf16_empty(nvox * IN_CH, net.device)
+    tg = torch.empty(nvox * USED, dtype=torch.float32, device=net.device)
+    scales = [1.0 / float(t[0].abs().max()) for t in trajs]
+    losses = []
+    for it in range(iters):
+        i = int(torch.randint(len(trajs), (1,), generator=g))
+        T = trajs[i].shape[0]
+        k = int(torch.randint(T - horizon, (1,), generator=g))
+        w_k = trajs[i][k].double()
+        pack_input(w_k, scales[i], res[i], out=xb)
+        pack_target(trajs[i][k + horizon].double() - w_k, scales[i] * gain, out=tg)
+        y = net.forward(xb, R)
+        part, grad = net.loss_and_grad(y, tg, nvox)
+        net.backward(grad)
+        net.adam(lr=lr)
+        if log_every and (it % log_every == 0 or it == iters - 1):
+            losses.append((it, part.sum().item() / (nvox * USED)))
+    return losses
+
+
+def propose(net: UNet, w_k: torch.Tensor, scale: float, re: float, gain: float = 5.0) -> torch.Tensor:
+    """The surrogate's proposal w_k + net(w_k) / (scale gain), FP64 planar."""
+    R = w_k.shape[-1]
+    xb = pack_input(w_k.double(), scale, re)
+    y = net.forward(xb, R)
+    return unpack_update(w_k.double(), y, scale * gain)
+
+
+def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: int, blocks: int, horizon: int = 4,
+                   tol: float = 1e-3, cfl: float = 0.5, n_buf: int = 8, gain: float = 5.0):
+    """Every `horizon` steps the surrogate proposes w_{k+h}; the plain FP64 step judges it from the
+    same state (rel. max error of the vorticity) and the roll-out continues from the proposal if the
+    error is within tol (velocity rebuilt by Vor2Vel), else from the plain result.  Returns per-block
+    errors, the persistence baseline (w_{k+h} ~ w_k) errors and timings."""
+    import workloads
+
+    from . import HerkState, max_cell_speed, vor2vel
+
+    ring = workloads.Ring(R=1.0, sigma=sigma, gamma=1.0, eps=1e-4, seed=seed, zc=-0.5)
+    w0 = torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring, quad=2)).to("cuda")
+    u = vor2vel(w0, dx)
+    dt = cfl * dx / max_cell_speed(u)
+    scale = 1.0 / float(vorticity(u, dx).abs().max())
+    out = {"err": [], "persistence_err": [], "accepted": [], "ms_surrogate": [], "ms_plain": []}
+    for _ in range(blocks):
+        w_k = vorticity(u, dx)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        prop = propose(net, w_k, scale, re, gain)
+        u_prop = vor2vel(prop, dx)
+        e1.record()
+        st = HerkState(u.clone(), dx, dt, re, "A", n_buf=n_buf)
+        for _ in range(horizon):
+            st.step()
+        e2.record()
+        torch.cuda.synchronize()
+        w_ref = vorticity(st.u, dx)
+        den = float(w_ref.abs().max())
+        err = float((prop - w_ref).abs().max()) / den
+        perr = float((w_k - w_ref).abs().max()) / den
+        ok = err <= tol
+        out["err"].append(err)
+        out["persistence_err"].append(perr)
+        out["accepted"].append(ok)
+        out["ms_surrogate"].append(e0.elapsed_time(e1))
+        out["ms_plain"].append(e1.elapsed_time(e2))
+        u = u_prop if ok else st.u
+    return out

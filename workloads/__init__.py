@@ -61,6 +61,7 @@ class Ring:
     gamma: float = 1.0
     eps: float = 0.0
     seed: int = 0
+    zc: float = 0.0  # height of the ring plane above the box centre
 
     def modes(self):
         rng = np.random.default_rng(self.seed)
@@ -71,6 +72,7 @@ class Ring:
     def omega(self, x, y, z):
         """Vorticity (wx, wy, wz) at points (arrays of equal shape)."""
         A, phi = self.modes()
+        z = z - self.zc
         rho = np.sqrt(x * x + y * y)
         th = np.arctan2(y, x)
         rc = np.full_like(rho, self.R)
@@ -98,7 +100,7 @@ def ring_edge_vorticity(n: int, dx: float, ring: Ring, quad: int = 4, cutoff: fl
     c = (n - 1) / 2.0
     gx, gw = _gauss_legendre(quad)
     rmax = ring.R * (1.0 + 10.0 * abs(ring.eps)) + cutoff * ring.sigma
-    zmax = cutoff * ring.sigma
+    zmax = cutoff * ring.sigma + abs(ring.zc)
     idx = np.arange(n)
     for q in range(3):
         # edge (q) position offsets in index units: -1/2 along axis q
@@ -168,3 +170,10 @@ def sample_targets(n: int, count: int, seed: int = 0) -> np.ndarray:
     j = (flat // n) % n
     i = flat % n
     return np.stack([k, j, i], axis=1).astype(np.int64)
+
+
+def surrogate_specs(count: int, seed: int = 0):
+    """Trajectory parameters of the surrogate's training data: (sigma/R, Re, perturbation seed) with
+    sigma/R ~ U[0.1, 0.3] and Re ~ U[250, 1000]; the ring starts half a radius below the centre."""
+    rng = np.random.default_rng(seed)
+    return [(float(rng.uniform(0.1, 0.3)), float(rng.uniform(250.0, 1000.0)), 2000 + i) for i in range(count)]
