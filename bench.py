@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--fft-plan", type=int, default=-1, choices=(-1, 0, 1),
+                    help="column-pass FFT radix plan: -1 per-length default, 0 narrow, 1 wide")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 1 GiB with the library's plain copy kernel (reference for byte counters)")
     args = ap.parse_args()
@@ -195,6 +197,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    nslgf.set_fft_plan(args.fft_plan)
     if args.calibrate:
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -329,6 +332,7 @@ def main():
             "n_buf": 16,
             "padded": [P, P, P],
             "table_build_s": round(table_s, 3),
+            "fft_plan": args.fft_plan,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -187,6 +187,15 @@ int max_cell_speed(nslgf_t h, const void *u, int nx, int ny, int nz, int dtype, 
  * far; NSLGF_EINVAL past the last one.  name receives at most name_cap bytes, NUL-terminated.
  */
 int nslgf_profile_enable(nslgf_t h, int enable);
+/*
+ * Radix plan of the strided (column) FFT passes of the convolution (Sec. 3.2's zero-padded FFT
+ * convolution; the plan changes the order of rounding only).  choice = 0: the narrow plan
+ * (fewer elements per thread, one LDS exchange per radix after the first); 1: the wide plan for
+ * padded lengths 256 and 512 (16 or 32 elements per thread, radices 16 x 16 and 16 x 32, one LDS
+ * exchange per transform); -1 (the default): wide in FP32, narrow in FP64.  Applies to plans built
+ * after the call (plans are cached per box, dtype and choice).  NSLGF_EINVAL for other values.
+ */
+int nslgf_set_fft_plan(nslgf_t h, int choice);
 /* Plain streaming copy of n elements of dtype (device pointers, no overlap, n * size a multiple of
  * 16 bytes, 16-byte aligned); the reference kernel whose hardware byte counters calibrate those of
  * the other kernels.  Profiled as "copy". */

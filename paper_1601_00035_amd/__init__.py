@@ -66,6 +66,7 @@ def lib():
                     "stencil_apply": [vp, i, vp, vp, i, i, i, i, d, i, vp],
                     "max_cell_speed": [vp, vp, i, i, i, i, ctypes.POINTER(d), vp],
                     "nslgf_profile_enable": [vp, i],
+                    "nslgf_set_fft_plan": [vp, i],
                     "nslgf_profile_read": [vp, i, ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_longlong),
                                            ctypes.POINTER(d)],
                     "nslgf_copy": [vp, vp, vp, ctypes.c_size_t, i, vp],
@@ -216,6 +217,12 @@ def max_cell_speed(u: torch.Tensor) -> float:
     _check("max_cell_speed", lib().max_cell_speed(handle(u.device.index), u.data_ptr(), nx, ny, nz, _dtype(u),
                                                   ctypes.byref(out), _stream(u)))
     return out.value
+
+
+def set_fft_plan(choice: int, device: int | None = None):
+    """Column-pass FFT plan of convolution plans built from now on: -1 per-length default,
+    0 narrow, 1 wide (lengths 256 and 512)."""
+    _check("nslgf_set_fft_plan", lib().nslgf_set_fft_plan(handle(device), int(choice)))
 
 
 def profile_enable(on: bool = True, device: int | None = None):

@@ -45,6 +45,7 @@ struct ConvPlan {
     int Px = 0, Py = 0, Pz = 0;
     long long XP = 0;
     int tb = 0, tiles = 0;
+    int vy = 0, vz = 0;  // column-pass plan variants of the y and z lengths
     DevBuf khat;
     DevBuf A1, A2;  // workspaces for up to 3 components
 };
@@ -123,7 +124,8 @@ struct nslgf_ctx {
         for (auto e : batch_events) (void)hipEventDestroy(e);
         if (capture) (void)hipStreamDestroy(capture);
     }
-    std::map<std::tuple<int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
+    int fft_plan = -1;  // column-pass plan choice: -1 per-length default, 0 narrow, 1 wide
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
 };
@@ -199,7 +201,7 @@ static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** t
                          const void** twz);
 
 static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, ConvPlan** out) {
-    auto key = std::make_tuple(nx, ny, nz, dtype);
+    auto key = std::make_tuple(nx, ny, nz, dtype, h->fft_plan);
     auto it = h->plans.find(key);
     if (it != h->plans.end()) {
         *out = it->second.get();
@@ -219,6 +221,8 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
         return NSLGF_EUNSUPPORTED;
     }
     p.XP = ((p.Px / 2 + 1 + 7) / 8) * 8;
+    p.vy = col_variant_choice(p.Py, dtype, h->fft_plan);
+    p.vz = col_variant_choice(p.Pz, dtype, h->fft_plan);
     p.tb = col_tile_width(p.Pz, dtype);
     p.tiles = ceil_div(p.Px / 2 + 1, p.tb);
     // FP64 kernel on the padded lattice and its spectrum
@@ -316,7 +320,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     c.n_in = p.ny;
     c.n_out = p.Py;
     c.tw = twy;
-    NSLGF_PROF(h, "conv_y_fwd", s, launch_col(p.Py, dt, COL_FWD, c, s));
+    NSLGF_PROF(h, "conv_y_fwd", s, launch_col(p.Py, dt, COL_FWD, c, s, p.vy));
     ColPass z{};
     z.in = A2;
     z.out = A2;
@@ -332,7 +336,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     z.khat_tiles = p.tiles;
     z.outer_period = p.Py;
     z.scale = scale;
-    NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s));
+    NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s, p.vz));
     ColPass y{};
     y.in = A2;
     y.out = A1;
@@ -347,7 +351,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     y.n_in = p.Py;
     y.n_out = p.ny;
     y.tw = twy;
-    NSLGF_PROF(h, "conv_y_inv", s, launch_col(p.Py, dt, COL_INV, y, s));
+    NSLGF_PROF(h, "conv_y_inv", s, launch_col(p.Py, dt, COL_INV, y, s, p.vy));
     RowPass o{};
     o.in = A1;
     o.out = dst;
@@ -515,7 +519,7 @@ int lgf_table(nslgf_t h, int nx, int ny, int nz, int dtype, void* stream) {
     NSLGF_ENTER(h);
     NSLGF_TRY(check_box(nx, ny, nz));
     NSLGF_TRY(check_dtype(dtype));
-    auto key = std::make_tuple(nx, ny, nz, dtype);
+    auto key = std::make_tuple(nx, ny, nz, dtype, h->fft_plan);
     h->plans.erase(key);
     ConvPlan* p = nullptr;
     return build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p);
@@ -666,7 +670,7 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
                                         (unsigned long long)st->scheme, (unsigned long long)st->n_buf,
                                         bits(st->dx), bits(st->dt), bits(st->re),
                                         (unsigned long long)(uintptr_t)st->u, (unsigned long long)(uintptr_t)st->d,
-                                        (unsigned long long)(uintptr_t)st->work};
+                                        (unsigned long long)(uintptr_t)st->work, (unsigned long long)(uintptr_t)p};
         key.insert(key.end(), std::begin(k), std::end(k));
     }
     if (!h->batch || h->batch->key != key) {
@@ -786,6 +790,13 @@ int nslgf_profile_enable(nslgf_t h, int enable) {
         h->prof.order.clear();
     }
     h->prof.on = enable != 0;
+    return NSLGF_OK;
+}
+
+int nslgf_set_fft_plan(nslgf_t h, int choice) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(choice >= -1 && choice <= 1, "nslgf_set_fft_plan: choice must be -1, 0 or 1");
+    h->fft_plan = choice;
     return NSLGF_OK;
 }
 

@@ -54,6 +54,19 @@ NSLGF_FFT_PLAN(384, 24, 3, 2, 8, 8)
 NSLGF_FFT_PLAN(512, 16, 8, 8, 8)
 #undef NSLGF_FFT_PLAN
 
+// Alternative plans with more elements per thread (fewer LDS exchanges, lower occupancy); the
+// plan builder times both variants of a length on the device and keeps the faster one.
+template <int L, int V> struct PlanV : Plan1D<L> {};
+template <> struct PlanV<512, 1> {
+    static constexpr int E = 32;
+    using Fwd = RList<16, 32>;
+};
+template <> struct PlanV<256, 1> {
+    static constexpr int E = 16;
+    using Fwd = RList<16, 16>;
+};
+template <int L> constexpr bool has_variant() { return L == 512 || L == 256; }
+
 // Columns per workgroup of the strided (column-tile) kernels: one 128-byte row segment at least,
 // and at least one wavefront per workgroup.
 template <typename T>
@@ -149,6 +162,41 @@ template <typename T, bool INV> struct DFT<T, 5, INV> {
     }
 };
 
+// Composite length R = R1 * R2 DFT on registers (decimation in time, n = R2 n1 + n2,
+// k = k1 + R1 k2): length-R1 DFTs over n1, internal twiddles W_R^{n2 k1} read from the root table
+// of the full transform (W_R^m = tw[m * (L/R)]), length-R2 DFTs over n2.
+template <typename T, int R1, int R2, bool INV> struct DFTC {
+    __device__ __forceinline__ static void run(cplx<T>* v, const cplx<T>* __restrict__ tw, int lr) {
+        constexpr int R = R1 * R2;
+        cplx<T> y[R];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) {
+            cplx<T> a[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) a[n1] = v[R2 * n1 + n2];
+            DFT<T, R1, INV>::run(a);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                if (n2 * k1 == 0) {
+                    y[k1 * R2 + n2] = a[k1];
+                } else {
+                    const cplx<T> w = tw[(n2 * k1) * lr];
+                    y[k1 * R2 + n2] = INV ? cmulc<T>(a[k1], w) : cmul<T>(a[k1], w);
+                }
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cplx<T> b[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) b[n2] = y[k1 * R2 + n2];
+            DFT<T, R2, INV>::run(b);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = b[k2];
+        }
+    }
+};
+
 // ---- passes -----------------------------------------------------------------------------------
 // tw: root table tw[m] = exp(-2 pi i m / L), m < L (forward); the inverse conjugates it.
 template <typename T, int L, int E, int TP, bool INV, int NS, int R>
@@ -164,7 +212,13 @@ __device__ __forceinline__ void pass_compute(cplx<T>* v, int t, const cplx<T>* _
                 v[b * R + r] = INV ? cmulc<T>(v[b * R + r], w) : cmul<T>(v[b * R + r], w);
             }
         }
-        DFT<T, R, INV>::run(v + b * R);
+        if constexpr (R == 16) {
+            DFTC<T, 4, 4, INV>::run(v + b * R, tw, L / 16);
+        } else if constexpr (R == 32) {
+            DFTC<T, 4, 8, INV>::run(v + b * R, tw, L / 32);
+        } else {
+            DFT<T, R, INV>::run(v + b * R);
+        }
     }
 }
 
@@ -214,9 +268,8 @@ struct Runner<T, L, E, TP, INV, NS, RList<R, R2, Rest...>> {
 
 // Full transform on registers: input v[b R1 + r] = x[t + b TP + r L/R1] (R1 = first radix of the
 // list), output v[b Rl + r] = X[t + b TP + r L/Rl] (Rl = last radix).
-template <typename T, int L, bool INV, class RL, class Acc>
+template <typename T, int L, bool INV, class RL, class Acc, int E = Plan1D<L>::E>
 __device__ __forceinline__ void fft_regs(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
-    constexpr int E = Plan1D<L>::E;
     Runner<T, L, E, L / E, INV, 1, RL>::run(v, t, tw, acc);
 }
 

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) k_if_cols(const T* __restrict__ in, T* __
 // its line into registers and produces S consecutive outputs with no bounds tests.
 // Line l of grid column group starts at comp * comp_stride + outer * outer_stride + l * line_stride
 // and its points are `stride` apart.
-template <typename T, int TB, int R, int S>
+template <typename T, int TB, int R, int S, bool CONTIG>
 __global__ void __launch_bounds__(256) k_if_lines(const T* __restrict__ in, T* __restrict__ out, int nlines, int len,
                                                   long long stride, long long line_stride, long long outer_stride,
                                                   long long comp_stride, IfWeights wts) {
@@ -141,22 +141,56 @@ __global__ void __launch_bounds__(256) k_if_lines(const T* __restrict__ in, T* _
     const bool valid = line < nlines;
     const long long base =
         blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride + (valid ? (long long)line * line_stride : 0);
-    for (int k = t; k < ROWS; k += TPC) {
-        const int kk = k - R;
-        lds[k * TB + c] = (valid && kk >= 0 && kk < len) ? in[base + kk * stride] : (T)0;
+    if (CONTIG) {
+        // lines are contiguous rows: global accesses run along the row (coalesced), LDS keeps [k][c]
+        for (int k = t; k < ROWS; k += TPC) lds[k * TB + c] = (T)0;
+        __syncthreads();
+        const long long base0 = blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride;
+        for (int e = threadIdx.x; e < TB * len; e += 256) {
+            const int cc = e / len, kk = e - cc * len;
+            const int ln = blockIdx.x * TB + cc;
+            if (ln < nlines) lds[(kk + R) * TB + cc] = in[base0 + (long long)ln * line_stride + kk];
+        }
+    } else {
+        for (int k = t; k < ROWS; k += TPC) {
+            const int kk = k - R;
+            lds[k * TB + c] = (valid && kk >= 0 && kk < len) ? in[base + kk * stride] : (T)0;
+        }
     }
     __syncthreads();
-    if (!valid || t * S >= len) return;
+    const bool active = valid && t * S < len;
     T v[S + 2 * R];
+    T res[S];
+    if (active) {
 #pragma unroll
-    for (int j = 0; j < S + 2 * R; ++j) v[j] = lds[(t * S + j) * TB + c];
+        for (int j = 0; j < S + 2 * R; ++j) v[j] = lds[(t * S + j) * TB + c];
 #pragma unroll
-    for (int m = 0; m < S; ++m) {
-        double acc = wts.w[0] * (double)v[m + R];
+        for (int m = 0; m < S; ++m) {
+            double acc = wts.w[0] * (double)v[m + R];
 #pragma unroll
-        for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
-        const int k = t * S + m;
-        if (k < len) out[base + k * stride] = (T)acc;
+            for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
+            res[m] = (T)acc;
+        }
+    }
+    if (CONTIG) {
+        __syncthreads();  // every window has been read: reuse the buffer for the outputs
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < S; ++m) lds[(t * S + m) * TB + c] = res[m];
+        }
+        __syncthreads();
+        const long long base0 = blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride;
+        for (int e = threadIdx.x; e < TB * len; e += 256) {
+            const int cc = e / len, kk = e - cc * len;
+            const int ln = blockIdx.x * TB + cc;
+            if (ln < nlines) out[base0 + (long long)ln * line_stride + kk] = lds[kk * TB + cc];
+        }
+    } else if (active) {
+#pragma unroll
+        for (int m = 0; m < S; ++m) {
+            const int k = t * S + m;
+            if (k < len) out[base + k * stride] = res[m];
+        }
     }
 }
 
@@ -193,8 +227,12 @@ static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int n
         outer_stride = nx;
     }
     dim3 grid(ceil_div(nlines, TB), nouter, ncomp);
-    hipLaunchKernelGGL((k_if_lines<T, TB, R, S>), grid, dim3(256), lds, s, in, out, nlines, len, stride, line_stride,
-                       outer_stride, n, wts);
+    if (axis == 0)
+        hipLaunchKernelGGL((k_if_lines<T, TB, R, S, true>), grid, dim3(256), lds, s, in, out, nlines, len, stride,
+                           line_stride, outer_stride, n, wts);
+    else
+        hipLaunchKernelGGL((k_if_lines<T, TB, R, S, false>), grid, dim3(256), lds, s, in, out, nlines, len, stride,
+                           line_stride, outer_stride, n, wts);
 }
 
 template <typename T>

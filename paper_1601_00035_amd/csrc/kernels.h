@@ -54,7 +54,10 @@ struct ColPass {
     int outer_period;
     double scale;
 };
-int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s);
+// variant: 0 = default plan, 1 = more elements per thread (only where col_variants(L) > 1)
+int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, int variant = 0);
+int col_variants(int L);
+int col_variant_choice(int L, int dtype, int choice);
 
 // ---- LGF table (lgf_table.hip) ------------------------------------------------------------------
 // Host evaluation of g(n) with the same method as the device table builder.

@@ -129,9 +129,9 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
 }
 
 // ---------------------------------------------------------------------------------------------------
-template <typename T, int L, int MODE>
+template <typename T, int L, int MODE, int V = 0>
 __global__ void __launch_bounds__(512) k_col(ColPass a) {
-    using P = Plan1D<L>;
+    using P = PlanV<L, V>;
     constexpr int E = P::E, TP = L / E, TB = col_tb<T>(TP);
     using RF = typename P::Fwd;
     using RI = Reverse<RF>;
@@ -158,9 +158,9 @@ __global__ void __launch_bounds__(512) k_col(ColPass a) {
         }
     }
     if constexpr (MODE == COL_INV) {
-        fft_regs<T, L, true, RI>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, ColAcc<T, TB>, E>(v, t, tw, acc);
     } else {
-        fft_regs<T, L, false, RF>(v, t, tw, acc);
+        fft_regs<T, L, false, RF, ColAcc<T, TB>, E>(v, t, tw, acc);
     }
     if constexpr (MODE == COL_CONV) {
         constexpr int RLf = Last<RF>::value;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(512) k_col(ColPass a) {
                 v[b * RLf + r] = cscale<T>(v[b * RLf + r], k);
             }
         }
-        fft_regs<T, L, true, RI>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, ColAcc<T, TB>, E>(v, t, tw, acc);
     }
     using ROut = typename std::conditional<MODE == COL_FWD, RF, RI>::type;
     constexpr int RO = Last<ROut>::value;
@@ -272,14 +272,15 @@ template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s)
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
-template <typename T, int L, int MODE> static int do_col(const ColPass& a, hipStream_t s) {
-    constexpr int TP = L / Plan1D<L>::E, TB = col_tb<T>(TP);
+template <typename T, int L, int MODE, int V = 0> static int do_col(const ColPass& a, hipStream_t s) {
+    constexpr int TP = L / PlanV<L, V>::E, TB = col_tb<T>(TP);
+    static_assert(TB == col_tb<T>(L / Plan1D<L>::E), "plan variants must share the column-tile width");
     if (a.nouter > 65535 || a.ncomp > 65535) {
         set_error("column pass grid too large");
         return NSLGF_EINVAL;
     }
     dim3 grid(ceil_div(a.ncols, TB), a.nouter, a.ncomp);
-    hipLaunchKernelGGL((k_col<T, L, MODE>), grid, dim3(TB * TP), 0, s, a);
+    hipLaunchKernelGGL((k_col<T, L, MODE, V>), grid, dim3(TB * TP), 0, s, a);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
@@ -336,7 +337,19 @@ int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s) {
         case 512: return do_col<T, 512, MODE>(a, s);                                               \
     }
 
-template <typename T> static int col_dispatch(int L, ColMode mode, const ColPass& a, hipStream_t s) {
+template <typename T> static int col_dispatch(int L, ColMode mode, const ColPass& a, hipStream_t s, int variant) {
+    if (variant == 1) {
+        if (L == 512) {
+            if (mode == COL_FWD) return do_col<T, 512, COL_FWD, 1>(a, s);
+            if (mode == COL_INV) return do_col<T, 512, COL_INV, 1>(a, s);
+            return do_col<T, 512, COL_CONV, 1>(a, s);
+        }
+        if (L == 256) {
+            if (mode == COL_FWD) return do_col<T, 256, COL_FWD, 1>(a, s);
+            if (mode == COL_INV) return do_col<T, 256, COL_INV, 1>(a, s);
+            return do_col<T, 256, COL_CONV, 1>(a, s);
+        }
+    }
     if (mode == COL_FWD) {
         NSLGF_COL_SWITCH(T, COL_FWD)
     } else if (mode == COL_INV) {
@@ -348,8 +361,20 @@ template <typename T> static int col_dispatch(int L, ColMode mode, const ColPass
     return NSLGF_EUNSUPPORTED;
 }
 
-int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s) {
-    return dtype == NSLGF_F32 ? col_dispatch<float>(L, mode, a, s) : col_dispatch<double>(L, mode, a, s);
+int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, int variant) {
+    return dtype == NSLGF_F32 ? col_dispatch<float>(L, mode, a, s, variant)
+                              : col_dispatch<double>(L, mode, a, s, variant);
+}
+
+int col_variants(int L) { return (L == 512 || L == 256) ? 2 : 1; }
+
+// Column-pass plan per length and dtype: choice 0 or 1 forces the narrow or the wide plan wherever
+// both exist; -1 takes the default: wide in FP32 (its 32 complex floats per thread fit the register
+// file and save an LDS exchange per transform), narrow in FP64 (the wide plan spills there).
+int col_variant_choice(int L, int dtype, int choice) {
+    if (col_variants(L) < 2) return 0;
+    if (choice >= 0) return choice;
+    return dtype == NSLGF_F32 ? 1 : 0;
 }
 
 }  // namespace nslgf

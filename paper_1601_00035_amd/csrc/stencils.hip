@@ -39,21 +39,34 @@ __device__ __forceinline__ T curl_at(const Vec3<T>& f, int q, int i, int j, int 
 }
 
 // Ntilde(f) at face (i, j, k), all three components (Eq. opr_def_nonlin and its cyclic images).
+// The nine edge values of e = C f it needs (e1, e2, e3 at the cell and one step back along the
+// other axes) use 24 distinct face values, each loaded once: component (1) at offsets
+// (0,0,0), (0,0,+-1), (0,+-1,0), (-1,0,0), (-1,+1,0), (-1,0,+1) and the cyclic images for (2), (3).
 template <typename T>
 __device__ __forceinline__ void nonlinear_at(const Vec3<T>& f, int i, int j, int k, T idx, T out[3]) {
-    T n1 = 0, n2 = 0, n3 = 0;
-#pragma unroll
-    for (int q = -1; q <= 0; ++q) {
-        n1 += curl_at(f, 1, i, j, k + q, idx) * (f.c[2](i, j, k + q) + f.c[2](i + 1, j, k + q)) -
-              curl_at(f, 2, i, j + q, k, idx) * (f.c[1](i, j + q, k) + f.c[1](i + 1, j + q, k));
-        n2 += curl_at(f, 2, i + q, j, k, idx) * (f.c[0](i + q, j, k) + f.c[0](i + q, j + 1, k)) -
-              curl_at(f, 0, i, j, k + q, idx) * (f.c[2](i, j, k + q) + f.c[2](i, j + 1, k + q));
-        n3 += curl_at(f, 0, i, j + q, k, idx) * (f.c[1](i, j + q, k) + f.c[1](i, j + q, k + 1)) -
-              curl_at(f, 1, i + q, j, k, idx) * (f.c[0](i + q, j, k) + f.c[0](i + q, j, k + 1));
-    }
-    out[0] = (T)0.25 * n1;
-    out[1] = (T)0.25 * n2;
-    out[2] = (T)0.25 * n3;
+    const Fld<T>& F1 = f.c[0];
+    const Fld<T>& F2 = f.c[1];
+    const Fld<T>& F3 = f.c[2];
+    const T a000 = F1(i, j, k), a00p = F1(i, j, k + 1), a00m = F1(i, j, k - 1), a0p0 = F1(i, j + 1, k),
+            a0m0 = F1(i, j - 1, k), am00 = F1(i - 1, j, k), amp0 = F1(i - 1, j + 1, k), am0p = F1(i - 1, j, k + 1);
+    const T b000 = F2(i, j, k), bp00 = F2(i + 1, j, k), bm00 = F2(i - 1, j, k), b00p = F2(i, j, k + 1),
+            b00m = F2(i, j, k - 1), b0m0 = F2(i, j - 1, k), bpm0 = F2(i + 1, j - 1, k), b0mp = F2(i, j - 1, k + 1);
+    const T c000 = F3(i, j, k), cp00 = F3(i + 1, j, k), cm00 = F3(i - 1, j, k), c0p0 = F3(i, j + 1, k),
+            c0m0 = F3(i, j - 1, k), c00m = F3(i, j, k - 1), cp0m = F3(i + 1, j, k - 1), c0pm = F3(i, j + 1, k - 1);
+    // edge values: e1 at (i,j,k), (i,j,k-1), (i,j-1,k); e2 at (i,j,k), (i,j,k-1), (i-1,j,k);
+    // e3 at (i,j,k), (i,j-1,k), (i-1,j,k)
+    const T e1_0 = (b000 - b00p + c0p0 - c000) * idx;
+    const T e1_km = (b00m - b000 + c0pm - c00m) * idx;
+    const T e1_jm = (b0m0 - b0mp + c000 - c0m0) * idx;
+    const T e2_0 = (c000 - cp00 + a00p - a000) * idx;
+    const T e2_km = (c00m - cp0m + a000 - a00m) * idx;
+    const T e2_im = (cm00 - c000 + am0p - am00) * idx;
+    const T e3_0 = (a000 - a0p0 + bp00 - b000) * idx;
+    const T e3_jm = (a0m0 - a000 + bpm0 - b0m0) * idx;
+    const T e3_im = (am00 - amp0 + b000 - bm00) * idx;
+    out[0] = (T)0.25 * (e2_0 * (c000 + cp00) + e2_km * (c00m + cp0m) - e3_0 * (b000 + bp00) - e3_jm * (b0m0 + bpm0));
+    out[1] = (T)0.25 * (e3_0 * (a000 + a0p0) + e3_im * (am00 + amp0) - e1_0 * (c000 + c0p0) - e1_km * (c00m + c0pm));
+    out[2] = (T)0.25 * (e1_0 * (b000 + b00p) + e1_jm * (b0m0 + b0mp) - e2_0 * (a000 + a00p) - e2_im * (am00 + am0p));
 }
 
 #define NSLGF_CELL_INDEX                                                                           \

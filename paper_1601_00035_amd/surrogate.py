@@ -372,7 +372,8 @@ def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: 
     """Every `horizon` steps the surrogate proposes w_{k+h}; the plain FP64 step judges it from the
     same state (rel. max error of the vorticity) and the roll-out continues from the proposal if the
     error is within tol (velocity rebuilt by Vor2Vel), else from the plain result.  Returns per-block
-    errors, the persistence baseline (w_{k+h} ~ w_k) errors and timings."""
+    errors, two baselines (persistence w_{k+h} ~ w_k, and linear extrapolation of the first plain step
+    w_{k+h} ~ w_k + h (w_{k+1} - w_k)) and timings."""
     import workloads
 
     from . import HerkState, max_cell_speed, vor2vel
@@ -382,28 +383,35 @@ def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: 
     u = vor2vel(w0, dx)
     dt = cfl * dx / max_cell_speed(u)
     scale = 1.0 / float(vorticity(u, dx).abs().max())
-    out = {"err": [], "persistence_err": [], "accepted": [], "ms_surrogate": [], "ms_plain": []}
+    out = {"err": [], "persistence_err": [], "extrapolation_err": [], "accepted": [], "ms_surrogate": [],
+           "ms_plain": []}
     for _ in range(blocks):
         w_k = vorticity(u, dx)
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0, e1, e2, e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(5))
         e0.record()
         prop = propose(net, w_k, scale, re, gain)
         u_prop = vor2vel(prop, dx)
         e1.record()
         st = HerkState(u.clone(), dx, dt, re, "A", n_buf=n_buf)
-        for _ in range(horizon):
-            st.step()
+        st.step()
         e2.record()
+        w_1 = vorticity(st.u, dx)
+        e3.record()
+        for _ in range(horizon - 1):
+            st.step()
+        e4.record()
         torch.cuda.synchronize()
         w_ref = vorticity(st.u, dx)
         den = float(w_ref.abs().max())
         err = float((prop - w_ref).abs().max()) / den
         perr = float((w_k - w_ref).abs().max()) / den
+        xerr = float((w_k + horizon * (w_1 - w_k) - w_ref).abs().max()) / den
         ok = err <= tol
         out["err"].append(err)
         out["persistence_err"].append(perr)
+        out["extrapolation_err"].append(xerr)
         out["accepted"].append(ok)
         out["ms_surrogate"].append(e0.elapsed_time(e1))
-        out["ms_plain"].append(e1.elapsed_time(e2))
+        out["ms_plain"].append(e1.elapsed_time(e2) + e3.elapsed_time(e4))
         u = u_prop if ok else st.u
     return out

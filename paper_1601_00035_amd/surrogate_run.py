@@ -7,7 +7,8 @@ Data: `trajectories` perturbed rings (sigma/R ~ U[0.1, 0.3], Re ~ U[250, 1000], 
 dx = R/24 (n = 128) or dx = 2 (R + 5 sigma)/(n - 16) (smaller boxes), `steps` Scheme A steps each,
 every step's vorticity kept (trajectories x (steps + 1) snapshots).  Training: Adam on random
 (w_k, w_{k+h}) pairs.  Evaluation: judged roll-out on a held-out ring, against the persistence
-baseline w_{k+h} ~ w_k, with the plain FP64 step as judge and fallback.
+baseline w_{k+h} ~ w_k and the linear extrapolation of one plain step, with the plain FP64 step as
+judge and fallback.
 """
 from __future__ import annotations
 
@@ -76,7 +77,8 @@ def main(argv=None):
         "ms_per_train_iter": round(1e3 * train_s / max(1, a.iters), 3),
         "loss_first": losses[0][1], "loss_last": losses[-1][1],
         "eval": {"sigma": sig, "Re": re, "tol": a.tol, "rel_err": ro["err"], "persistence_rel_err": ro["persistence_err"],
-                 "error_reduction_vs_persistence": gain, "accepted": ro["accepted"],
+                 "error_reduction_vs_persistence": gain, "extrapolation_rel_err": ro["extrapolation_err"],
+                 "accepted": ro["accepted"],
                  "accept_rate": sum(ro["accepted"]) / len(ro["accepted"]),
                  "ms_surrogate_proposal": ro["ms_surrogate"], "ms_plain_horizon": ro["ms_plain"]},
     }

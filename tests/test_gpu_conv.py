@@ -98,6 +98,35 @@ def test_ring_vorticity_sampled(n, dtype, tol):
     assert not out[2].any()  # omega_z = 0 convolves to exactly 0
 
 
+@pytest.mark.parametrize("shape", [(200, 100, 9), (100, 250, 20)])
+def test_fft_plans_agree(shape):
+    """Both column-pass radix plans (narrow and wide) at padded lengths 256 and 512 along y and z,
+    with ragged column tiles, against direct sums at seeded sample points, and against each other."""
+    rng = np.random.default_rng(shape[0])
+    s = rng.standard_normal(shape)
+    dx = 0.21
+    nz, ny, nx = shape
+    flat = rng.choice(nz * ny * nx, size=48, replace=False)
+    tg = np.stack([flat // (ny * nx), (flat // nx) % ny, flat % nx], axis=1).astype(np.int64)
+    tg = np.concatenate([tg, np.array([[0, 0, 0], [nz - 1, ny - 1, nx - 1]])])
+    ref = native.lgf_direct_targets(s, dx, tg)
+    scale = np.abs(ref).max()
+    outs = {}
+    try:
+        for choice in (0, 1):
+            nslgf.set_fft_plan(choice)
+            for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
+                out = gpu_conv(s, dx, dtype)
+                got = out[tg[:, 0], tg[:, 1], tg[:, 2]]
+                assert np.abs(got - ref).max() < tol * scale, (choice, dtype, np.abs(got - ref).max() / scale)
+                outs[(choice, dtype)] = out
+    finally:
+        nslgf.set_fft_plan(-1)
+    assert rel(outs[(1, torch.float64)], outs[(0, torch.float64)]) < 1e-13
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.set_fft_plan(2)
+
+
 def test_invalid_arguments():
     t = torch.zeros((4, 4, 4), dtype=torch.float64, device=DEV)
     with pytest.raises(nslgf.NslgfError):
