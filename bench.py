@@ -43,20 +43,22 @@ def alg_bytes_per_step(N: int, P: int, es: int) -> dict:
     nh = P // 2 + 1
     ce = 2 * es
     C = 6  # scalar LGF solves per step: 3 (Vor2Vel) + 3 (pressure)
+    CL = 4  # convolution launches per step (one of three components, three of one); the spectrum is read once per launch
     return {
         "conv_x_r2c": C * (n3 * es + N * N * nh * ce),
         "conv_y_fwd": C * (N * N * nh * ce + N * P * nh * ce),
-        "conv_z_fused": C * (2 * N * P * nh * ce + nh ** 3 * es),
+        "conv_z_fused": C * 2 * N * P * nh * ce + CL * nh ** 3 * es,
         "conv_y_inv": C * (N * P * nh * ce + N * N * nh * ce),
         "conv_x_c2r": C * (N * N * nh * ce + n3 * es),
-        "if_x": 15 * 2 * n3 * es,
+        # 15 component-applications of the IF; the last stage's x pass also reads w^{2,1}, w^{2,2}
+        "if_x": (15 * 2 + 6) * n3 * es,
         "if_y": 15 * 2 * n3 * es,
         "if_z": 15 * 2 * n3 * es,
         "curl_bar": 6 * n3 * es,
         "stage_rhs": 30 * n3 * es,
         "stage_div": 12 * n3 * es,
         "stage_project": 36 * n3 * es,
-        "axpby": 14 * n3 * es,
+        "axpby": 2 * n3 * es,
     }
 
 
@@ -179,8 +181,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--fft-plan", type=int, default=-1, choices=(-1, 0, 1),
-                    help="column-pass FFT radix plan: -1 per-length default, 0 narrow, 1 wide")
+    ap.add_argument("--fft-plan", type=int, default=-1, choices=(-1, 0, 1, 2),
+                    help="column-pass FFT radix plan: -1 default, 0 narrow, 1 wide, 2 narrow on fewer elements")
     ap.add_argument("--calibrate", action="store_true",
                     help="first copy 1 GiB with the library's plain copy kernel (reference for byte counters)")
     args = ap.parse_args()

@@ -188,12 +188,15 @@ int max_cell_speed(nslgf_t h, const void *u, int nx, int ny, int nz, int dtype, 
  */
 int nslgf_profile_enable(nslgf_t h, int enable);
 /*
- * Radix plan of the strided (column) FFT passes of the convolution (Sec. 3.2's zero-padded FFT
- * convolution; the plan changes the order of rounding only).  choice = 0: the narrow plan
- * (fewer elements per thread, one LDS exchange per radix after the first); 1: the wide plan for
- * padded lengths 256 and 512 (16 or 32 elements per thread, radices 16 x 16 and 16 x 32, one LDS
- * exchange per transform); -1 (the default): wide in FP32, narrow in FP64.  Applies to plans built
- * after the call (plans are cached per box, dtype and choice).  NSLGF_EINVAL for other values.
+ * Radix plan of the strided (column) FFT passes of the convolution (Sec. 2.2's zero-padded FFT
+ * convolution; the plan changes the order of rounding only) for padded lengths 256 and 512:
+ *   0  narrow: 8 (length 256) or 16 (length 512) complex elements per thread, radix-4/8 passes,
+ *      an LDS exchange between passes;
+ *   1  wide: 16 or 32 elements per thread, radices 16 x 16 or 16 x 32, one exchange per transform;
+ *   2  (FP64 only) the narrow radices on 4 or 8 elements per thread;
+ *  -1  (the default) wide in FP32 and at length 256, 2 at length 512 in FP64.
+ * A variant that does not exist for a dtype falls back to the default.  Applies to plans built after
+ * the call (plans are cached per box, dtype and choice).  NSLGF_EINVAL outside -1 .. 2.
  */
 int nslgf_set_fft_plan(nslgf_t h, int choice);
 /* Plain streaming copy of n elements of dtype (device pointers, no overlap, n * size a multiple of

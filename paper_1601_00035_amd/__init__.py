@@ -220,8 +220,8 @@ def max_cell_speed(u: torch.Tensor) -> float:
 
 
 def set_fft_plan(choice: int, device: int | None = None):
-    """Column-pass FFT plan of convolution plans built from now on: -1 per-length default,
-    0 narrow, 1 wide (lengths 256 and 512)."""
+    """Column-pass FFT plan of convolution plans built from now on (lengths 256 and 512): -1 the
+    default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread (FP64)."""
     _check("nslgf_set_fft_plan", lib().nslgf_set_fft_plan(handle(device), int(choice)))
 
 

@@ -124,7 +124,7 @@ struct nslgf_ctx {
         for (auto e : batch_events) (void)hipEventDestroy(e);
         if (capture) (void)hipStreamDestroy(capture);
     }
-    int fft_plan = -1;  // column-pass plan choice: -1 per-length default, 0 narrow, 1 wide
+    int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
@@ -396,6 +396,28 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
     return NSLGF_OK;
 }
 
+// M E(alpha) M applied to the combination c0 p0 + c1 p1 + c2 p2 (formed in FP64, rounded once): the
+// combination is formed while the x pass loads its input, so it never makes a round trip through
+// memory; identity and runtime-radius cases combine first into dst.
+static int run_if_combined(nslgf_ctx* h, const IfCombine& cb, void* dst, int ncomp, int nx, int ny, int nz,
+                           double alpha, int dtype, hipStream_t s, void* t1, void* t2) {
+    const long long n = (long long)nx * ny * nz;
+    if (alpha != 0.0) {
+        double w[kIfMaxRadius + 1];
+        const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
+        if (r < 0) return NSLGF_EINVAL;
+        if (r >= 1 && r <= kIfFixedMaxRadius) {
+            NSLGF_PROF(h, "if_x", s, launch_if_x_combined(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
+            NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, t1, t2, ncomp, nx, ny, nz, w, r, s));
+            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t2, dst, ncomp, nx, ny, nz, w, r, s));
+            return NSLGF_OK;
+        }
+    }
+    NSLGF_PROF(h, "axpby", s,
+               launch_axpby(dtype, dst, cb.p[0], cb.c[0], cb.p[1], cb.c[1], cb.p[2], cb.c[2], ncomp * n, s));
+    return run_if(h, dst, dst, ncomp, nx, ny, nz, alpha, dtype, s, t1, t2);
+}
+
 static int run_if_shared(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha,
                          int dtype, hipStream_t s) {
     const size_t bytes = (size_t)ncomp * nx * ny * nz * dtype_size(dtype);
@@ -610,23 +632,30 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     } else {
         // final-stage form: r^3 = H^2 (q^2 + dt (a~31 w^{2,1} + a~32 w^{2,2})) + g^3
         const double a_prev = (ct[2] - ct[1]) * beta;
-        NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, r, q, 1.0, w1, dt * at[3][1], w2, dt * at[3][2], 3 * M, s));
-        NSLGF_TRY(run_if(h, r, r, 3, nx, ny, nz, a_prev, dt_, s, t1, t2));
+        const IfCombine cb{{q, w1, w2}, {1.0, dt * at[3][1], dt * at[3][2]}};
+        NSLGF_TRY(run_if_combined(h, cb, r, 3, nx, ny, nz, a_prev, dt_, s, t1, t2));
         c.c_q = 1.0;
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     }
     NSLGF_PROF(h, "stage_div", s, launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
     NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s, a1, a2));
+    // u^i = H^i (r^i - G dhat^i): with H^i = I (alpha = 0, e.g. the last stage of Schemes A and B) the
+    // projection writes u directly
+    void* proj = alpha == 0.0 ? st->u : r;
     if (stage == 1) {
-        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_project", s,
+                   launch_stage_project(dt_, r, proj, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz,
+                                        st->dx, s));
     } else if (stage == 2) {
-        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny, nz,
-                                       st->dx, s));
+        NSLGF_PROF(h, "stage_project", s,
+                   launch_stage_project(dt_, r, proj, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny,
+                                        nz, st->dx, s));
     } else {
-        NSLGF_PROF(h, "stage_project", s, launch_stage_project(dt_, r, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx, ny, nz,
-                                       st->dx, s));
+        NSLGF_PROF(h, "stage_project", s,
+                   launch_stage_project(dt_, r, proj, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx,
+                                        ny, nz, st->dx, s));
     }
-    NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s, t1, t2));
+    if (alpha != 0.0) NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s, t1, t2));
     if (stage == 3) {
         NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
         st->t += dt;
@@ -795,7 +824,7 @@ int nslgf_profile_enable(nslgf_t h, int enable) {
 
 int nslgf_set_fft_plan(nslgf_t h, int choice) {
     NSLGF_ENTER(h);
-    NSLGF_CHECK_ARG(choice >= -1 && choice <= 1, "nslgf_set_fft_plan: choice must be -1, 0 or 1");
+    NSLGF_CHECK_ARG(choice >= -1 && choice <= 2, "nslgf_set_fft_plan: choice must be -1, 0, 1 or 2");
     h->fft_plan = choice;
     return NSLGF_OK;
 }

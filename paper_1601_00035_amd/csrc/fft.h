@@ -54,18 +54,37 @@ NSLGF_FFT_PLAN(384, 24, 3, 2, 8, 8)
 NSLGF_FFT_PLAN(512, 16, 8, 8, 8)
 #undef NSLGF_FFT_PLAN
 
-// Alternative plans with more elements per thread (fewer LDS exchanges, lower occupancy); the
-// plan builder times both variants of a length on the device and keeps the faster one.
-template <int L, int V> struct PlanV : Plan1D<L> {};
+// Column-pass plan variants of lengths 256 and 512 (the plan builder picks one per length and dtype):
+//   V = 0  default plan of the length
+//   V = 1  wide: radices 16 x 16 or 16 x 32, one LDS exchange per transform
+//   V = 2  the default radices on fewer elements per thread (more waves per workgroup), with the
+//          register budget held to four waves per SIMD
+// `waves` is the minimum number of waves per SIMD the register allocation must allow.
+template <int L, int V> struct PlanV {
+    static constexpr int E = Plan1D<L>::E;
+    using Fwd = typename Plan1D<L>::Fwd;
+    static constexpr int waves = 1;
+};
 template <> struct PlanV<512, 1> {
     static constexpr int E = 32;
     using Fwd = RList<16, 32>;
+    static constexpr int waves = 1;
 };
 template <> struct PlanV<256, 1> {
     static constexpr int E = 16;
     using Fwd = RList<16, 16>;
+    static constexpr int waves = 1;
 };
-template <int L> constexpr bool has_variant() { return L == 512 || L == 256; }
+template <> struct PlanV<512, 2> {
+    static constexpr int E = 8;
+    using Fwd = RList<8, 8, 8>;
+    static constexpr int waves = 4;
+};
+template <> struct PlanV<256, 2> {
+    static constexpr int E = 4;
+    using Fwd = RList<4, 4, 4, 4>;
+    static constexpr int waves = 4;
+};
 
 // Columns per workgroup of the strided (column-tile) kernels: one 128-byte row segment at least,
 // and at least one wavefront per workgroup.

@@ -1,9 +1,8 @@
 // Integrating factor E(alpha) (Sec. 2.3): the kernel of the discrete heat semigroup is the product
 // of three 1D factors w[k] = e^{-2 alpha} I_k(2 alpha) (Appendix B, Eq. lgf_intfac), so
 // M E(alpha) M is applied as three masked 1D convolutions, one per axis, each reading its input
-// with zero extension outside the box.  Each pass stages whole lines in LDS so that every element
-// is read from and written to HBM once, with coalesced accesses (rows for x, tiles of adjacent
-// x-columns for y and z).
+// with zero extension outside the box.  Every pass reads and writes each element of HBM once with
+// coalesced accesses: rows through LDS for x, register windows over adjacent x-columns for y and z.
 #include <cmath>
 
 #include "kernels.h"
@@ -120,119 +119,116 @@ __global__ void __launch_bounds__(256) k_if_cols(const T* __restrict__ in, T* __
     }
 }
 
-// Fixed-radius variant for every axis: a workgroup owns TB lines (adjacent x-columns for the y and
-// z passes, rows for the x pass), staged in LDS as [position][line] with R zeros at both ends, so
-// that consecutive lanes touch consecutive lines (no bank conflicts) while each line's global
-// accesses stay contiguous across its threads.  Each thread then loads a window of S + 2R values of
-// its line into registers and produces S consecutive outputs with no bounds tests.
-// Line l of grid column group starts at comp * comp_stride + outer * outer_stride + l * line_stride
-// and its points are `stride` apart.
-template <typename T, int TB, int R, int S, bool CONTIG>
-__global__ void __launch_bounds__(256) k_if_lines(const T* __restrict__ in, T* __restrict__ out, int nlines, int len,
-                                                  long long stride, long long line_stride, long long outer_stride,
-                                                  long long comp_stride, IfWeights wts) {
+// Fixed-radius passes (radius R known at compile time).  Outputs are formed in one order on every
+// axis: w[0] v[k] + sum_{d = 1..R} w[d] (v[k - d] + v[k + d]), accumulated in FP64, with v = 0
+// outside the box.  Input and output must not overlap.
+//
+// x pass: a workgroup stages `rpb` whole rows (components are consecutive rows too) in LDS in their
+// natural order with R zeros at both ends of each row; global reads and writes are contiguous and
+// consecutive lanes read consecutive LDS words (no bank conflicts).
+struct IfTerms {  // optional extra input terms of the x pass: v = c0 in + c1 in1 + c2 in2
+    const void* in1;
+    const void* in2;
+    double c0, c1, c2;
+};
+
+template <typename T, int R, bool COMB>
+__global__ void __launch_bounds__(256) k_if_x(const T* __restrict__ in, T* __restrict__ out, long long nrows, int len,
+                                              int rpb, IfWeights wts, IfTerms terms) {
     extern __shared__ unsigned char smem[];
-    T* lds = (T*)smem;  // [TPC * S + 2R][TB]
-    constexpr int TPC = 256 / TB;
-    constexpr int ROWS = TPC * S + 2 * R;
-    const int c = threadIdx.x % TB;
-    const int t = threadIdx.x / TB;
-    const int line = blockIdx.x * TB + c;
-    const bool valid = line < nlines;
-    const long long base =
-        blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride + (valid ? (long long)line * line_stride : 0);
-    if (CONTIG) {
-        // lines are contiguous rows: global accesses run along the row (coalesced), LDS keeps [k][c]
-        for (int k = t; k < ROWS; k += TPC) lds[k * TB + c] = (T)0;
-        __syncthreads();
-        const long long base0 = blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride;
-        for (int e = threadIdx.x; e < TB * len; e += 256) {
-            const int cc = e / len, kk = e - cc * len;
-            const int ln = blockIdx.x * TB + cc;
-            if (ln < nlines) lds[(kk + R) * TB + cc] = in[base0 + (long long)ln * line_stride + kk];
+    T* lds = (T*)smem;  // [rpb][len + 2R]
+    const int W = len + 2 * R;
+    const long long row0 = (long long)blockIdx.x * rpb;
+    const int nr = (int)min((long long)rpb, nrows - row0);
+    const int cnt = nr * len;
+    const T* src = in + row0 * len;
+    T* dst = out + row0 * len;
+    for (int e = threadIdx.x; e < nr * 2 * R; e += 256) {
+        const int r = e / (2 * R), h = e - r * (2 * R);
+        lds[r * W + (h < R ? h : len + h)] = (T)0;
+    }
+    if constexpr (COMB) {
+        const T* s1 = (const T*)terms.in1 + row0 * len;
+        const T* s2 = terms.in2 ? (const T*)terms.in2 + row0 * len : nullptr;
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            const int r = e / len;
+            double v = terms.c0 * (double)src[e];
+            v += terms.c1 * (double)s1[e];
+            if (s2) v += terms.c2 * (double)s2[e];
+            lds[r * W + R + (e - r * len)] = (T)v;
         }
     } else {
-        for (int k = t; k < ROWS; k += TPC) {
-            const int kk = k - R;
-            lds[k * TB + c] = (valid && kk >= 0 && kk < len) ? in[base + kk * stride] : (T)0;
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            const int r = e / len;
+            lds[r * W + R + (e - r * len)] = src[e];
         }
     }
     __syncthreads();
-    const bool active = valid && t * S < len;
+    for (int e = threadIdx.x; e < cnt; e += 256) {
+        const int r = e / len;
+        const T* p = lds + r * W + R + (e - r * len);
+        double acc = wts.w[0] * (double)p[0];
+#pragma unroll
+        for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(p[-d] + p[d]);
+        dst[e] = (T)acc;
+    }
+}
+
+// y and z passes: a thread owns one x position (consecutive lanes take consecutive x, so every load
+// and store of a wavefront is one contiguous row segment) and S consecutive outputs of its line; the
+// S + 2R inputs go straight from memory into registers (neighbouring segments re-read their shared
+// halo through the caches, not from HBM).  No LDS and no barriers.
+template <typename T, int R, int S>
+__global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T* __restrict__ out, int nx, int len,
+                                                    long long stride, int nouter, long long outer_stride,
+                                                    long long comp_stride, IfWeights wts) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int k0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * S;
+    if (x >= nx || k0 >= len) return;
+    const int o = blockIdx.z % nouter, comp = blockIdx.z / nouter;
+    const long long base = comp * comp_stride + (long long)o * outer_stride + x;
     T v[S + 2 * R];
-    T res[S];
-    if (active) {
 #pragma unroll
-        for (int j = 0; j < S + 2 * R; ++j) v[j] = lds[(t * S + j) * TB + c];
+    for (int j = 0; j < S + 2 * R; ++j) {
+        const int k = k0 - R + j;
+        v[j] = (k >= 0 && k < len) ? in[base + (long long)k * stride] : (T)0;
+    }
 #pragma unroll
-        for (int m = 0; m < S; ++m) {
+    for (int m = 0; m < S; ++m) {
+        if (k0 + m < len) {
             double acc = wts.w[0] * (double)v[m + R];
 #pragma unroll
             for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
-            res[m] = (T)acc;
-        }
-    }
-    if (CONTIG) {
-        __syncthreads();  // every window has been read: reuse the buffer for the outputs
-        if (active) {
-#pragma unroll
-            for (int m = 0; m < S; ++m) lds[(t * S + m) * TB + c] = res[m];
-        }
-        __syncthreads();
-        const long long base0 = blockIdx.z * comp_stride + (long long)blockIdx.y * outer_stride;
-        for (int e = threadIdx.x; e < TB * len; e += 256) {
-            const int cc = e / len, kk = e - cc * len;
-            const int ln = blockIdx.x * TB + cc;
-            if (ln < nlines) out[base0 + (long long)ln * line_stride + kk] = lds[kk * TB + cc];
-        }
-    } else if (active) {
-#pragma unroll
-        for (int m = 0; m < S; ++m) {
-            const int k = t * S + m;
-            if (k < len) out[base + k * stride] = res[m];
+            out[base + (long long)(k0 + m) * stride] = (T)acc;
         }
     }
 }
 
+constexpr int kIfSegment = 32;  // outputs per thread of the strided passes
+
 template <typename T, int R>
 static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
-                         hipStream_t s) {
+                         hipStream_t s, const IfTerms* terms = nullptr) {
     const long long n = (long long)nx * ny * nz;
-    constexpr int TB = (int)(128 / sizeof(T));
-    constexpr int TPC = 256 / TB;
-    constexpr int S = 256 / TPC;  // the longest line (256 points) split over the threads of a line
-    const size_t lds = (size_t)(TPC * S + 2 * R) * TB * sizeof(T);
-    int nlines, len, nouter;
-    long long stride, line_stride, outer_stride;
-    if (axis == 0) {  // rows: lines are (y, z) rows of nx points
-        nlines = ny * nz;
-        len = nx;
-        stride = 1;
-        line_stride = nx;
-        nouter = 1;
-        outer_stride = 0;
-    } else if (axis == 1) {  // lines along y: x-columns of each z-plane
-        nlines = nx;
-        len = ny;
-        stride = nx;
-        line_stride = 1;
-        nouter = nz;
-        outer_stride = (long long)nx * ny;
-    } else {  // lines along z: x-columns of each y-row
-        nlines = nx;
-        len = nz;
-        stride = (long long)nx * ny;
-        line_stride = 1;
-        nouter = ny;
-        outer_stride = nx;
+    if (axis == 0) {
+        const long long nrows = (long long)ncomp * ny * nz;
+        const int rpb = nx + 2 * R >= 2048 ? 1 : 2048 / (nx + 2 * R);  // at most 2048 LDS elements
+        const size_t lds = (size_t)rpb * (nx + 2 * R) * sizeof(T);
+        const dim3 grid((unsigned)ceil_div(nrows, rpb));
+        if (terms)
+            hipLaunchKernelGGL((k_if_x<T, R, true>), grid, dim3(256), lds, s, in, out, nrows, nx, rpb, wts, *terms);
+        else
+            hipLaunchKernelGGL((k_if_x<T, R, false>), grid, dim3(256), lds, s, in, out, nrows, nx, rpb, wts,
+                               IfTerms{});
+        return;
     }
-    dim3 grid(ceil_div(nlines, TB), nouter, ncomp);
-    if (axis == 0)
-        hipLaunchKernelGGL((k_if_lines<T, TB, R, S, true>), grid, dim3(256), lds, s, in, out, nlines, len, stride,
-                           line_stride, outer_stride, n, wts);
-    else
-        hipLaunchKernelGGL((k_if_lines<T, TB, R, S, false>), grid, dim3(256), lds, s, in, out, nlines, len, stride,
-                           line_stride, outer_stride, n, wts);
+    const int len = axis == 1 ? ny : nz;
+    const long long stride = axis == 1 ? (long long)nx : (long long)nx * ny;
+    const int nouter = axis == 1 ? nz : ny;
+    const long long outer_stride = axis == 1 ? (long long)nx * ny : (long long)nx;
+    dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, kIfSegment), 4), nouter * ncomp);
+    hipLaunchKernelGGL((k_if_strided<T, R, kIfSegment>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
+                       outer_stride, n, wts);
 }
 
 template <typename T>
@@ -273,6 +269,34 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
     }
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
+}
+
+template <typename T>
+static int if_x_combined_t(const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
+                           int radius, hipStream_t s) {
+    IfWeights wts;
+    for (int k = 0; k <= kIfMaxRadius; ++k) wts.w[k] = k <= radius ? w[k] : 0.0;
+    const IfTerms terms{comb.p[1], comb.p[2], comb.c[0], comb.c[1], comb.c[2]};
+    const T* src = (const T*)comb.p[0];
+    T* dst = (T*)out;
+    switch (radius) {
+#define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(0, src, dst, ncomp, nx, ny, nz, wts, s, &terms); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
+        NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
+        NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
+#undef NSLGF_IF_R
+        default: break;
+    }
+    return NSLGF_EUNSUPPORTED;
+}
+
+int launch_if_x_combined(int dtype, const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz,
+                         const double* w, int radius, hipStream_t s) {
+    if (!comb.p[0] || !comb.p[1]) {
+        set_error("if_apply: a combined input needs at least two terms");
+        return NSLGF_EINVAL;
+    }
+    if (dtype == NSLGF_F32) return if_x_combined_t<float>(comb, out, ncomp, nx, ny, nz, w, radius, s);
+    return if_x_combined_t<double>(comb, out, ncomp, nx, ny, nz, w, radius, s);
 }
 
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz, const double* w,

@@ -54,9 +54,8 @@ struct ColPass {
     int outer_period;
     double scale;
 };
-// variant: 0 = default plan, 1 = more elements per thread (only where col_variants(L) > 1)
+// variant: plan variant of lengths 256 and 512 (0 = default; see PlanV and col_variant_choice)
 int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, int variant = 0);
-int col_variants(int L);
 int col_variant_choice(int L, int dtype, int choice);
 
 // ---- LGF table (lgf_table.hip) ------------------------------------------------------------------
@@ -74,8 +73,19 @@ int extract_spectrum(const void* spec, int Px, int Py, int Pz, long long XP, dou
 // Host: w[k] = e^{-2 alpha} I_k(2 alpha), k = 0..r (returns r, the truncation radius for the dtype).
 int if_weights(double alpha, int dtype, double* w, int wmax);
 constexpr int kIfMaxRadius = 63;
+constexpr int kIfFixedMaxRadius = 12;  // radii with compile-time passes (larger ones run the runtime-radius passes)
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz,
                    const double* w, int radius, hipStream_t s);
+// Linear combination of up to three fields read in place of a single input: c[0] p[0] + c[1] p[1] +
+// c[2] p[2] (null p[1], p[2] are skipped), formed in FP64 and rounded once to the dtype.
+struct IfCombine {
+    const void* p[3];
+    double c[3];
+};
+// The x pass with its input formed by `comb` on load, for radius 1 .. kIfFixedMaxRadius (else
+// NSLGF_EUNSUPPORTED, launching nothing).
+int launch_if_x_combined(int dtype, const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz,
+                         const double* w, int radius, hipStream_t s);
 
 // ---- stencils (stencils.hip) --------------------------------------------------------------------
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
@@ -95,10 +105,11 @@ int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, co
 // s = M_supp Dbar r
 int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, int ny, int nz, double dx,
                       hipStream_t s);
-// y = r - G dhat (in place into r); w_new = (y - base) * inv  where base = c_q q + c_w1 w1 + c_w2 w2 (optional)
-int launch_stage_project(int dtype, void* r, const void* dhat, const void* q, const void* w1, const void* w2,
-                         double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny, int nz,
-                         double dx, hipStream_t s);
+// rout = r - G dhat (rout may be r); w_new = (rout - base) * inv  where base = c_q q + c_w1 w1 + c_w2 w2
+// (optional)
+int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat, const void* q, const void* w1,
+                         const void* w2, double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny,
+                         int nz, double dx, hipStream_t s);
 // out = a*x + b*y + c*z (elementwise over n elements; y, z may be null)
 int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
                  long long n, hipStream_t s);

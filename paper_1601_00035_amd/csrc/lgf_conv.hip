@@ -130,22 +130,42 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
 
 // ---------------------------------------------------------------------------------------------------
 template <typename T, int L, int MODE, int V = 0>
-__global__ void __launch_bounds__(512) k_col(ColPass a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PlanV<L, V>::waves)))
+k_col(ColPass a) {
     using P = PlanV<L, V>;
     constexpr int E = P::E, TP = L / E, TB = col_tb<T>(TP);
     using RF = typename P::Fwd;
     using RI = Reverse<RF>;
+    static_assert(TB * TP <= 512, "column pass workgroup too large");
     constexpr int LD = col_lds_len<L>();
+    using Acc = ColAcc<T, TB>;
     __shared__ cplx<T> lds[TB * LD];
     const int tid = threadIdx.x;
     const int c = tid % TB, t = tid / TB;
-    const int col = blockIdx.x * TB + c;
+    int tile, outer, comp;
+    if constexpr (MODE == COL_CONV) {
+        // One-dimensional grid, remapped so that the workgroups sharing a spectrum tile (the mirrored
+        // outer indices ky and P - ky, every component) run on one XCD one after the other: the
+        // hardware hands workgroup b to XCD b mod 8, so XCD x takes the x-th contiguous chunk of the
+        // logical order below and the tile stays in that XCD's L2.
+        const int n = (int)gridDim.x, b = (int)blockIdx.x, x = b % 8;
+        const int lg = x * (n / 8) + min(x, n % 8) + b / 8;
+        comp = lg % a.ncomp;
+        const int rest = lg / a.ncomp;
+        const int sq = rest % a.nouter;
+        tile = rest / a.nouter;
+        outer = (sq & 1) ? a.nouter - 1 - (sq >> 1) : (sq >> 1);
+    } else {
+        tile = blockIdx.x;
+        outer = blockIdx.y;
+        comp = blockIdx.z;
+    }
+    const int col = tile * TB + c;
     const bool valid = col < a.ncols;
-    const int outer = blockIdx.y, comp = blockIdx.z;
     const cplx<T>* in = (const cplx<T>*)a.in + comp * a.in_comp + (long long)outer * a.in_outer + (valid ? col : 0);
     cplx<T>* out = (cplx<T>*)a.out + comp * a.out_comp + (long long)outer * a.out_outer + (valid ? col : 0);
     const cplx<T>* tw = (const cplx<T>*)a.tw;
-    ColAcc<T, TB> acc{lds, c};
+    Acc acc{lds, c};
     cplx<T> v[E];
     constexpr int R1 = (MODE == COL_INV) ? First<RI>::value : First<RF>::value;
 #pragma unroll
@@ -158,14 +178,14 @@ __global__ void __launch_bounds__(512) k_col(ColPass a) {
         }
     }
     if constexpr (MODE == COL_INV) {
-        fft_regs<T, L, true, RI, ColAcc<T, TB>, E>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
     } else {
-        fft_regs<T, L, false, RF, ColAcc<T, TB>, E>(v, t, tw, acc);
+        fft_regs<T, L, false, RF, Acc, E>(v, t, tw, acc);
     }
     if constexpr (MODE == COL_CONV) {
         constexpr int RLf = Last<RF>::value;
         const int kyf = min(outer, a.outer_period - outer);
-        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + blockIdx.x) * (L / 2 + 1) * TB + c;
+        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + tile) * (L / 2 + 1) * TB + c;
         const T sc = (T)a.scale;
 #pragma unroll
         for (int b = 0; b < E / RLf; ++b) {
@@ -178,7 +198,7 @@ __global__ void __launch_bounds__(512) k_col(ColPass a) {
                 v[b * RLf + r] = cscale<T>(v[b * RLf + r], k);
             }
         }
-        fft_regs<T, L, true, RI, ColAcc<T, TB>, E>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
     }
     using ROut = typename std::conditional<MODE == COL_FWD, RF, RI>::type;
     constexpr int RO = Last<ROut>::value;
@@ -280,6 +300,7 @@ template <typename T, int L, int MODE, int V = 0> static int do_col(const ColPas
         return NSLGF_EINVAL;
     }
     dim3 grid(ceil_div(a.ncols, TB), a.nouter, a.ncomp);
+    if (MODE == COL_CONV) grid = dim3(ceil_div(a.ncols, TB) * a.nouter * a.ncomp);
     hipLaunchKernelGGL((k_col<T, L, MODE, V>), grid, dim3(TB * TP), 0, s, a);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -337,18 +358,24 @@ int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s) {
         case 512: return do_col<T, 512, MODE>(a, s);                                               \
     }
 
+template <typename T, int L, int V> static int col_modes(ColMode mode, const ColPass& a, hipStream_t s) {
+    if (mode == COL_FWD) return do_col<T, L, COL_FWD, V>(a, s);
+    if (mode == COL_INV) return do_col<T, L, COL_INV, V>(a, s);
+    return do_col<T, L, COL_CONV, V>(a, s);
+}
+
+template <typename T, int L> static int col_variant(int variant, ColMode mode, const ColPass& a, hipStream_t s) {
+    if (variant == 1) return col_modes<T, L, 1>(mode, a, s);
+    if constexpr (sizeof(T) == 8) {  // 512-thread workgroups: double only (float tiles are twice as wide)
+        if (variant == 2) return col_modes<T, L, 2>(mode, a, s);
+    }
+    return col_modes<T, L, 0>(mode, a, s);
+}
+
 template <typename T> static int col_dispatch(int L, ColMode mode, const ColPass& a, hipStream_t s, int variant) {
-    if (variant == 1) {
-        if (L == 512) {
-            if (mode == COL_FWD) return do_col<T, 512, COL_FWD, 1>(a, s);
-            if (mode == COL_INV) return do_col<T, 512, COL_INV, 1>(a, s);
-            return do_col<T, 512, COL_CONV, 1>(a, s);
-        }
-        if (L == 256) {
-            if (mode == COL_FWD) return do_col<T, 256, COL_FWD, 1>(a, s);
-            if (mode == COL_INV) return do_col<T, 256, COL_INV, 1>(a, s);
-            return do_col<T, 256, COL_CONV, 1>(a, s);
-        }
+    if (variant > 0) {
+        if (L == 512) return col_variant<T, 512>(variant, mode, a, s);
+        if (L == 256) return col_variant<T, 256>(variant, mode, a, s);
     }
     if (mode == COL_FWD) {
         NSLGF_COL_SWITCH(T, COL_FWD)
@@ -366,15 +393,20 @@ int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, 
                               : col_dispatch<double>(L, mode, a, s, variant);
 }
 
-int col_variants(int L) { return (L == 512 || L == 256) ? 2 : 1; }
+static bool col_variant_valid(int L, int dtype, int v) {
+    if (L != 512 && L != 256) return v == 0;
+    return v == 0 || v == 1 || (v == 2 && dtype == NSLGF_F64);
+}
 
-// Column-pass plan per length and dtype: choice 0 or 1 forces the narrow or the wide plan wherever
-// both exist; -1 takes the default: wide in FP32 (its 32 complex floats per thread fit the register
-// file and save an LDS exchange per transform), narrow in FP64 (the wide plan spills there).
+// Column-pass plan per length and dtype: a valid choice >= 0 forces that variant; -1 (or a variant
+// that does not exist for the length and dtype) takes the default measured fastest on gfx950: wide
+// in FP32 and at length 256 in FP64; at length 512 in FP64 the wide plan spills its registers, and
+// the default radices on 8 elements per thread (twice the waves of the default) win.
 int col_variant_choice(int L, int dtype, int choice) {
-    if (col_variants(L) < 2) return 0;
-    if (choice >= 0) return choice;
-    return dtype == NSLGF_F32 ? 1 : 0;
+    if (choice >= 0 && col_variant_valid(L, dtype, choice)) return choice;
+    if (L != 512 && L != 256) return 0;
+    if (dtype == NSLGF_F32 || L == 256) return 1;
+    return 2;
 }
 
 }  // namespace nslgf

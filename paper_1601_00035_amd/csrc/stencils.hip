@@ -163,9 +163,9 @@ __global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1
 
 // y = r - G dhat (into r); if wnew: wnew = (y - (c_q q + c_w1 w1 + c_w2 w2)) * inv
 template <typename T>
-__global__ void __launch_bounds__(256) k_stage_project(T* r, const T* dhat, const T* q, const T* w1, const T* w2,
-                                                       double c_q, double c_w1, double c_w2, T* wnew, double inv,
-                                                       int nx, int ny, int nz, T idx_) {
+__global__ void __launch_bounds__(256) k_stage_project(const T* r, T* rout, const T* dhat, const T* q, const T* w1,
+                                                       const T* w2, double c_q, double c_w1, double c_w2, T* wnew,
+                                                       double inv, int nx, int ny, int nz, T idx_) {
     NSLGF_CELL_INDEX
     Fld<T> D{dhat, nx, ny, nz};
     const T d0 = D(i, j, k);
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_stage_project(T* r, const T* dhat, cons
     for (int a = 0; a < 3; ++a) {
         const long long p = a * n + idx;
         const T y = r[p] - g[a];
-        r[p] = y;
+        rout[p] = y;
         if (wnew) {
             double base = c_q * (double)q[p];
             if (w1) base += c_w1 * (double)w1[p];
@@ -293,17 +293,17 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
     return NSLGF_OK;
 }
 
-int launch_stage_project(int dtype, void* r, const void* dhat, const void* q, const void* w1, const void* w2,
-                         double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny, int nz,
-                         double dx, hipStream_t s) {
+int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat, const void* q, const void* w1,
+                         const void* w2, double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny,
+                         int nz, double dx, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_project<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (float*)r,
-                           (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
+        hipLaunchKernelGGL(k_stage_project<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)r,
+                           (float*)rout, (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
                            (float*)wnew, inv, nx, ny, nz, (float)(1.0 / dx));
     else
-        hipLaunchKernelGGL(k_stage_project<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (double*)r,
-                           (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
+        hipLaunchKernelGGL(k_stage_project<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)r,
+                           (double*)rout, (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
                            c_w2, (double*)wnew, inv, nx, ny, nz, 1.0 / dx);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;

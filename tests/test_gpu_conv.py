@@ -100,8 +100,9 @@ def test_ring_vorticity_sampled(n, dtype, tol):
 
 @pytest.mark.parametrize("shape", [(200, 100, 9), (100, 250, 20)])
 def test_fft_plans_agree(shape):
-    """Both column-pass radix plans (narrow and wide) at padded lengths 256 and 512 along y and z,
-    with ragged column tiles, against direct sums at seeded sample points, and against each other."""
+    """Every column-pass plan variant (narrow, wide, fewer elements per thread) at
+    padded lengths 256 and 512 along y and z, with ragged column tiles, against direct sums at seeded
+    sample points, and against each other."""
     rng = np.random.default_rng(shape[0])
     s = rng.standard_normal(shape)
     dx = 0.21
@@ -113,7 +114,7 @@ def test_fft_plans_agree(shape):
     scale = np.abs(ref).max()
     outs = {}
     try:
-        for choice in (0, 1):
+        for choice in (0, 1, 2):
             nslgf.set_fft_plan(choice)
             for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
                 out = gpu_conv(s, dx, dtype)
@@ -122,9 +123,10 @@ def test_fft_plans_agree(shape):
                 outs[(choice, dtype)] = out
     finally:
         nslgf.set_fft_plan(-1)
-    assert rel(outs[(1, torch.float64)], outs[(0, torch.float64)]) < 1e-13
+    for choice in (1, 2):
+        assert rel(outs[(choice, torch.float64)], outs[(0, torch.float64)]) < 1e-13, choice
     with pytest.raises(nslgf.NslgfError):
-        nslgf.set_fft_plan(2)
+        nslgf.set_fft_plan(3)
 
 
 def test_invalid_arguments():

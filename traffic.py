@@ -1,0 +1,123 @@
+"""HBM traffic of the benchmark's dominant kernel from two rocprofv3 counter runs.
+
+    cd /tmp && export TMPDIR=/tmp
+    rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o f -- \\
+        python3 -u $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-secondary --calibrate
+    rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o w -- \\
+        python3 -u $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-secondary --calibrate
+    python3 $R/traffic.py --fetch $R/gpurun_out/pmc_fetch --write $R/gpurun_out/pmc_write
+
+`--calibrate` makes the benchmark first copy 1 GiB with the library's plain copy kernel; the ratio
+of 1 GiB to what each counter reads for that copy scales the counter values of the other kernels
+(FETCH_SIZE and WRITE_SIZE count in KiB per dispatch).  The result goes to profiles/traffic.json
+together with the hash of the kernel sources it was taken on; bench.py reports it only while that
+hash matches.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import json
+import os
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+GIB = float(1 << 30)
+# the dominant kernel of the 256^3 FP64 step and the symbol of its HIP kernel
+KERNELS = {"conv_z_fused": "nslgf::k_col<double, 512, 2, 2>"}
+# launches of that kernel in one step, by number of components: Vor2Vel (3) and three pressure solves (1)
+STEP_MIX = {3: 1, 1: 3}
+
+
+def per_dispatch(run_dir: str, counter: str):
+    """{dispatch: (kernel name, grid size, value)} of one counter from a rocprofv3 --pmc output folder
+    (the rocpd SQLite database, or counter_collection.csv files)."""
+    vals = collections.OrderedDict()
+
+    def add(key, name, grid, v):
+        old = vals.get(key, (name, int(grid), 0.0))
+        vals[key] = (old[0], old[1], old[2] + float(v))
+
+    for f in glob.glob(os.path.join(run_dir, "**", "*_results.db"), recursive=True):
+        con = sqlite3.connect(f)
+        for did, name, grid, v in con.execute(
+                "select dispatch_id, kernel_name, grid_size, value from counters_collection where counter_name = ?",
+                (counter,)):
+            add((f, did), name, grid, v)
+        con.close()
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    add((f, r["Dispatch_Id"]), r["Kernel_Name"], r["Grid_Size"], r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} values under {run_dir}")
+    return vals
+
+
+def summarize(run_dir: str, counter: str):
+    """Calibration factor, and per kernel the counter in bytes per launch averaged over one step's
+    launch mix (dispatches grouped by grid size: a launch over c components has c times the grid)."""
+    vals = per_dispatch(run_dir, counter)
+    copies = [v for name, _, v in vals.values() if "k_copy" in name]
+    if not copies:
+        raise SystemExit(f"{run_dir}: no calibration copy (run bench.py with --calibrate)")
+    factor = GIB / (max(copies) * 1024.0)
+    out = {}
+    for key, sym in KERNELS.items():
+        groups = collections.defaultdict(list)
+        for name, grid, v in vals.values():
+            if sym in name:
+                groups[grid].append(v)
+        if not groups:
+            continue
+        g1 = min(groups)
+        by_comp = {grid // g1: sum(v) / len(v) * 1024.0 * factor for grid, v in groups.items()}
+        if not all(c in by_comp for c in STEP_MIX):
+            raise SystemExit(f"{key}: launches over {sorted(by_comp)} components, expected {sorted(STEP_MIX)}")
+        per_launch = sum(STEP_MIX[c] * by_comp[c] for c in STEP_MIX) / sum(STEP_MIX.values())
+        out[key] = {"dispatches": sum(len(v) for v in groups.values()), "bytes_avg": per_launch,
+                    "bytes_by_components": {str(c): int(b) for c, b in sorted(by_comp.items())}}
+    return factor, out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    a = ap.parse_args()
+    import bench
+
+    ff, fk = summarize(a.fetch, "FETCH_SIZE")
+    wf, wk = summarize(a.write, "WRITE_SIZE")
+    kernels = {}
+    for key in KERNELS:
+        if key in fk and key in wk:
+            kernels[key] = {"bytes_per_launch": int(fk[key]["bytes_avg"] + wk[key]["bytes_avg"]),
+                            "read_bytes_per_launch": int(fk[key]["bytes_avg"]),
+                            "write_bytes_per_launch": int(wk[key]["bytes_avg"]),
+                            "read_bytes_by_components": fk[key]["bytes_by_components"],
+                            "write_bytes_by_components": wk[key]["bytes_by_components"],
+                            "step_mix_components": {str(c): m for c, m in STEP_MIX.items()},
+                            "dispatches": fk[key]["dispatches"]}
+    rec = {"workload": "ns_lgf_step_256_ring_fp64", "source_hash": bench.kernel_source_hash(),
+           "calibration": {"FETCH_SIZE_factor": round(ff, 4), "WRITE_SIZE_factor": round(wf, 4),
+                           "copy_bytes": int(GIB)},
+           "kernels": kernels,
+           "command": ["rocprofv3 --pmc FETCH_SIZE -- python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline "
+                       "--no-secondary --calibrate",
+                       "rocprofv3 --pmc WRITE_SIZE -- python3 -u bench.py --steps 2 --warmup 1 --no-cpu-baseline "
+                       "--no-secondary --calibrate"]}
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
