@@ -390,6 +390,12 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
     double w[kIfMaxRadius + 1];
     const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
     if (r < 0) return NSLGF_EINVAL;
+    if (r >= 1 && r <= kIfFixedMaxRadius) {
+        const IfCombine cb{{src, nullptr, nullptr}, {1.0, 0.0, 0.0}};
+        NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
+        NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s));
+        return NSLGF_OK;
+    }
     NSLGF_PROF(h, "if_x", s, launch_if_axis(0, dtype, src, t1, ncomp, nx, ny, nz, w, r, s));
     NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, t1, t2, ncomp, nx, ny, nz, w, r, s));
     NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t2, dst, ncomp, nx, ny, nz, w, r, s));
@@ -397,8 +403,8 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
 }
 
 // M E(alpha) M applied to the combination c0 p0 + c1 p1 + c2 p2 (formed in FP64, rounded once): the
-// combination is formed while the x pass loads its input, so it never makes a round trip through
-// memory; identity and runtime-radius cases combine first into dst.
+// combination is formed while the fused x-y pass loads its input, so it never makes a round trip
+// through memory; identity and runtime-radius cases combine first into dst.
 static int run_if_combined(nslgf_ctx* h, const IfCombine& cb, void* dst, int ncomp, int nx, int ny, int nz,
                            double alpha, int dtype, hipStream_t s, void* t1, void* t2) {
     const long long n = (long long)nx * ny * nz;
@@ -407,9 +413,8 @@ static int run_if_combined(nslgf_ctx* h, const IfCombine& cb, void* dst, int nco
         const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
         if (r < 0) return NSLGF_EINVAL;
         if (r >= 1 && r <= kIfFixedMaxRadius) {
-            NSLGF_PROF(h, "if_x", s, launch_if_x_combined(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
-            NSLGF_PROF(h, "if_y", s, launch_if_axis(1, dtype, t1, t2, ncomp, nx, ny, nz, w, r, s));
-            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t2, dst, ncomp, nx, ny, nz, w, r, s));
+            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
+            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s));
             return NSLGF_OK;
         }
     }

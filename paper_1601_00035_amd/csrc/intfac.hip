@@ -123,54 +123,104 @@ __global__ void __launch_bounds__(256) k_if_cols(const T* __restrict__ in, T* __
 // axis: w[0] v[k] + sum_{d = 1..R} w[d] (v[k - d] + v[k + d]), accumulated in FP64, with v = 0
 // outside the box.  Input and output must not overlap.
 //
-// x pass: a workgroup stages `rpb` whole rows (components are consecutive rows too) in LDS in their
-// natural order with R zeros at both ends of each row; global reads and writes are contiguous and
-// consecutive lanes read consecutive LDS words (no bank conflicts).
-struct IfTerms {  // optional extra input terms of the x pass: v = c0 in + c1 in1 + c2 in2
+struct IfTerms {  // optional extra input terms of the fused x-y pass: v = c0 in + c1 in1 + c2 in2
     const void* in1;
     const void* in2;
     double c0, c1, c2;
 };
 
-template <typename T, int R, bool COMB>
-__global__ void __launch_bounds__(256) k_if_x(const T* __restrict__ in, T* __restrict__ out, long long nrows, int len,
-                                              int rpb, IfWeights wts, IfTerms terms) {
-    extern __shared__ unsigned char smem[];
-    T* lds = (T*)smem;  // [rpb][len + 2R]
-    const int W = len + 2 * R;
-    const long long row0 = (long long)blockIdx.x * rpb;
-    const int nr = (int)min((long long)rpb, nrows - row0);
-    const int cnt = nr * len;
-    const T* src = in + row0 * len;
-    T* dst = out + row0 * len;
-    for (int e = threadIdx.x; e < nr * 2 * R; e += 256) {
-        const int r = e / (2 * R), h = e - r * (2 * R);
-        lds[r * W + (h < R ? h : len + h)] = (T)0;
-    }
-    if constexpr (COMB) {
-        const T* s1 = (const T*)terms.in1 + row0 * len;
-        const T* s2 = terms.in2 ? (const T*)terms.in2 + row0 * len : nullptr;
-        for (int e = threadIdx.x; e < cnt; e += 256) {
-            const int r = e / len;
-            double v = terms.c0 * (double)src[e];
-            v += terms.c1 * (double)s1[e];
-            if (s2) v += terms.c2 * (double)s2[e];
-            lds[r * W + R + (e - r * len)] = (T)v;
-        }
-    } else {
-        for (int e = threadIdx.x; e < cnt; e += 256) {
-            const int r = e / len;
-            lds[r * W + R + (e - r * len)] = src[e];
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += 256) {
-        const int r = e / len;
-        const T* p = lds + r * W + R + (e - r * len);
-        double acc = wts.w[0] * (double)p[0];
+// Fused x and y passes (fixed radius R): a workgroup owns one (component, z) plane and S consecutive
+// output rows y0 .. y0 + S - 1, one thread per x (nx <= 256).  It walks the rows from y0 - R upwards,
+// RB rows per step: each thread holds the raw values of the next P steps in registers (loads issued
+// P steps ahead), the step's rows go through a double-buffered LDS tile with R zeros at both ends of
+// each row (one barrier per step), each x-filtered value is rounded to the dtype and pushed into a
+// register window of the last 2R + RB rows, and every row whose 2R + 1 neighbours are in the window
+// is y-filtered and stored.  The values are the ones the separate x and y passes produce (same order
+// of operations and roundings) without the intermediate field making a round trip through HBM.
+// With COMB the raw value is the combination c0 in + c1 in1 + c2 in2, formed in FP64 and rounded once.
+// Workgroups are numbered so that all row blocks of one plane run on one XCD (the hardware hands
+// workgroup b to XCD b mod 8) and share their halo rows through its L2.
+template <typename T, int R, int S, int RB, int P, bool COMB>
+__global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz,
+                                               int ntiles, IfWeights wts, IfTerms terms) {
+    constexpr int W = 256 + 2 * R;  // LDS row length
+    constexpr int NSTEP = (S + 2 * R + RB - 1) / RB;
+    constexpr int NW = 2 * R + RB;  // register window (x-filtered rows)
+    __shared__ T tile_lds[2][RB][W];
+    const int nb = (int)gridDim.x, b = (int)blockIdx.x, xcd = b % 8;
+    const int lg = xcd * (nb / 8) + min(xcd, nb % 8) + b / 8;
+    const int tile = lg % ntiles, plane = lg / ntiles;  // plane = comp * nz + z
+    const int x = threadIdx.x;
+    const bool act = x < nx;
+    const long long pbase = (long long)plane * nx * ny;
+    const int y0 = tile * S, ylo = y0 - R;
+    if (threadIdx.x < 2 * R) {
+        const int h = threadIdx.x < R ? threadIdx.x : nx + threadIdx.x;
 #pragma unroll
-        for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(p[-d] + p[d]);
-        dst[e] = (T)acc;
+        for (int i = 0; i < RB; ++i) {
+            tile_lds[0][i][h] = (T)0;
+            tile_lds[1][i][h] = (T)0;
+        }
+    }
+    auto raw = [&](int y) -> T {
+        if (!act || y < 0 || y >= ny) return (T)0;
+        const long long e = pbase + (long long)y * nx + x;
+        if constexpr (COMB) {
+            double v = terms.c0 * (double)in[e];
+            v += terms.c1 * (double)((const T*)terms.in1)[e];
+            if (terms.in2) v += terms.c2 * (double)((const T*)terms.in2)[e];
+            return (T)v;
+        } else {
+            return in[e];
+        }
+    };
+    T q[P][RB];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) q[j][i] = raw(ylo + j * RB + i);
+    T win[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) win[i] = (T)0;
+    for (int ks = 0; ks < NSTEP; ++ks) {
+        T (*lt)[W] = tile_lds[ks & 1];
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i) lt[i][R + x] = q[0][i];
+        }
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j)
+#pragma unroll
+            for (int i = 0; i < RB; ++i) q[j][i] = q[j + 1][i];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) q[P - 1][i] = raw(ylo + (ks + P) * RB + i);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) win[i] = win[i + RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            T xf = (T)0;
+            if (act) {
+                const T* p = &lt[i][R + x];
+                double acc = wts.w[0] * (double)p[0];
+#pragma unroll
+                for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(p[-d] + p[d]);
+                xf = (T)acc;
+            }
+            win[2 * R + i] = xf;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int kk = ks * RB + i;  // rows ylo .. ylo + kk are in; the row y = ylo + kk - R is complete
+            const int y = ylo + kk - R;
+            if (kk >= 2 * R && act && y < ny && y < y0 + S) {
+                const T* v = win + i;
+                double acc = wts.w[0] * (double)v[R];
+#pragma unroll
+                for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[R - d] + v[R + d]);
+                out[pbase + (long long)y * nx + x] = (T)acc;
+            }
+        }
     }
 }
 
@@ -206,22 +256,14 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
 
 constexpr int kIfSegment = 32;  // outputs per thread of the strided passes
 
+constexpr int kIfRowsPerBlock = 64;  // output rows per workgroup of the fused x-y pass
+constexpr int kIfRowsPerStep = 4;    // rows per barrier of the fused x-y pass
+constexpr int kIfPrefetch = 2;       // steps loaded ahead by the fused x-y pass
+
 template <typename T, int R>
 static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
-                         hipStream_t s, const IfTerms* terms = nullptr) {
+                         hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
-    if (axis == 0) {
-        const long long nrows = (long long)ncomp * ny * nz;
-        const int rpb = nx + 2 * R >= 2048 ? 1 : 2048 / (nx + 2 * R);  // at most 2048 LDS elements
-        const size_t lds = (size_t)rpb * (nx + 2 * R) * sizeof(T);
-        const dim3 grid((unsigned)ceil_div(nrows, rpb));
-        if (terms)
-            hipLaunchKernelGGL((k_if_x<T, R, true>), grid, dim3(256), lds, s, in, out, nrows, nx, rpb, wts, *terms);
-        else
-            hipLaunchKernelGGL((k_if_x<T, R, false>), grid, dim3(256), lds, s, in, out, nrows, nx, rpb, wts,
-                               IfTerms{});
-        return;
-    }
     const int len = axis == 1 ? ny : nz;
     const long long stride = axis == 1 ? (long long)nx : (long long)nx * ny;
     const int nouter = axis == 1 ? nz : ny;
@@ -229,6 +271,22 @@ static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int n
     dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, kIfSegment), 4), nouter * ncomp);
     hipLaunchKernelGGL((k_if_strided<T, R, kIfSegment>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
                        outer_stride, n, wts);
+}
+
+template <typename T, int R>
+static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
+                      hipStream_t s) {
+    const int ntiles = ceil_div(ny, kIfRowsPerBlock);
+    const dim3 grid((unsigned)((long long)ntiles * nz * ncomp));
+    const T* in = (const T*)cb.p[0];
+    if (cb.p[1]) {
+        const IfTerms terms{cb.p[1], cb.p[2], cb.c[0], cb.c[1], cb.c[2]};
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, true>), grid, dim3(256), 0, s, in, out, nx,
+                           ny, nz, ntiles, wts, terms);
+    } else {
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, false>), grid, dim3(256), 0, s, in, out, nx,
+                           ny, nz, ntiles, wts, IfTerms{});
+    }
 }
 
 template <typename T>
@@ -239,14 +297,16 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
     const long long n = (long long)nx * ny * nz;
     const T* src = (const T*)in;
     T* dst = (T*)out;
-    switch (radius) {
+    if (axis != 0) {
+        switch (radius) {
 #define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(axis, src, dst, ncomp, nx, ny, nz, wts, s); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
-        NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
-        NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
+            NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
+            NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
 #undef NSLGF_IF_R
-        default: break;
+            default: break;
+        }
     }
-    // larger radii: runtime-radius passes
+    // runtime-radius passes (every radius on x; radii above the fixed ones on y and z)
     if (axis == 0) {
         if (nx > kIfRowElems) {
             set_error("if_apply: rows longer than the LDS row buffer");
@@ -272,31 +332,34 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
 }
 
 template <typename T>
-static int if_x_combined_t(const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
-                           int radius, hipStream_t s) {
+static int if_xy_t(const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w, int radius,
+                   hipStream_t s) {
     IfWeights wts;
     for (int k = 0; k <= kIfMaxRadius; ++k) wts.w[k] = k <= radius ? w[k] : 0.0;
-    const IfTerms terms{comb.p[1], comb.p[2], comb.c[0], comb.c[1], comb.c[2]};
-    const T* src = (const T*)comb.p[0];
     T* dst = (T*)out;
     switch (radius) {
-#define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(0, src, dst, ncomp, nx, ny, nz, wts, s, &terms); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
+#define NSLGF_IF_R(R_) case R_: launch_xy<T, R_>(cb, dst, ncomp, nx, ny, nz, wts, s); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
         NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
         NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
 #undef NSLGF_IF_R
         default: break;
     }
+    set_error("if_apply: no fused x-y pass for this radius");
     return NSLGF_EUNSUPPORTED;
 }
 
-int launch_if_x_combined(int dtype, const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz,
-                         const double* w, int radius, hipStream_t s) {
-    if (!comb.p[0] || !comb.p[1]) {
-        set_error("if_apply: a combined input needs at least two terms");
+int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
+                 int radius, hipStream_t s) {
+    if (!cb.p[0] || (cb.p[2] && !cb.p[1])) {
+        set_error("if_apply: bad input combination");
         return NSLGF_EINVAL;
     }
-    if (dtype == NSLGF_F32) return if_x_combined_t<float>(comb, out, ncomp, nx, ny, nz, w, radius, s);
-    return if_x_combined_t<double>(comb, out, ncomp, nx, ny, nz, w, radius, s);
+    if (nx > 256) {
+        set_error("if_apply: the fused x-y pass needs nx <= 256");
+        return NSLGF_EUNSUPPORTED;
+    }
+    if (dtype == NSLGF_F32) return if_xy_t<float>(cb, out, ncomp, nx, ny, nz, w, radius, s);
+    return if_xy_t<double>(cb, out, ncomp, nx, ny, nz, w, radius, s);
 }
 
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz, const double* w,

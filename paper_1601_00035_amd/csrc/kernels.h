@@ -76,16 +76,16 @@ constexpr int kIfMaxRadius = 63;
 constexpr int kIfFixedMaxRadius = 12;  // radii with compile-time passes (larger ones run the runtime-radius passes)
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz,
                    const double* w, int radius, hipStream_t s);
-// Linear combination of up to three fields read in place of a single input: c[0] p[0] + c[1] p[1] +
-// c[2] p[2] (null p[1], p[2] are skipped), formed in FP64 and rounded once to the dtype.
+// Input of the fused x-y pass: c[0] p[0] + c[1] p[1] + c[2] p[2] (p[1], p[2] null: p[0] alone, c
+// ignored), formed in FP64 and rounded once to the dtype.
 struct IfCombine {
     const void* p[3];
     double c[3];
 };
-// The x pass with its input formed by `comb` on load, for radius 1 .. kIfFixedMaxRadius (else
-// NSLGF_EUNSUPPORTED, launching nothing).
-int launch_if_x_combined(int dtype, const IfCombine& comb, void* out, int ncomp, int nx, int ny, int nz,
-                         const double* w, int radius, hipStream_t s);
+// x and y passes in one launch (no intermediate field in HBM), for radius 1 .. kIfFixedMaxRadius and
+// nx <= 256 (else NSLGF_EUNSUPPORTED, launching nothing).  out must not overlap the inputs.
+int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
+                 int radius, hipStream_t s);
 
 // ---- stencils (stencils.hip) --------------------------------------------------------------------
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
