@@ -1,4 +1,5 @@
-"""HBM traffic of the benchmark's dominant kernel from two rocprofv3 counter runs.
+"""HBM traffic of the benchmark's dominant kernel from two rocprofv3 counter runs, and the kernel
+time summary of a rocprofv3 kernel trace.
 
     cd /tmp && export TMPDIR=/tmp
     rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o f -- \\
@@ -12,6 +13,13 @@ of 1 GiB to what each counter reads for that copy scales the counter values of t
 (FETCH_SIZE and WRITE_SIZE count in KiB per dispatch).  The result goes to profiles/traffic.json
 together with the hash of the kernel sources it was taken on; bench.py reports it only while that
 hash matches.
+
+    rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_step -o step -- \
+        python3 -u $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-secondary
+    python3 $R/traffic.py --trace $R/gpurun_out/prof_step > profiles/step256_fp64_kernel_trace.md
+
+prints per-kernel launch counts and durations, and for the dominant kernel the average launch
+duration over one step's launch mix (the figure bench.py measures with HIP events).
 """
 from __future__ import annotations
 
@@ -86,12 +94,60 @@ def summarize(run_dir: str, counter: str):
     return factor, out
 
 
+def trace_summary(run_dir: str, last: int) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace database; the dominant kernel's launch-mix
+    average is taken over its last `last` launches (the timed steps)."""
+    dbs = glob.glob(os.path.join(run_dir, "**", "*_results.db"), recursive=True)
+    if not dbs:
+        raise SystemExit(f"no *_results.db under {run_dir}")
+    rows = []
+    for f in dbs:
+        con = sqlite3.connect(f)
+        rows += con.execute("select name, duration, grid_x * grid_y * grid_z, dispatch_id from kernels "
+                            "order by dispatch_id").fetchall()
+        con.close()
+    per = collections.defaultdict(list)
+    for name, dur, grid, _ in rows:
+        per[name].append((float(dur), int(grid)))
+    total = sum(d for v in per.values() for d, _ in v)
+    out = ["| kernel | calls | total ms | avg ms | % |", "|---|---:|---:|---:|---:|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(d for d, _ in kv[1])):
+        t = sum(d for d, _ in v)
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {len(v)} | {t / 1e6:.3f} | {t / len(v) / 1e6:.4f} | {100 * t / total:.1f} |")
+    for key, sym in KERNELS.items():
+        groups = collections.defaultdict(list)
+        mine = [(d, g) for name, v in per.items() if sym in name for d, g in v]
+        for d, g in mine[-last:]:
+            groups[g].append(d)
+        if not groups:
+            continue
+        g1 = min(groups)
+        by_comp = {g // g1: sum(v) / len(v) for g, v in groups.items()}
+        if all(c in by_comp for c in STEP_MIX):
+            avg = sum(STEP_MIX[c] * by_comp[c] for c in STEP_MIX) / sum(STEP_MIX.values())
+            parts = ", ".join(f"{c} component(s): {by_comp[c] / 1e6:.4f} ms ({len(groups[c * g1])} launches)"
+                              for c in sorted(by_comp))
+            out.append("")
+            out.append(f"`{key}` (`{sym}`), last {last} launches (the timed steps): {parts}; "
+                       f"average over one step's launch mix "
+                       f"({', '.join(f'{m} x {c}' for c, m in STEP_MIX.items())}): {avg / 1e6:.4f} ms per launch.")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--trace", help="rocprofv3 --kernel-trace output folder: print the time summary instead")
+    ap.add_argument("--last", type=int, default=12, help="launches of the dominant kernel in the timed steps")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
+    if a.trace:
+        print(trace_summary(a.trace, a.last))
+        return
+    if not (a.fetch and a.write):
+        ap.error("--fetch and --write are required without --trace")
     import bench
 
     ff, fk = summarize(a.fetch, "FETCH_SIZE")
