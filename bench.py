@@ -295,9 +295,21 @@ def main():
         d = (y32.double() - y64)
         rel_l2 = (d.norm() / y64.norm()).item()
         rel_linf = (d.abs().max() / y64.abs().max()).item()
+        def solve_bytes(es):
+            # algorithmic bytes of one three-component solve: the five passes per component, the
+            # spectrum once
+            a = alg_bytes_per_step(N, P, es)
+            per_comp = sum(a[k] for k in ("conv_x_r2c", "conv_y_fwd", "conv_y_inv", "conv_x_c2r")) / 6
+            per_comp += 2 * N * P * (P // 2 + 1) * 2 * es
+            return 3 * per_comp + (P // 2 + 1) ** 3 * es
+
+        def rate(ms, es):
+            gbs = solve_bytes(es) / (ms * 1e-3) / 1e9
+            return {"alg_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
         secondary["lgf_solve_3comp"] = {
-            "fp64": {"ms": round(ms64, 4), "Mpts_per_s": round(3 * N ** 3 / (ms64 * 1e-3) / 1e6, 1)},
-            "fp32": {"ms": round(ms32, 4), "Mpts_per_s": round(3 * N ** 3 / (ms32 * 1e-3) / 1e6, 1),
+            "fp64": {"ms": round(ms64, 4), "Mpts_per_s": round(3 * N ** 3 / (ms64 * 1e-3) / 1e6, 1), **rate(ms64, 8)},
+            "fp32": {"ms": round(ms32, 4), "Mpts_per_s": round(3 * N ** 3 / (ms32 * 1e-3) / 1e6, 1), **rate(ms32, 4),
                      "rel_l2_vs_fp64": rel_l2, "rel_linf_vs_fp64": rel_linf},
         }
         del w32, y32, y64

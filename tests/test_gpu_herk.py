@@ -97,11 +97,13 @@ def test_stokes_case_gpu():
     assert rel(u.cpu().numpy(), expect) < 1e-7
 
 
-def test_step128_properties():
-    """The 128^3 step (Gaussian ring R = 1, sigma = 0.2, dx = 1/24, Re = 500, CFL 0.5, 1e-4
-    azimuthal perturbation): velocity divergence-free to rounding inside the support domain, the
+@pytest.mark.parametrize("case", ["step128", "conv256"])
+def test_full_size_step_properties(case):
+    """Full-size steps in the benchmark's configuration (FP64, Scheme A, n_buf 16): the 128^3 ring
+    (R = 1, sigma = 0.2, dx = 1/24, Re = 500, CFL 0.5, 1e-4 azimuthal perturbation) and the 256^3 ring
+    (sigma = 0.1, dx = 1/48).  Velocity divergence-free to rounding inside the support domain, the
     ring keeps moving in +z, and the step is finite."""
-    n, dx, ring, re, cfl = workloads.ring_case("step128")
+    n, dx, ring, re, cfl = workloads.ring_case(case)
     w = workloads.ring_edge_vorticity(n, dx, ring)
     wt = torch.from_numpy(w).to(DEV)
     u = nslgf.vor2vel(wt, dx)
