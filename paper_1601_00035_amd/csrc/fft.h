@@ -301,12 +301,17 @@ struct ColAcc {
 };
 template <int L> __host__ __device__ constexpr int col_lds_len() { return L + L / 16 + 1; }
 
-// LDS accessor of the row kernels: one contiguous (padded) segment per row.
+// LDS accessor of the row kernels: one contiguous segment per row, one pad element every 2^S
+// elements.  For complex doubles S = 3 spreads the strided stores of the radix-4 and radix-8 passes
+// (NS = 1 and 4) over distinct bank groups; complex floats keep S = 4.
+template <typename T> __host__ __device__ constexpr int row_pad_shift() { return sizeof(T) == 8 ? 3 : 4; }
 template <typename T>
 struct RowAcc {
     cplx<T>* base;
-    __device__ __forceinline__ cplx<T>& operator()(int pos) { return base[pos + (pos >> 4)]; }
+    __device__ __forceinline__ cplx<T>& operator()(int pos) { return base[pos + (pos >> row_pad_shift<T>())]; }
 };
-template <int L> __host__ __device__ constexpr int row_lds_len() { return L + 1 + (L + 1) / 16 + 1; }
+template <typename T, int L> __host__ __device__ constexpr int row_lds_len() {
+    return L + 1 + ((L + 1) >> row_pad_shift<T>()) + 1;
+}
 
 }  // namespace nslgf

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
     using RL = typename P::Fwd;
-    constexpr int LD = row_lds_len<LH>();
+    constexpr int LD = row_lds_len<T, LH>();
     __shared__ cplx<T> lds[RPW * LD];
     const int tid = threadIdx.x;
     const int rl = tid / TP, t = tid % TP;
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
     using RL = Reverse<typename P::Fwd>;
-    constexpr int LD = row_lds_len<LH>();
+    constexpr int LD = row_lds_len<T, LH>();
     __shared__ cplx<T> lds[RPW * LD];
     const int tid = threadIdx.x;
     const int rl = tid / TP, t = tid % TP;

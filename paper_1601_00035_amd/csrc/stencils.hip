@@ -9,11 +9,12 @@
 
 namespace nslgf {
 
+// Boxes have at most 256 points per axis, so a point's offset within one component fits 32 bits.
 template <typename T> struct Fld {
     const T* p;
     int nx, ny, nz;
     __device__ __forceinline__ T operator()(int i, int j, int k) const {
-        return (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) ? p[((long long)k * ny + j) * nx + i] : (T)0;
+        return (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) ? p[(k * ny + j) * nx + i] : (T)0;
     }
 };
 
@@ -69,13 +70,22 @@ __device__ __forceinline__ void nonlinear_at(const Vec3<T>& f, int i, int j, int
     out[2] = (T)0.25 * (e1_0 * (b000 + b00p) + e1_jm * (b0m0 + b0mp) - e2_0 * (a000 + a00p) - e2_im * (am00 + am0p));
 }
 
+// Point kernels run on (64 x 4)-thread blocks tiling (x, y), one z plane per grid z (no integer
+// division); launch with cell_grid / kCellBlock.  (Renumbering the blocks so that each XCD works
+// through a contiguous range of planes was measured slower for the stage kernels.)
 #define NSLGF_CELL_INDEX                                                                           \
     const long long n = (long long)nx * ny * nz;                                                   \
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;                        \
-    if (idx >= n) return;                                                                          \
-    const int i = (int)(idx % nx);                                                                 \
-    const int j = (int)((idx / nx) % ny);                                                          \
-    const int k = (int)(idx / ((long long)nx * ny));
+    const int i = (int)(blockIdx.x * 64 + threadIdx.x);                                            \
+    const int j = (int)(blockIdx.y * 4 + threadIdx.y);                                             \
+    const int kz_ = (int)blockIdx.z;                                                               \
+    const int k = kz_ % nz;                                                                        \
+    if (i >= nx || j >= ny) return;                                                                \
+    const long long idx = (long long)((k * ny + j) * nx + i);
+
+static const dim3 kCellBlock(64, 4);
+static dim3 cell_grid(int nx, int ny, int nz, int ncomp = 1) {
+    return dim3(ceil_div(nx, 64), ceil_div(ny, 4), nz * ncomp);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_grad(const T* c, T* f, int nx, int ny, int nz, T idx_) {
@@ -127,7 +137,7 @@ __global__ void __launch_bounds__(256) k_nonlinear(const T* f, T* out, int nx, i
 template <typename T>
 __global__ void __launch_bounds__(256) k_laplacian(const T* a, T* out, int nx, int ny, int nz, T idx2) {
     NSLGF_CELL_INDEX
-    const int comp = blockIdx.y;
+    const int comp = kz_ / nz;
     Fld<T> A{a + comp * n, nx, ny, nz};
     out[comp * n + idx] = (-(T)6 * A(i, j, k) + A(i + 1, j, k) + A(i - 1, j, k) + A(i, j + 1, k) + A(i, j - 1, k) +
                            A(i, j, k + 1) + A(i, j, k - 1)) * idx2;
@@ -242,7 +252,7 @@ template <typename T>
 static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     const T idx_ = (T)(1.0 / dx);
-    dim3 grid(ceil_div(n, 256)), block(256);
+    const dim3 grid = cell_grid(nx, ny, nz), block = kCellBlock;
     switch (op) {
         case NSLGF_OP_GRAD: hipLaunchKernelGGL(k_grad<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_DIV: hipLaunchKernelGGL(k_div<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
@@ -250,8 +260,8 @@ static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int 
         case NSLGF_OP_CURL_BAR: hipLaunchKernelGGL(k_curl_bar<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_NONLINEAR: hipLaunchKernelGGL(k_nonlinear<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_LAPLACIAN:
-            hipLaunchKernelGGL(k_laplacian<T>, dim3(ceil_div(n, 256), ncomp), block, 0, s, (const T*)src, (T*)dst, nx, ny,
-                               nz, (T)(1.0 / (dx * dx)));
+            hipLaunchKernelGGL(k_laplacian<T>, cell_grid(nx, ny, nz, ncomp), block, 0, s, (const T*)src, (T*)dst, nx,
+                               ny, nz, (T)(1.0 / (dx * dx)));
             break;
         default: set_error("stencil_apply: unknown operator"); return NSLGF_EINVAL;
     }
@@ -271,10 +281,10 @@ int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, co
     const int copy_q = c.copy_q;
     const StageCoef cc = c;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_rhs<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)u, (float*)q,
+        hipLaunchKernelGGL(k_stage_rhs<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)u, (float*)q,
                            (const float*)w1, (const float*)w2, (float*)r, (float)(1.0 / dx), cc, copy_q, nx, ny, nz);
     else
-        hipLaunchKernelGGL(k_stage_rhs<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)u, (double*)q,
+        hipLaunchKernelGGL(k_stage_rhs<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)u, (double*)q,
                            (const double*)w1, (const double*)w2, (double*)r, 1.0 / dx, cc, copy_q, nx, ny, nz);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -284,10 +294,10 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
                       hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_div<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)r, (float*)sdiv, nx,
+        hipLaunchKernelGGL(k_div<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)r, (float*)sdiv, nx,
                            ny, nz, (float)(1.0 / dx), nbuf);
     else
-        hipLaunchKernelGGL(k_div<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)r, (double*)sdiv, nx,
+        hipLaunchKernelGGL(k_div<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)r, (double*)sdiv, nx,
                            ny, nz, 1.0 / dx, nbuf);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -298,11 +308,11 @@ int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat,
                          int nz, double dx, hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_project<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const float*)r,
+        hipLaunchKernelGGL(k_stage_project<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)r,
                            (float*)rout, (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
                            (float*)wnew, inv, nx, ny, nz, (float)(1.0 / dx));
     else
-        hipLaunchKernelGGL(k_stage_project<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double*)r,
+        hipLaunchKernelGGL(k_stage_project<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)r,
                            (double*)rout, (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
                            c_w2, (double*)wnew, inv, nx, ny, nz, 1.0 / dx);
     NSLGF_LAUNCH_CHECK();
