@@ -194,11 +194,18 @@ int nslgf_profile_enable(nslgf_t h, int enable);
  *      an LDS exchange between passes;
  *   1  wide: 16 or 32 elements per thread, radices 16 x 16 or 16 x 32, one exchange per transform;
  *   2  (FP64 only) the narrow radices on 4 or 8 elements per thread;
- *  -1  (the default) wide in FP32 and at length 256, 2 at length 512 in FP64.
+ *  -1  (the default) wide in FP32 and at length 256, 2 at length 512 in FP64;
+ *  -2  (NSLGF_FFT_PLAN_AUTOTUNE) the autotuner: when a plan is built, every variant that exists for
+ *      its y and z lengths is timed on the device on the plan's own shapes and the fastest is kept
+ *      (the choice may differ between runs, so results may differ in the last bits).
  * A variant that does not exist for a dtype falls back to the default.  Applies to plans built after
- * the call (plans are cached per box, dtype and choice).  NSLGF_EINVAL outside -1 .. 2.
+ * the call (plans are cached per box, dtype and choice).  NSLGF_EINVAL outside -2 .. 2.
  */
+#define NSLGF_FFT_PLAN_AUTOTUNE (-2)
 int nslgf_set_fft_plan(nslgf_t h, int choice);
+/* The column-plan variants (y and z passes) of the plan for this box and dtype under the handle's
+ * current choice, building the plan (on `stream`) if needed; host outputs. */
+int nslgf_plan_info(nslgf_t h, int nx, int ny, int nz, int dtype, void *stream, int *vy, int *vz);
 /* Plain streaming copy of n elements of dtype (device pointers, no overlap, n * size a multiple of
  * 16 bytes, 16-byte aligned); the reference kernel whose hardware byte counters calibrate those of
  * the other kernels.  Profiled as "copy". */

@@ -67,6 +67,7 @@ def lib():
                     "max_cell_speed": [vp, vp, i, i, i, i, ctypes.POINTER(d), vp],
                     "nslgf_profile_enable": [vp, i],
                     "nslgf_set_fft_plan": [vp, i],
+                    "nslgf_plan_info": [vp, i, i, i, i, vp, ctypes.POINTER(i), ctypes.POINTER(i)],
                     "nslgf_profile_read": [vp, i, ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_longlong),
                                            ctypes.POINTER(d)],
                     "nslgf_copy": [vp, vp, vp, ctypes.c_size_t, i, vp],
@@ -219,10 +220,25 @@ def max_cell_speed(u: torch.Tensor) -> float:
     return out.value
 
 
+FFT_PLAN_AUTOTUNE = -2
+
+
 def set_fft_plan(choice: int, device: int | None = None):
     """Column-pass FFT plan of convolution plans built from now on (lengths 256 and 512): -1 the
-    default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread (FP64)."""
+    default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread (FP64), -2 autotune
+    (time every variant when a plan is built and keep the fastest)."""
     _check("nslgf_set_fft_plan", lib().nslgf_set_fft_plan(handle(device), int(choice)))
+
+
+def plan_info(nx: int, ny: int, nz: int, dtype=torch.float64, device: int | None = None) -> tuple:
+    """(y variant, z variant) of the convolution plan for this box and dtype (built if needed)."""
+    vy, vz = ctypes.c_int(), ctypes.c_int()
+    code = F64 if dtype == torch.float64 else F32
+    dev = torch.cuda.current_device() if device is None else device
+    s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check("nslgf_plan_info", lib().nslgf_plan_info(handle(dev), nx, ny, nz, code, s, ctypes.byref(vy),
+                                                    ctypes.byref(vz)))
+    return vy.value, vz.value
 
 
 def profile_enable(on: bool = True, device: int | None = None):

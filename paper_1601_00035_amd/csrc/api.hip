@@ -1,7 +1,7 @@
 // C-ABI of the library: handle lifecycle, per-box convolution plans (LGF spectrum, twiddles,
 // workspaces), the integrating factor, the IF-HERK stage driver and Vor2Vel.
-#include <cmath>
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <iterator>
 #include <map>
@@ -124,7 +124,7 @@ struct nslgf_ctx {
         for (auto e : batch_events) (void)hipEventDestroy(e);
         if (capture) (void)hipStreamDestroy(capture);
     }
-    int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, else a variant index
+    int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
@@ -200,6 +200,107 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
 static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** twh, const void** twf, const void** twy,
                          const void** twz);
 
+// Timing of one launch sequence: the minimum over `reps` runs (after one warm-up run) of the
+// event-to-event time on the stream, in milliseconds.
+template <class F> static int time_min_ms(hipStream_t s, int reps, F&& run, float* best) {
+    hipEvent_t a = nullptr, b = nullptr;
+    NSLGF_HIP_CHECK(hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        set_error("hipEventCreate failed");
+        return NSLGF_EHIP;
+    }
+    int rc = run();
+    *best = 3.4e38f;
+    for (int i = 0; rc == NSLGF_OK && i < reps; ++i) {
+        float ms = 0.f;
+        if (hipEventRecord(a, s) != hipSuccess) rc = NSLGF_EHIP;
+        if (rc == NSLGF_OK) rc = run();
+        if (rc == NSLGF_OK && (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                               hipEventElapsedTime(&ms, a, b) != hipSuccess))
+            rc = NSLGF_EHIP;
+        if (rc == NSLGF_OK) *best = std::min(*best, ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc == NSLGF_EHIP) set_error("autotune: event timing failed");
+    return rc;
+}
+
+// Autotuner of the column-pass plans: times every variant that exists for the plan's y and z lengths
+// on the plan's own shapes (one component, zero data, the workspaces of one solve) and keeps the
+// fastest for each.  Runs once per plan, before any capture.
+static int autotune_plan(nslgf_ctx* h, ConvPlan& p, hipStream_t s) {
+    const int dt = p.dtype;
+    const size_t es = dtype_size(dt);
+    DevBuf a1, a2;
+    NSLGF_TRY(a1.ensure((size_t)p.nz * p.ny * p.XP * 2 * es));
+    NSLGF_TRY(a2.ensure((size_t)p.nz * p.Py * p.XP * 2 * es));
+    NSLGF_HIP_CHECK(hipMemsetAsync(a1.p, 0, a1.bytes, s));
+    NSLGF_HIP_CHECK(hipMemsetAsync(a2.p, 0, a2.bytes, s));
+    const void *twy, *twz;
+    NSLGF_TRY(get_twiddles(h, p.Py, dt, &twy));
+    NSLGF_TRY(get_twiddles(h, p.Pz, dt, &twz));
+    ColPass y{};
+    y.ncols = p.Px / 2 + 1;
+    y.nouter = p.nz;
+    y.in_row = y.out_row = p.XP;
+    y.ncomp = 1;
+    y.tw = twy;
+    ColPass z{};
+    z.in = z.out = a2.p;
+    z.ncols = p.Px / 2 + 1;
+    z.nouter = p.Py;
+    z.in_outer = z.out_outer = p.XP;
+    z.in_row = z.out_row = (long long)p.Py * p.XP;
+    z.ncomp = 1;
+    z.n_in = z.n_out = p.nz;
+    z.tw = twz;
+    z.khat = p.khat.p;
+    z.khat_tiles = p.tiles;
+    z.outer_period = p.Py;
+    z.scale = 1.0;
+    float best = 3.4e38f;
+    for (int v = 0; v < kColVariants; ++v) {
+        if (!col_variant_valid(p.Pz, dt, v)) continue;
+        float ms = 0.f;
+        NSLGF_TRY(time_min_ms(s, 3, [&] { return launch_col(p.Pz, dt, COL_CONV, z, s, v); }, &ms));
+        if (ms < best) {
+            best = ms;
+            p.vz = v;
+        }
+    }
+    best = 3.4e38f;
+    for (int v = 0; v < kColVariants; ++v) {
+        if (!col_variant_valid(p.Py, dt, v)) continue;
+        float ms = 0.f;
+        auto run = [&] {
+            ColPass f = y, b = y;
+            f.in = a1.p;
+            f.out = a2.p;
+            f.in_outer = (long long)p.ny * p.XP;
+            f.out_outer = (long long)p.Py * p.XP;
+            f.n_in = p.ny;
+            f.n_out = p.Py;
+            b.in = a2.p;
+            b.out = a1.p;
+            b.in_outer = (long long)p.Py * p.XP;
+            b.out_outer = (long long)p.ny * p.XP;
+            b.n_in = p.Py;
+            b.n_out = p.ny;
+            const int rc = launch_col(p.Py, dt, COL_FWD, f, s, v);
+            return rc != NSLGF_OK ? rc : launch_col(p.Py, dt, COL_INV, b, s, v);
+        };
+        NSLGF_TRY(time_min_ms(s, 3, run, &ms));
+        if (ms < best) {
+            best = ms;
+            p.vy = v;
+        }
+    }
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    return NSLGF_OK;
+}
+
 static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, ConvPlan** out) {
     auto key = std::make_tuple(nx, ny, nz, dtype, h->fft_plan);
     auto it = h->plans.find(key);
@@ -268,6 +369,7 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
     NSLGF_TRY(p.khat.ensure(kbytes));
     NSLGF_TRY(extract_spectrum(spec.p, p.Px, p.Py, p.Pz, p.XP, 1.0 / (double)ktot, p.tb, p.tiles, dtype, p.khat.p, s));
     NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    if (h->fft_plan == NSLGF_FFT_PLAN_AUTOTUNE) NSLGF_TRY(autotune_plan(h, p, s));
     *out = plan.get();
     h->plans.emplace(key, std::move(plan));
     return NSLGF_OK;
@@ -829,8 +931,20 @@ int nslgf_profile_enable(nslgf_t h, int enable) {
 
 int nslgf_set_fft_plan(nslgf_t h, int choice) {
     NSLGF_ENTER(h);
-    NSLGF_CHECK_ARG(choice >= -1 && choice <= 2, "nslgf_set_fft_plan: choice must be -1, 0, 1 or 2");
+    NSLGF_CHECK_ARG(choice >= NSLGF_FFT_PLAN_AUTOTUNE && choice <= 2, "nslgf_set_fft_plan: choice must be -2 .. 2");
     h->fft_plan = choice;
+    return NSLGF_OK;
+}
+
+int nslgf_plan_info(nslgf_t h, int nx, int ny, int nz, int dtype, void* stream, int* vy, int* vz) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(vy && vz, "nslgf_plan_info: null output");
+    ConvPlan* p = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p));
+    *vy = p->vy;
+    *vz = p->vz;
     return NSLGF_OK;
 }
 

@@ -57,6 +57,8 @@ struct ColPass {
 // variant: plan variant of lengths 256 and 512 (0 = default; see PlanV and col_variant_choice)
 int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, int variant = 0);
 int col_variant_choice(int L, int dtype, int choice);
+constexpr int kColVariants = 3;  // variants 0 .. kColVariants - 1 (not all exist for every length and dtype)
+bool col_variant_valid(int L, int dtype, int v);
 
 // ---- LGF table (lgf_table.hip) ------------------------------------------------------------------
 // Host evaluation of g(n) with the same method as the device table builder.

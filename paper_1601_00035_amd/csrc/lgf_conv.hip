@@ -393,7 +393,7 @@ int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, 
                               : col_dispatch<double>(L, mode, a, s, variant);
 }
 
-static bool col_variant_valid(int L, int dtype, int v) {
+bool col_variant_valid(int L, int dtype, int v) {
     if (L != 512 && L != 256) return v == 0;
     return v == 0 || v == 1 || (v == 2 && dtype == NSLGF_F64);
 }

@@ -127,6 +127,30 @@ def test_fft_plans_agree(shape):
         assert rel(outs[(choice, torch.float64)], outs[(0, torch.float64)]) < 1e-13, choice
     with pytest.raises(nslgf.NslgfError):
         nslgf.set_fft_plan(3)
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.set_fft_plan(-3)
+
+
+def test_fft_plan_autotune():
+    """The autotuner picks existing variants for padded lengths 512 (z) and 256 (y), and its plan
+    matches the direct sum; plans of other choices are unaffected."""
+    shape = (200, 100, 9)
+    rng = np.random.default_rng(7)
+    s = rng.standard_normal(shape)
+    dx = 0.3
+    tg = np.array([[0, 0, 0], [199, 99, 8], [100, 50, 4], [13, 77, 2]], dtype=np.int64)
+    ref = native.lgf_direct_targets(s, dx, tg)
+    try:
+        nslgf.set_fft_plan(nslgf.FFT_PLAN_AUTOTUNE)
+        for dtype, tol, valid in ((torch.float64, 1e-12, (0, 1, 2)), (torch.float32, 1e-6, (0, 1))):
+            vy, vz = nslgf.plan_info(9, 100, 200, dtype)
+            assert vy in valid and vz in valid, (dtype, vy, vz)
+            out = gpu_conv(s, dx, dtype)
+            got = out[tg[:, 0], tg[:, 1], tg[:, 2]]
+            assert np.abs(got - ref).max() < tol * np.abs(ref).max()
+    finally:
+        nslgf.set_fft_plan(-1)
+    assert nslgf.plan_info(9, 100, 200, torch.float64) == (1, 2)  # the default table: wide at 256, 2 at 512
 
 
 def test_invalid_arguments():
