@@ -194,7 +194,7 @@ int nslgf_profile_enable(nslgf_t h, int enable);
  *      an LDS exchange between passes;
  *   1  wide: 16 or 32 elements per thread, radices 16 x 16 or 16 x 32, one exchange per transform;
  *   2  (FP64 only) the narrow radices on 4 or 8 elements per thread;
- *  -1  (the default) wide in FP32 and at length 256, 2 at length 512 in FP64;
+ *  -1  (the default) wide in FP32; in FP64 narrow at length 256 and 2 at length 512;
  *  -2  (NSLGF_FFT_PLAN_AUTOTUNE) the autotuner: when a plan is built, every variant that exists for
  *      its y and z lengths is timed on the device on the plan's own shapes and the fastest is kept
  *      (the choice may differ between runs, so results may differ in the last bits).

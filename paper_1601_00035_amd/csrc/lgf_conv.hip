@@ -164,7 +164,19 @@ k_col(ColPass a) {
     const bool valid = col < a.ncols;
     const cplx<T>* in = (const cplx<T>*)a.in + comp * a.in_comp + (long long)outer * a.in_outer + (valid ? col : 0);
     cplx<T>* out = (cplx<T>*)a.out + comp * a.out_comp + (long long)outer * a.out_outer + (valid ? col : 0);
-    const cplx<T>* tw = (const cplx<T>*)a.tw;
+    // The fused pass reads its twiddles from a copy of the root table in LDS, made once per
+    // workgroup (the barrier matters: composite radix-16/32 butterflies read the table already in
+    // the first pass); the single-transform passes read them through the caches, which measured
+    // faster there.
+    const cplx<T>* tw;
+    if constexpr (MODE == COL_CONV) {
+        __shared__ cplx<T> twl[L];
+        for (int m = tid; m < L; m += TB * TP) twl[m] = ((const cplx<T>*)a.tw)[m];
+        __syncthreads();
+        tw = twl;
+    } else {
+        tw = (const cplx<T>*)a.tw;
+    }
     Acc acc{lds, c};
     cplx<T> v[E];
     constexpr int R1 = (MODE == COL_INV) ? First<RI>::value : First<RF>::value;
@@ -177,27 +189,32 @@ k_col(ColPass a) {
             v[b * R1 + r] = (valid && row < a.n_in) ? in[(long long)row * a.in_row] : mk<T>((T)0, (T)0);
         }
     }
-    if constexpr (MODE == COL_INV) {
-        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
-    } else {
-        fft_regs<T, L, false, RF, Acc, E>(v, t, tw, acc);
-    }
+    // COL_CONV: the spectrum values this thread multiplies by are loaded now, behind the data loads,
+    // so that their latency overlaps the forward transform
+    constexpr int RLf = Last<RF>::value;
+    T kv[MODE == COL_CONV ? E : 1];
     if constexpr (MODE == COL_CONV) {
-        constexpr int RLf = Last<RF>::value;
         const int kyf = min(outer, a.outer_period - outer);
         const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + tile) * (L / 2 + 1) * TB + c;
-        const T sc = (T)a.scale;
 #pragma unroll
         for (int b = 0; b < E / RLf; ++b) {
             const int j = t + b * TP;
 #pragma unroll
             for (int r = 0; r < RLf; ++r) {
                 const int kz = j + r * (L / RLf);
-                const int kzf = min(kz, L - kz);
-                const T k = kh[kzf * TB] * sc;
-                v[b * RLf + r] = cscale<T>(v[b * RLf + r], k);
+                kv[b * RLf + r] = kh[min(kz, L - kz) * TB];
             }
         }
+    }
+    if constexpr (MODE == COL_INV) {
+        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
+    } else {
+        fft_regs<T, L, false, RF, Acc, E>(v, t, tw, acc);
+    }
+    if constexpr (MODE == COL_CONV) {
+        const T sc = (T)a.scale;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale<T>(v[e], kv[e] * sc);
         fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
     }
     using ROut = typename std::conditional<MODE == COL_FWD, RF, RI>::type;
@@ -400,13 +417,13 @@ bool col_variant_valid(int L, int dtype, int v) {
 
 // Column-pass plan per length and dtype: a valid choice >= 0 forces that variant; -1 (or a variant
 // that does not exist for the length and dtype) takes the default measured fastest on gfx950: wide
-// in FP32 and at length 256 in FP64; at length 512 in FP64 the wide plan spills its registers, and
-// the default radices on 8 elements per thread (twice the waves of the default) win.
+// in FP32; in FP64 the wide plan spills its registers at length 512, where the default radices on
+// 8 elements per thread (twice the waves of the default) win, and the default plan wins at 256.
 int col_variant_choice(int L, int dtype, int choice) {
     if (choice >= 0 && col_variant_valid(L, dtype, choice)) return choice;
     if (L != 512 && L != 256) return 0;
-    if (dtype == NSLGF_F32 || L == 256) return 1;
-    return 2;
+    if (dtype == NSLGF_F32) return 1;
+    return L == 512 ? 2 : 0;
 }
 
 }  // namespace nslgf

@@ -22,8 +22,9 @@ def _problem(n, seed, dtype):
 
 
 def test_batched_equals_unbatched_bitwise():
+    # 128^3 in FP32 and FP64 pads to 256, where the column passes use the wide and the narrow plan
     specs = [(24, 1, torch.float64), (32, 2, torch.float64), (20, 3, torch.float32), (28, 4, torch.float64),
-             (24, 5, torch.float32)]
+             (24, 5, torch.float32), (128, 6, torch.float32), (128, 7, torch.float64)]
     probs = [_problem(*s) for s in specs]
     solo = [nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2) for (u, dx, dt, re) in probs]
     batch = [nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2) for (u, dx, dt, re) in probs]

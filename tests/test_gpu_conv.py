@@ -131,6 +131,24 @@ def test_fft_plans_agree(shape):
         nslgf.set_fft_plan(-3)
 
 
+@pytest.mark.parametrize("choice", [-1, 0, 1, 2])
+def test_repeated_solves_bitwise(choice):
+    """Repeated solves of one source give bitwise equal results in every plan variant and dtype (no
+    order-dependent reduction and no race between the workgroup's threads), at padded lengths 256 and
+    512 along y and z."""
+    rng = np.random.default_rng(11)
+    s = torch.from_numpy(rng.standard_normal((2, 200, 100, 9))).to(DEV)
+    try:
+        nslgf.set_fft_plan(choice)
+        for dtype in (torch.float64, torch.float32):
+            src = s.to(dtype)
+            first = nslgf.lgf_convolve(src, 0.5)
+            for _ in range(4):
+                assert torch.equal(nslgf.lgf_convolve(src, 0.5), first), (choice, dtype)
+    finally:
+        nslgf.set_fft_plan(-1)
+
+
 def test_fft_plan_autotune():
     """The autotuner picks existing variants for padded lengths 512 (z) and 256 (y), and its plan
     matches the direct sum; plans of other choices are unaffected."""
@@ -150,7 +168,8 @@ def test_fft_plan_autotune():
             assert np.abs(got - ref).max() < tol * np.abs(ref).max()
     finally:
         nslgf.set_fft_plan(-1)
-    assert nslgf.plan_info(9, 100, 200, torch.float64) == (1, 2)  # the default table: wide at 256, 2 at 512
+    assert nslgf.plan_info(9, 100, 200, torch.float64) == (0, 2)  # the default table in FP64
+    assert nslgf.plan_info(9, 100, 200, torch.float32) == (1, 1)  # and in FP32
 
 
 def test_invalid_arguments():
