@@ -18,9 +18,25 @@ template <typename T> struct Fld {
     }
 };
 
+// The same field read without bounds tests, for points whose neighbours are all inside the box (the
+// tests would otherwise turn every load into a branch).
+template <typename T> struct FldIn {
+    const T* p;
+    int nx, ny, nz;
+    __device__ __forceinline__ T operator()(int i, int j, int k) const { return p[(k * ny + j) * nx + i]; }
+};
+
 template <typename T> struct Vec3 {
     Fld<T> c[3];
 };
+template <typename T> struct Vec3In {
+    FldIn<T> c[3];
+};
+template <typename T> __device__ __forceinline__ Vec3In<T> unchecked(const Vec3<T>& v) {
+    Vec3In<T> r;
+    for (int q = 0; q < 3; ++q) r.c[q] = FldIn<T>{v.c[q].p, v.c[q].nx, v.c[q].ny, v.c[q].nz};
+    return r;
+}
 
 template <typename T>
 __device__ __forceinline__ Vec3<T> vec3(const T* p, int nx, int ny, int nz) {
@@ -43,11 +59,11 @@ __device__ __forceinline__ T curl_at(const Vec3<T>& f, int q, int i, int j, int 
 // The nine edge values of e = C f it needs (e1, e2, e3 at the cell and one step back along the
 // other axes) use 24 distinct face values, each loaded once: component (1) at offsets
 // (0,0,0), (0,0,+-1), (0,+-1,0), (-1,0,0), (-1,+1,0), (-1,0,+1) and the cyclic images for (2), (3).
-template <typename T>
-__device__ __forceinline__ void nonlinear_at(const Vec3<T>& f, int i, int j, int k, T idx, T out[3]) {
-    const Fld<T>& F1 = f.c[0];
-    const Fld<T>& F2 = f.c[1];
-    const Fld<T>& F3 = f.c[2];
+template <typename T, class V>
+__device__ __forceinline__ void nonlinear_at(const V& f, int i, int j, int k, T idx, T out[3]) {
+    const auto& F1 = f.c[0];
+    const auto& F2 = f.c[1];
+    const auto& F3 = f.c[2];
     const T a000 = F1(i, j, k), a00p = F1(i, j, k + 1), a00m = F1(i, j, k - 1), a0p0 = F1(i, j + 1, k),
             a0m0 = F1(i, j - 1, k), am00 = F1(i - 1, j, k), amp0 = F1(i - 1, j + 1, k), am0p = F1(i - 1, j, k + 1);
     const T b000 = F2(i, j, k), bp00 = F2(i + 1, j, k), bm00 = F2(i - 1, j, k), b00p = F2(i, j, k + 1),
@@ -153,7 +169,12 @@ __global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1
     const bool in_soln = i >= c.nbuf && i < nx - c.nbuf && j >= c.nbuf && j < ny - c.nbuf && k >= c.nbuf &&
                          k < nz - c.nbuf;
     T nl[3] = {0, 0, 0};
-    if (in_soln) nonlinear_at(U, i, j, k, idx_, nl);
+    if (in_soln) {
+        if (i >= 1 && i < nx - 1 && j >= 1 && j < ny - 1 && k >= 1 && k < nz - 1)
+            nonlinear_at(unchecked(U), i, j, k, idx_, nl);
+        else
+            nonlinear_at(U, i, j, k, idx_, nl);
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const long long p = a * n + idx;
