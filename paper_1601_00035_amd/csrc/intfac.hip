@@ -238,14 +238,20 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
     const int o = blockIdx.z % nouter, comp = blockIdx.z / nouter;
     const long long base = comp * comp_stride + (long long)o * outer_stride + x;
     T v[S + 2 * R];
+    if (k0 >= R && k0 + S + R <= len) {  // the whole window inside the line: loads without tests
 #pragma unroll
-    for (int j = 0; j < S + 2 * R; ++j) {
-        const int k = k0 - R + j;
-        v[j] = (k >= 0 && k < len) ? in[base + (long long)k * stride] : (T)0;
+        for (int j = 0; j < S + 2 * R; ++j) v[j] = in[base + (long long)(k0 - R + j) * stride];
+    } else {
+#pragma unroll
+        for (int j = 0; j < S + 2 * R; ++j) {
+            const int k = k0 - R + j;
+            v[j] = (k >= 0 && k < len) ? in[base + (long long)k * stride] : (T)0;
+        }
     }
+    const bool full = k0 + S <= len;
 #pragma unroll
     for (int m = 0; m < S; ++m) {
-        if (k0 + m < len) {
+        if (full || k0 + m < len) {
             double acc = wts.w[0] * (double)v[m + R];
 #pragma unroll
             for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
