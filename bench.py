@@ -50,14 +50,15 @@ def alg_bytes_per_step(N: int, P: int, es: int) -> dict:
         "conv_z_fused": C * 2 * N * P * nh * ce + CL * nh ** 3 * es,
         "conv_y_inv": C * (N * P * nh * ce + N * N * nh * ce),
         "conv_x_c2r": C * (N * N * nh * ce + n3 * es),
-        # 15 component-applications of the IF (fused x-y pass, then z pass); the last stage's x-y
-        # pass also reads w^{2,1} and w^{2,2}
-        "if_xy": (15 * 2 + 6) * n3 * es,
+        # 15 component-applications of the IF (fused x-y pass, then z pass); the x-y pass of the last
+        # stage also reads w^{2,1} and w^{2,2}, those of stages 1 and 2 project on the way (reading
+        # dhat per component, q, and w^{2,1} in stage 2; writing w^{1,1} and w^{2,2})
+        "if_xy": (15 * 2 + 6 + 9 + 12) * n3 * es,
         "if_z": 15 * 2 * n3 * es,
         "curl_bar": 6 * n3 * es,
         "stage_rhs": 30 * n3 * es,
         "stage_div": 12 * n3 * es,
-        "stage_project": 36 * n3 * es,
+        "stage_project": 7 * n3 * es,  # the last stage only (H^3 = I): reads r, dhat, writes u
         "axpby": 2 * n3 * es,
     }
 

@@ -525,6 +525,31 @@ static int run_if_combined(nslgf_ctx* h, const IfCombine& cb, void* dst, int nco
     return run_if(h, dst, dst, ncomp, nx, ny, nz, alpha, dtype, s, t1, t2);
 }
 
+// u = M E(alpha) M (r - G dhat) with the stage's w update, the projection formed while the fused x-y
+// pass loads (r - G dhat never makes a round trip through memory); alpha = 0 or runtime radii project
+// first into r.
+static int run_if_projected(nslgf_ctx* h, void* r, const IfProject& pj, void* dst, int nx, int ny, int nz,
+                            double alpha, int dtype, double dx, hipStream_t s, void* t1, void* t2) {
+    if (alpha != 0.0) {
+        double w[kIfMaxRadius + 1];
+        const int rad = if_weights(alpha, dtype, w, kIfMaxRadius);
+        if (rad < 0) return NSLGF_EINVAL;
+        if (rad >= 1 && rad <= kIfFixedMaxRadius && nx <= 256) {
+            IfCombine cb{{r, nullptr, nullptr}, {1.0, 0.0, 0.0}};
+            cb.proj = &pj;
+            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, 3, nx, ny, nz, w, rad, s));
+            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, 3, nx, ny, nz, w, rad, s));
+            return NSLGF_OK;
+        }
+    }
+    void* proj_out = alpha == 0.0 ? dst : r;
+    NSLGF_PROF(h, "stage_project", s,
+               launch_stage_project(dtype, r, proj_out, pj.dhat, pj.q, pj.w1, nullptr, pj.c_q, pj.c_w1, 0.0, pj.wnew,
+                                    pj.inv, nx, ny, nz, dx, s));
+    if (alpha != 0.0) NSLGF_TRY(run_if(h, r, dst, 3, nx, ny, nz, alpha, dtype, s, t1, t2));
+    return NSLGF_OK;
+}
+
 static int run_if_shared(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha,
                          int dtype, hipStream_t s) {
     const size_t bytes = (size_t)ncomp * nx * ny * nz * dtype_size(dtype);
@@ -746,23 +771,24 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     }
     NSLGF_PROF(h, "stage_div", s, launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
     NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s, a1, a2));
-    // u^i = H^i (r^i - G dhat^i): with H^i = I (alpha = 0, e.g. the last stage of Schemes A and B) the
-    // projection writes u directly
-    void* proj = alpha == 0.0 ? st->u : r;
+    // u^i = H^i (r^i - G dhat^i) and w^{i,i} = (g^i - G dhat^i) / (a~_ii dt) = (r^i - G dhat^i - q^i -
+    // dt sum_j a~_ij w^{i,j}) / (a~_ii dt); the projection is applied while the IF loads (with H^i = I,
+    // e.g. the last stage of Schemes A and B, it writes u directly)
+    IfProject pj{dhat, 1.0 / st->dx, nullptr, nullptr, 0.0, 0.0, nullptr, 0.0};
     if (stage == 1) {
-        NSLGF_PROF(h, "stage_project", s,
-                   launch_stage_project(dt_, r, proj, dhat, q, nullptr, nullptr, 1.0, 0.0, 0.0, w1, inv, nx, ny, nz,
-                                        st->dx, s));
+        pj.q = q;
+        pj.c_q = 1.0;
+        pj.wnew = w1;
+        pj.inv = inv;
     } else if (stage == 2) {
-        NSLGF_PROF(h, "stage_project", s,
-                   launch_stage_project(dt_, r, proj, dhat, q, w1, nullptr, 1.0, dt * at[2][1], 0.0, w2, inv, nx, ny,
-                                        nz, st->dx, s));
-    } else {
-        NSLGF_PROF(h, "stage_project", s,
-                   launch_stage_project(dt_, r, proj, dhat, nullptr, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr, 0.0, nx,
-                                        ny, nz, st->dx, s));
+        pj.q = q;
+        pj.w1 = w1;
+        pj.c_q = 1.0;
+        pj.c_w1 = dt * at[2][1];
+        pj.wnew = w2;
+        pj.inv = inv;
     }
-    if (alpha != 0.0) NSLGF_TRY(run_if(h, r, st->u, 3, nx, ny, nz, alpha, dt_, s, t1, t2));
+    NSLGF_TRY(run_if_projected(h, r, pj, st->u, nx, ny, nz, alpha, dt_, st->dx, s, t1, t2));
     if (stage == 3) {
         NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
         st->t += dt;

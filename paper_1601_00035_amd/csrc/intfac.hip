@@ -123,10 +123,20 @@ __global__ void __launch_bounds__(256) k_if_cols(const T* __restrict__ in, T* __
 // axis: w[0] v[k] + sum_{d = 1..R} w[d] (v[k - d] + v[k + d]), accumulated in FP64, with v = 0
 // outside the box.  Input and output must not overlap.
 //
-struct IfTerms {  // optional extra input terms of the fused x-y pass: v = c0 in + c1 in1 + c2 in2
+// Input modes of the fused x-y pass.
+enum IfInput { IF_IN_PLAIN = 0, IF_IN_COMB = 1, IF_IN_PROJ = 2 };
+struct IfTerms {
+    // IF_IN_COMB: v = c0 in + c1 in1 + c2 in2
     const void* in1;
     const void* in2;
     double c0, c1, c2;
+    // IF_IN_PROJ: v = in - G dhat (component a of a 3-component field: the difference of dhat along axis
+    // a); wnew = (v - (c_q q + c_w1 w1)) inv where wnew is given
+    const void* dhat;
+    const void* q;
+    const void* w1;
+    void* wnew;
+    double idx, c_q, c_w1, inv;
 };
 
 // Fused x and y passes (fixed radius R): a workgroup owns one (component, z) plane and S consecutive
@@ -137,10 +147,13 @@ struct IfTerms {  // optional extra input terms of the fused x-y pass: v = c0 in
 // register window of the last 2R + RB rows, and every row whose 2R + 1 neighbours are in the window
 // is y-filtered and stored.  The values are the ones the separate x and y passes produce (same order
 // of operations and roundings) without the intermediate field making a round trip through HBM.
-// With COMB the raw value is the combination c0 in + c1 in1 + c2 in2, formed in FP64 and rounded once.
+// With IF_IN_COMB the raw value is the combination c0 in + c1 in1 + c2 in2, formed in FP64 and
+// rounded once; with IF_IN_PROJ it is the projection r - G dhat of the stage (in the order of
+// operations of the projection kernel), and the stage's new w is written on the way (each point by
+// the workgroup that owns its output row).
 // Workgroups are numbered so that all row blocks of one plane run on one XCD (the hardware hands
 // workgroup b to XCD b mod 8) and share their halo rows through its L2.
-template <typename T, int R, int S, int RB, int P, bool COMB>
+template <typename T, int R, int S, int RB, int P, int MODE>
 __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz,
                                                int ntiles, IfWeights wts, IfTerms terms) {
     constexpr int W = 256 + 2 * R;  // LDS row length
@@ -162,14 +175,34 @@ __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __re
             tile_lds[1][i][h] = (T)0;
         }
     }
+    const int comp = plane / nz, zpl = plane - comp * nz;
     auto raw = [&](int y) -> T {
         if (!act || y < 0 || y >= ny) return (T)0;
         const long long e = pbase + (long long)y * nx + x;
-        if constexpr (COMB) {
+        if constexpr (MODE == IF_IN_COMB) {
             double v = terms.c0 * (double)in[e];
             v += terms.c1 * (double)((const T*)terms.in1)[e];
             if (terms.in2) v += terms.c2 * (double)((const T*)terms.in2)[e];
             return (T)v;
+        } else if constexpr (MODE == IF_IN_PROJ) {
+            const T* D = (const T*)terms.dhat;
+            const long long c0 = ((long long)zpl * ny + y) * nx + x;  // offset within one component
+            const T d0 = D[c0];
+            T d1 = (T)0;
+            if (comp == 0) {
+                if (x + 1 < nx) d1 = D[c0 + 1];
+            } else if (comp == 1) {
+                if (y + 1 < ny) d1 = D[c0 + nx];
+            } else {
+                if (zpl + 1 < nz) d1 = D[c0 + (long long)nx * ny];
+            }
+            const T v = in[e] - (d1 - d0) * (T)terms.idx;
+            if (terms.wnew && y >= y0 && y < y0 + S) {
+                double base = terms.c_q * (double)((const T*)terms.q)[e];
+                if (terms.w1) base += terms.c_w1 * (double)((const T*)terms.w1)[e];
+                ((T*)terms.wnew)[e] = (T)(((double)v - base) * terms.inv);
+            }
+            return v;
         } else {
             return in[e];
         }
@@ -285,13 +318,30 @@ static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, in
     const int ntiles = ceil_div(ny, kIfRowsPerBlock);
     const dim3 grid((unsigned)((long long)ntiles * nz * ncomp));
     const T* in = (const T*)cb.p[0];
-    if (cb.p[1]) {
-        const IfTerms terms{cb.p[1], cb.p[2], cb.c[0], cb.c[1], cb.c[2]};
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, true>), grid, dim3(256), 0, s, in, out, nx,
-                           ny, nz, ntiles, wts, terms);
+    IfTerms terms{};
+    if (cb.proj) {
+        const IfProject& pj = *cb.proj;
+        terms.dhat = pj.dhat;
+        terms.q = pj.q;
+        terms.w1 = pj.w1;
+        terms.wnew = pj.wnew;
+        terms.idx = pj.idx;
+        terms.c_q = pj.c_q;
+        terms.c_w1 = pj.c_w1;
+        terms.inv = pj.inv;
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_PROJ>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, wts, terms);
+    } else if (cb.p[1]) {
+        terms.in1 = cb.p[1];
+        terms.in2 = cb.p[2];
+        terms.c0 = cb.c[0];
+        terms.c1 = cb.c[1];
+        terms.c2 = cb.c[2];
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_COMB>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, wts, terms);
     } else {
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, false>), grid, dim3(256), 0, s, in, out, nx,
-                           ny, nz, ntiles, wts, IfTerms{});
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_PLAIN>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, wts, terms);
     }
 }
 
@@ -356,7 +406,8 @@ static int if_xy_t(const IfCombine& cb, void* out, int ncomp, int nx, int ny, in
 
 int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
                  int radius, hipStream_t s) {
-    if (!cb.p[0] || (cb.p[2] && !cb.p[1])) {
+    if (!cb.p[0] || (cb.p[2] && !cb.p[1]) || (cb.proj && (cb.p[1] || ncomp != 3 || !cb.proj->dhat ||
+                                                          (cb.proj->wnew && !cb.proj->q)))) {
         set_error("if_apply: bad input combination");
         return NSLGF_EINVAL;
     }

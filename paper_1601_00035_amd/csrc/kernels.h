@@ -78,11 +78,24 @@ constexpr int kIfMaxRadius = 63;
 constexpr int kIfFixedMaxRadius = 12;  // radii with compile-time passes (larger ones run the runtime-radius passes)
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz,
                    const double* w, int radius, hipStream_t s);
+// Projection of an IF-HERK stage applied while the fused x-y pass loads (Sec. 3.2, Eq. ifherk_aux_1
+// and the w^{ii} update): the input is u = r - G dhat (r the 3-component p[0]), and where wnew is
+// given, wnew = (u - (c_q q + c_w1 w1)) inv is written too (w1 may be null).
+struct IfProject {
+    const void* dhat;
+    double idx;  // 1 / dx
+    const void* q;
+    const void* w1;
+    double c_q, c_w1;
+    void* wnew;
+    double inv;
+};
 // Input of the fused x-y pass: c[0] p[0] + c[1] p[1] + c[2] p[2] (p[1], p[2] null: p[0] alone, c
-// ignored), formed in FP64 and rounded once to the dtype.
+// ignored), formed in FP64 and rounded once to the dtype; or, with proj, the projection of p[0].
 struct IfCombine {
     const void* p[3];
     double c[3];
+    const IfProject* proj = nullptr;
 };
 // x and y passes in one launch (no intermediate field in HBM), for radius 1 .. kIfFixedMaxRadius and
 // nx <= 256 (else NSLGF_EUNSUPPORTED, launching nothing).  out must not overlap the inputs.

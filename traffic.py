@@ -36,10 +36,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 GIB = float(1 << 30)
-# the dominant kernel of the 256^3 FP64 step and the symbol of its HIP kernel
-KERNELS = {"conv_z_fused": "nslgf::k_col<double, 512, 2, 2>"}
-# launches of that kernel in one step, by number of components: Vor2Vel (3) and three pressure solves (1)
-STEP_MIX = {3: 1, 1: 3}
+# The kernels that can dominate the 256^3 FP64 step: their HIP symbols and how one step's launches
+# are averaged.  conv_z_fused runs over 3 components once (Vor2Vel) and over 1 component three times
+# (pressure); its dispatches are grouped by grid size (a launch over c components has c times the
+# grid) and weighted by that mix.  if_xy runs four different launches per step (and nowhere else), so
+# its dispatches are averaged as they come.
+KERNELS = {"conv_z_fused": "nslgf::k_col<double, 512, 2, 2>", "if_xy": "nslgf::k_if_xy<double,"}
+STEP_MIX = {"conv_z_fused": {3: 1, 1: 3}, "if_xy": None}
+
+
+def step_average(key, grids_values):
+    """(average per launch over one step, details) from [(grid size, value)] of one kernel."""
+    mix = STEP_MIX[key]
+    if mix is None:
+        vals = [v for _, v in grids_values]
+        return sum(vals) / len(vals), {"launches": len(vals)}
+    groups = collections.defaultdict(list)
+    for g, v in grids_values:
+        groups[g].append(v)
+    g1 = min(groups)
+    by_comp = {g // g1: sum(v) / len(v) for g, v in groups.items()}
+    if not all(c in by_comp for c in mix):
+        raise SystemExit(f"{key}: launches over {sorted(by_comp)} components, expected {sorted(mix)}")
+    avg = sum(mix[c] * by_comp[c] for c in mix) / sum(mix.values())
+    return avg, {"by_components": {str(c): by_comp[c] for c in sorted(by_comp)},
+                 "launches_by_components": {str(c): len(groups[c * g1]) for c in sorted(by_comp)},
+                 "step_mix_components": {str(c): m for c, m in mix.items()}}
 
 
 def per_dispatch(run_dir: str, counter: str):
@@ -78,19 +100,11 @@ def summarize(run_dir: str, counter: str):
     factor = GIB / (max(copies) * 1024.0)
     out = {}
     for key, sym in KERNELS.items():
-        groups = collections.defaultdict(list)
-        for name, grid, v in vals.values():
-            if sym in name:
-                groups[grid].append(v)
-        if not groups:
+        gv = [(grid, v * 1024.0 * factor) for name, grid, v in vals.values() if sym in name]
+        if not gv:
             continue
-        g1 = min(groups)
-        by_comp = {grid // g1: sum(v) / len(v) * 1024.0 * factor for grid, v in groups.items()}
-        if not all(c in by_comp for c in STEP_MIX):
-            raise SystemExit(f"{key}: launches over {sorted(by_comp)} components, expected {sorted(STEP_MIX)}")
-        per_launch = sum(STEP_MIX[c] * by_comp[c] for c in STEP_MIX) / sum(STEP_MIX.values())
-        out[key] = {"dispatches": sum(len(v) for v in groups.values()), "bytes_avg": per_launch,
-                    "bytes_by_components": {str(c): int(b) for c, b in sorted(by_comp.items())}}
+        avg, det = step_average(key, gv)
+        out[key] = {"dispatches": len(gv), "bytes_avg": avg, "detail": det}
     return factor, out
 
 
@@ -116,22 +130,17 @@ def trace_summary(run_dir: str, last: int) -> str:
         short = name.split("(")[0].replace("void ", "")
         out.append(f"| `{short}` | {len(v)} | {t / 1e6:.3f} | {t / len(v) / 1e6:.4f} | {100 * t / total:.1f} |")
     for key, sym in KERNELS.items():
-        groups = collections.defaultdict(list)
-        mine = [(d, g) for name, v in per.items() if sym in name for d, g in v]
-        for d, g in mine[-last:]:
-            groups[g].append(d)
-        if not groups:
+        mine = [(g, d) for name, v in per.items() if sym in name for d, g in v]
+        if not mine:
             continue
-        g1 = min(groups)
-        by_comp = {g // g1: sum(v) / len(v) for g, v in groups.items()}
-        if all(c in by_comp for c in STEP_MIX):
-            avg = sum(STEP_MIX[c] * by_comp[c] for c in STEP_MIX) / sum(STEP_MIX.values())
-            parts = ", ".join(f"{c} component(s): {by_comp[c] / 1e6:.4f} ms ({len(groups[c * g1])} launches)"
-                              for c in sorted(by_comp))
-            out.append("")
-            out.append(f"`{key}` (`{sym}`), last {last} launches (the timed steps): {parts}; "
-                       f"average over one step's launch mix "
-                       f"({', '.join(f'{m} x {c}' for c, m in STEP_MIX.items())}): {avg / 1e6:.4f} ms per launch.")
+        avg, det = step_average(key, mine[-last:])
+        parts = ""
+        if "by_components" in det:
+            parts = ", ".join(f"{c} component(s): {t / 1e6:.4f} ms ({det['launches_by_components'][c]} launches)"
+                              for c, t in det["by_components"].items()) + "; "
+        out.append("")
+        out.append(f"`{key}` (`{sym}`), last {last} launches (the timed steps): {parts}"
+                   f"average over one step's launches: {avg / 1e6:.4f} ms per launch.")
     return "\n".join(out)
 
 
@@ -158,9 +167,7 @@ def main():
             kernels[key] = {"bytes_per_launch": int(fk[key]["bytes_avg"] + wk[key]["bytes_avg"]),
                             "read_bytes_per_launch": int(fk[key]["bytes_avg"]),
                             "write_bytes_per_launch": int(wk[key]["bytes_avg"]),
-                            "read_bytes_by_components": fk[key]["bytes_by_components"],
-                            "write_bytes_by_components": wk[key]["bytes_by_components"],
-                            "step_mix_components": {str(c): m for c, m in STEP_MIX.items()},
+                            "read_detail": fk[key]["detail"], "write_detail": wk[key]["detail"],
                             "dispatches": fk[key]["dispatches"]}
     rec = {"workload": "ns_lgf_step_256_ring_fp64", "source_hash": bench.kernel_source_hash(),
            "calibration": {"FETCH_SIZE_factor": round(ff, 4), "WRITE_SIZE_factor": round(wf, 4),
