@@ -21,7 +21,9 @@
 namespace nslgf {
 
 // ---------------------------------------------------------------------------------------------------
-template <typename T, int LH>
+// PAIRS: the real rows are read as pairs (x[2n], x[2n+1]) with one vector load each (the host sets it
+// when the base is aligned, rows and components have even lengths, and n_io is even).
+template <typename T, int LH, bool PAIRS>
 __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
@@ -46,9 +48,13 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int m = 2 * (j + r * (LH / R1));  // z[n] = x[2n] + i x[2n+1]
-            const T re = (valid && m < a.n_io) ? in[m] : (T)0;
-            const T im = (valid && m + 1 < a.n_io) ? in[m + 1] : (T)0;
-            v[b * R1 + r] = mk<T>(re, im);
+            if constexpr (PAIRS) {
+                v[b * R1 + r] = (valid && m < a.n_io) ? *(const cplx<T>*)(in + m) : mk<T>((T)0, (T)0);
+            } else {
+                const T re = (valid && m < a.n_io) ? in[m] : (T)0;
+                const T im = (valid && m + 1 < a.n_io) ? in[m + 1] : (T)0;
+                v[b * R1 + r] = mk<T>(re, im);
+            }
         }
     }
     fft_regs<T, LH, false, RL>(v, t, twh, acc);
@@ -78,7 +84,8 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
     }
 }
 
-template <typename T, int LH>
+// PAIRS: the real outputs are written as pairs with one vector store each (conditions as for r2c).
+template <typename T, int LH, bool PAIRS>
 __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
@@ -121,8 +128,12 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
 #pragma unroll
             for (int r = 0; r < RLs; ++r) {
                 const int m = 2 * (j + r * (LH / RLs));
-                if (m < a.n_io) out[m] = v[b * RLs + r].x;
-                if (m + 1 < a.n_io) out[m + 1] = v[b * RLs + r].y;
+                if constexpr (PAIRS) {
+                    if (m < a.n_io) *(cplx<T>*)(out + m) = v[b * RLs + r];
+                } else {
+                    if (m < a.n_io) out[m] = v[b * RLs + r].x;
+                    if (m + 1 < a.n_io) out[m + 1] = v[b * RLs + r].y;
+                }
             }
         }
     }
@@ -295,17 +306,26 @@ int make_twiddles(int L, int dtype, void** dev_out) {
     return NSLGF_OK;
 }
 
+template <typename T> static bool real_pairs(const void* p, long long row, long long comp, int n_io) {
+    return ((uintptr_t)p % (2 * sizeof(T))) == 0 && row % 2 == 0 && comp % 2 == 0 && n_io % 2 == 0;
+}
 template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s) {
     constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
-    hipLaunchKernelGGL((k_row_r2c<T, LH>), grid, dim3(RPW * TP), 0, s, a);
+    if (real_pairs<T>(a.in, a.in_row, a.in_comp, a.n_io))
+        hipLaunchKernelGGL((k_row_r2c<T, LH, true>), grid, dim3(RPW * TP), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_row_r2c<T, LH, false>), grid, dim3(RPW * TP), 0, s, a);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
 template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s) {
     constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
-    hipLaunchKernelGGL((k_row_c2r<T, LH>), grid, dim3(RPW * TP), 0, s, a);
+    if (real_pairs<T>(a.out, a.out_row, a.out_comp, a.n_io))
+        hipLaunchKernelGGL((k_row_c2r<T, LH, true>), grid, dim3(RPW * TP), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_row_c2r<T, LH, false>), grid, dim3(RPW * TP), 0, s, a);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
