@@ -315,6 +315,36 @@ def main():
         }
         del w32, y32, y64
         torch.cuda.empty_cache()
+        # the whole step in FP32 (Vor2Vel + IF-HERK step from the same start as an FP64 step), its
+        # time and its deviation from the FP64 step
+        u0 = nslgf.vor2vel(w, dx)
+        s64 = nslgf.HerkState(u0.clone(), dx, dt, re, "A", n_buf=16)
+        s64.step()
+        w32 = w.float()
+        s32 = nslgf.HerkState(u0.float(), dx, dt, re, "A", n_buf=16)
+        s32.step()
+        diff = (s32.u.double() - s64.u)
+        step_err = {"rel_l2_vs_fp64": float(diff.norm() / s64.u.norm()),
+                    "rel_linf_vs_fp64": float(diff.abs().max() / s64.u.abs().max())}
+
+        def step32():
+            nslgf.vor2vel(w32, dx, out=s32.u)
+            s32.step()
+
+        step32()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(5):
+            step32()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms32s = e0.elapsed_time(e1) / 5
+        secondary["step_fp32"] = {"ms_per_step": round(ms32s, 4),
+                                  "Mpts_per_s": round(6 * N ** 3 / (ms32s * 1e-3) / 1e6, 1),
+                                  "speedup_vs_fp64": round(ms / ms32s, 3), **step_err}
+        del u0, s64, s32, w32, diff
+        torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
                                 "fp32": batched_measure(nslgf, torch, torch.float32)}

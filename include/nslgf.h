@@ -15,7 +15,9 @@
  *   (the mask operators of Sec. 4.1); every output is produced on the box only.
  * Memory.  All field pointers are DEVICE pointers (hipMalloc / torch CUDA tensors) on the
  *   handle's device, owned by the caller, 256-byte aligned, and must not alias unless a call says
- *   so.  The library owns its tables and workspaces (allocated lazily, freed by nslgf_destroy).
+ *   so.  The library owns its tables and workspaces (allocated lazily, freed by nslgf_destroy;
+ *   the plan of each box size, dtype and FFT-plan choice, with its spectrum and convolution
+ *   workspaces, stays cached for the handle's lifetime).
  * Precision.  dtype NSLGF_F64 (double) or NSLGF_F32 (float) for the field data.  Tables (the LGF,
  *   its spectrum, the integrating-factor weights) are always built in FP64; the FP32 path rounds
  *   them once.
