@@ -45,7 +45,8 @@ def alg_bytes_per_step(N: int, P: int, es: int) -> dict:
     C = 6  # scalar LGF solves per step: 3 (Vor2Vel) + 3 (pressure)
     CL = 4  # convolution launches per step (one of three components, three of one); the spectrum is read once per launch
     return {
-        "conv_x_r2c": C * (n3 * es + N * N * nh * ce),
+        # the three pressure solves read their source as the divergence of r (3 fields) in this pass
+        "conv_x_r2c": C * (n3 * es + N * N * nh * ce) + 3 * 2 * n3 * es,
         "conv_y_fwd": C * (N * N * nh * ce + N * P * nh * ce),
         "conv_z_fused": C * 2 * N * P * nh * ce + CL * nh ** 3 * es,
         "conv_y_inv": C * (N * P * nh * ce + N * N * nh * ce),
@@ -57,7 +58,6 @@ def alg_bytes_per_step(N: int, P: int, es: int) -> dict:
         "if_z": 15 * 2 * n3 * es,
         "curl_bar": 6 * n3 * es,
         "stage_rhs": 30 * n3 * es,
-        "stage_div": 12 * n3 * es,
         "stage_project": 7 * n3 * es,  # the last stage only (H^3 = I): reads r, dhat, writes u
         "axpby": 2 * n3 * es,
     }
@@ -299,10 +299,10 @@ def main():
         def solve_bytes(es):
             # algorithmic bytes of one three-component solve: the five passes per component, the
             # spectrum once
-            a = alg_bytes_per_step(N, P, es)
-            per_comp = sum(a[k] for k in ("conv_x_r2c", "conv_y_fwd", "conv_y_inv", "conv_x_c2r")) / 6
-            per_comp += 2 * N * P * (P // 2 + 1) * 2 * es
-            return 3 * per_comp + (P // 2 + 1) ** 3 * es
+            nh, ce, n3 = P // 2 + 1, 2 * es, N ** 3
+            per_comp = 2 * (n3 * es + N * N * nh * ce) + 2 * (N * N * nh * ce + N * P * nh * ce)
+            per_comp += 2 * N * P * nh * ce
+            return 3 * per_comp + nh ** 3 * es
 
         def rate(ms, es):
             gbs = solve_bytes(es) / (ms * 1e-3) / 1e9

@@ -194,8 +194,14 @@ static int padded(int n) {
 }
 
 // Five-pass convolution of ncomp scalar fields with a plan's spectrum times `scale`.
+// Source given as the masked divergence of a 3-component face field (formed by the first pass).
+struct DivSource {
+    const void* f;
+    int nbuf;
+    double idx;
+};
 static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s,
-                    void* A1, void* A2);
+                    void* A1, void* A2, const DivSource* div = nullptr);
 // Twiddle tables of a plan's lengths for a dtype (built on first use; call before any capture).
 static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** twh, const void** twf, const void** twy,
                          const void** twz);
@@ -389,7 +395,7 @@ static size_t conv_ws_elems_a1(const ConvPlan& p) { return (size_t)p.nz * p.ny *
 static size_t conv_ws_elems_a2(const ConvPlan& p) { return (size_t)p.nz * p.Py * p.XP * 2; }
 
 static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s,
-                    void* A1, void* A2) {
+                    void* A1, void* A2, const DivSource* div) {
     const int dt = p.dtype;
     const long long a1c = (long long)p.nz * p.ny * p.XP, a2c = (long long)p.nz * p.Py * p.XP;
     const void *twh, *twf, *twy, *twz;
@@ -407,6 +413,17 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     r.n_io = p.nx;
     r.tw_half = twh;
     r.tw_full = twf;
+    if (div) {
+        if (ncomp != 1) {
+            set_error("run_conv: a divergence source has one component");
+            return NSLGF_EINVAL;
+        }
+        r.div_src = div->f;
+        r.div_ny = p.ny;
+        r.div_nz = p.nz;
+        r.div_nbuf = div->nbuf;
+        r.div_idx = div->idx;
+    }
     NSLGF_PROF(h, "conv_x_r2c", s, launch_row_r2c(p.Px, dt, r, s));
     ColPass c{};
     c.in = A1;
@@ -560,7 +577,7 @@ static int run_if_shared(nslgf_ctx* h, const void* src, void* dst, int ncomp, in
 
 // Layout of an IF-HERK state's workspace, in elements of its dtype.
 struct StateLayout {
-    size_t q, w1, w2, r, sdiv, dhat, t1, t2, a1, a2, total;
+    size_t q, w1, w2, r, dhat, t1, t2, a1, a2, total;
 };
 static StateLayout state_layout(int nx, int ny, int nz) {
     const size_t M = (size_t)nx * ny * nz;
@@ -572,11 +589,10 @@ static StateLayout state_layout(int nx, int ny, int nz) {
     L.w1 = 3 * M;   // w1 directly after q: stage 2 applies H^1 to both as one 6-component field
     L.w2 = 6 * M;
     L.r = 9 * M;
-    L.sdiv = 12 * M;
-    L.dhat = 13 * M;
-    L.t1 = 14 * M;  // IF temporaries, 6 components each
-    L.t2 = 20 * M;
-    L.a1 = 26 * M;  // one-component convolution workspaces (complex)
+    L.dhat = 12 * M;  // (the pressure source is formed inside the convolution's first pass)
+    L.t1 = 13 * M;    // IF temporaries, 6 components each
+    L.t2 = 19 * M;
+    L.a1 = 25 * M;    // one-component convolution workspaces (complex)
     L.a2 = L.a1 + (size_t)nz * ny * XP * 2;
     L.total = L.a2 + (size_t)nz * Py * XP * 2;
     return L;
@@ -735,7 +751,6 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     void* w1 = w + L.w1 * es;
     void* w2 = w + L.w2 * es;
     void* r = w + L.r * es;
-    void* sdiv = w + L.sdiv * es;
     void* dhat = w + L.dhat * es;
     void* t1 = w + L.t1 * es;
     void* t2 = w + L.t2 * es;
@@ -769,8 +784,9 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         c.c_q = 1.0;
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     }
-    NSLGF_PROF(h, "stage_div", s, launch_masked_div(dt_, r, sdiv, st->n_buf, nx, ny, nz, st->dx, s));
-    NSLGF_TRY(run_conv(h, *plan, sdiv, dhat, 1, st->dx * st->dx, s, a1, a2));
+    // pressure source M_supp Dbar r, formed while the convolution's first pass loads
+    const DivSource dsrc{r, st->n_buf, 1.0 / st->dx};
+    NSLGF_TRY(run_conv(h, *plan, nullptr, dhat, 1, st->dx * st->dx, s, a1, a2, &dsrc));
     // u^i = H^i (r^i - G dhat^i) and w^{i,i} = (g^i - G dhat^i) / (a~_ii dt) = (r^i - G dhat^i - q^i -
     // dt sum_j a~_ij w^{i,j}) / (a~_ii dt); the projection is applied while the IF loads (with H^i = I,
     // e.g. the last stage of Schemes A and B, it writes u directly)

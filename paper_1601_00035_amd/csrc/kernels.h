@@ -31,6 +31,12 @@ struct RowPass {
     int n_io;             // R2C: real inputs per row (rest zero); C2R: real outputs kept per row
     const void* tw_half;  // root table of length P/2 (complex FFT)
     const void* tw_full;  // root table of length P (real pre/post processing)
+    // R2C only, when div_src is set: the input rows are not read from `in` but formed on load as the
+    // masked divergence M_supp Dbar f of the 3-component face field div_src (box nx = n_io, ny, nz;
+    // rows are (z, y) pairs, one component; points closer than div_nbuf to a box face give 0)
+    const void* div_src;
+    int div_ny, div_nz, div_nbuf;
+    double div_idx;  // 1 / dx
 };
 int launch_row_r2c(int P, int dtype, const RowPass& a, hipStream_t s);
 int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s);

@@ -21,9 +21,22 @@
 namespace nslgf {
 
 // ---------------------------------------------------------------------------------------------------
+// Masked divergence of a face field at (x, y, z), in the order of operations of the divergence kernel.
+template <typename T>
+__device__ __forceinline__ T masked_div_at(const T* f, int x, int y, int z, int nx, int ny, int nz, int nbuf, T idx) {
+    if (x < nbuf || x >= nx - nbuf || y < nbuf || y >= ny - nbuf || z < nbuf || z >= nz - nbuf) return (T)0;
+    const long long n = (long long)nx * ny * nz;
+    const long long c = ((long long)z * ny + y) * nx + x;
+    const T f0m = x > 0 ? f[c - 1] : (T)0;
+    const T f1m = y > 0 ? f[n + c - nx] : (T)0;
+    const T f2m = z > 0 ? f[2 * n + c - (long long)nx * ny] : (T)0;
+    return (f[c] + f[n + c] + f[2 * n + c] - f0m - f1m - f2m) * idx;
+}
+
 // PAIRS: the real rows are read as pairs (x[2n], x[2n+1]) with one vector load each (the host sets it
-// when the base is aligned, rows and components have even lengths, and n_io is even).
-template <typename T, int LH, bool PAIRS>
+// when the base is aligned, rows and components have even lengths, and n_io is even).  DIV: the rows
+// are the masked divergence of RowPass::div_src, formed on load.
+template <typename T, int LH, bool PAIRS, bool DIV>
 __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
@@ -48,7 +61,18 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int m = 2 * (j + r * (LH / R1));  // z[n] = x[2n] + i x[2n+1]
-            if constexpr (PAIRS) {
+            if constexpr (DIV) {
+                const int y = (int)(row % a.div_ny), z = (int)(row / a.div_ny);
+                const T* f = (const T*)a.div_src;
+                const T idx = (T)a.div_idx;
+                const T re = (valid && m < a.n_io)
+                                 ? masked_div_at<T>(f, m, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, idx)
+                                 : (T)0;
+                const T im = (valid && m + 1 < a.n_io)
+                                 ? masked_div_at<T>(f, m + 1, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, idx)
+                                 : (T)0;
+                v[b * R1 + r] = mk<T>(re, im);
+            } else if constexpr (PAIRS) {
                 v[b * R1 + r] = (valid && m < a.n_io) ? *(const cplx<T>*)(in + m) : mk<T>((T)0, (T)0);
             } else {
                 const T re = (valid && m < a.n_io) ? in[m] : (T)0;
@@ -312,10 +336,17 @@ template <typename T> static bool real_pairs(const void* p, long long row, long 
 template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s) {
     constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
-    if (real_pairs<T>(a.in, a.in_row, a.in_comp, a.n_io))
-        hipLaunchKernelGGL((k_row_r2c<T, LH, true>), grid, dim3(RPW * TP), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_row_r2c<T, LH, false>), grid, dim3(RPW * TP), 0, s, a);
+    if (a.div_src) {
+        if (a.ncomp != 1 || a.nrows != (long long)a.div_ny * a.div_nz) {
+            set_error("row pass: the divergence input needs one component over ny * nz rows");
+            return NSLGF_EINVAL;
+        }
+        hipLaunchKernelGGL((k_row_r2c<T, LH, false, true>), grid, dim3(RPW * TP), 0, s, a);
+    } else if (real_pairs<T>(a.in, a.in_row, a.in_comp, a.n_io)) {
+        hipLaunchKernelGGL((k_row_r2c<T, LH, true, false>), grid, dim3(RPW * TP), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_row_r2c<T, LH, false, false>), grid, dim3(RPW * TP), 0, s, a);
+    }
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
