@@ -302,9 +302,9 @@ struct ColAcc {
 template <int L> __host__ __device__ constexpr int col_lds_len() { return L + L / 16 + 1; }
 
 // LDS accessor of the row kernels: one contiguous segment per row, one pad element every 2^S
-// elements.  For complex doubles S = 3 spreads the strided stores of the radix-4 and radix-8 passes
-// (NS = 1 and 4) over distinct bank groups; complex floats keep S = 4.
-template <typename T> __host__ __device__ constexpr int row_pad_shift() { return sizeof(T) == 8 ? 3 : 4; }
+// elements (S = 4; padding every 8 complex doubles measured no faster and would cost the row kernels
+// a workgroup per CU once their twiddle table is in LDS).
+template <typename T> __host__ __device__ constexpr int row_pad_shift() { return 4; }
 template <typename T>
 struct RowAcc {
     cplx<T>* base;

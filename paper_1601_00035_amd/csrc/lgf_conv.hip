@@ -50,7 +50,9 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
     const bool valid = row < a.nrows;
     const T* in = (const T*)a.in + comp * a.in_comp + (valid ? row : 0) * a.in_row;
     cplx<T>* out = (cplx<T>*)a.out + comp * a.out_comp + (valid ? row : 0) * a.out_row;
-    const cplx<T>* twh = (const cplx<T>*)a.tw_half;
+    // the half-length root table goes to LDS (read by the transform's passes after the barrier below)
+    __shared__ cplx<T> twh[LH];
+    for (int m = tid; m < LH; m += RPW * TP) twh[m] = ((const cplx<T>*)a.tw_half)[m];
     const cplx<T>* twf = (const cplx<T>*)a.tw_full;
     RowAcc<T> acc{lds + rl * LD};
     cplx<T> v[E];
@@ -81,6 +83,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
             }
         }
     }
+    __syncthreads();
     fft_regs<T, LH, false, RL>(v, t, twh, acc);
     constexpr int RLs = Last<RL>::value;
     __syncthreads();
@@ -123,7 +126,8 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
     const bool valid = row < a.nrows;
     const cplx<T>* in = (const cplx<T>*)a.in + comp * a.in_comp + (valid ? row : 0) * a.in_row;
     T* out = (T*)a.out + comp * a.out_comp + (valid ? row : 0) * a.out_row;
-    const cplx<T>* twh = (const cplx<T>*)a.tw_half;
+    __shared__ cplx<T> twh[LH];  // the half-length root table, in LDS from the first barrier on
+    for (int m = tid; m < LH; m += RPW * TP) twh[m] = ((const cplx<T>*)a.tw_half)[m];
     const cplx<T>* twf = (const cplx<T>*)a.tw_full;
     RowAcc<T> acc{lds + rl * LD};
     for (int k = t; k <= LH; k += TP) acc(k) = valid ? in[k] : mk<T>((T)0, (T)0);
