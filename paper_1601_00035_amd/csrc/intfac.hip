@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
 
 constexpr int kIfSegment = 32;  // outputs per thread of the strided passes
 
-constexpr int kIfRowsPerBlock = 64;  // output rows per workgroup of the fused x-y pass
+constexpr int kIfRowsPerBlock = 128;  // output rows per workgroup of the fused x-y pass (halo rows re-read: 2R / 128)
 constexpr int kIfRowsPerStep = 4;    // rows per barrier of the fused x-y pass
 constexpr int kIfPrefetch = 2;       // steps loaded ahead by the fused x-y pass
 
