@@ -47,6 +47,24 @@ def test_step_parity(scheme, n_buf):
     assert abs(st.t - dt) < 1e-15
 
 
+@pytest.mark.parametrize("scheme", ["A", "C"])
+def test_step_parity_wide_integrating_factor(scheme):
+    """A viscous step whose integrating-factor radius exceeds the compile-time radii (beta = dt/(dx^2 Re)
+    of 3): the stages then take the runtime-radius passes with a separate projection and combination,
+    in both FP64 and FP32."""
+    n, dx, w, re, cfl = _case(24, seed=5)
+    u0 = ifherk.vor2vel(w, dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    re_v = dt / (dx * dx * 3.0)
+    u_ref, d_ref = ifherk.step(u0, dt, dx, re_v, scheme, n_buf=2)
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        u = torch.from_numpy(u0).to(DEV, dtype)
+        st = nslgf.HerkState(u, dx, dt, re_v, scheme, n_buf=2)
+        st.step()
+        assert rel(u.double().cpu().numpy(), u_ref) < tol, dtype
+        assert rel(st.d.double().cpu().numpy(), d_ref) < 10 * tol, dtype
+
+
 def test_two_steps_and_fp32():
     n, dx, w, re, cfl = _case(20, seed=3)
     u0 = ifherk.vor2vel(w, dx)
