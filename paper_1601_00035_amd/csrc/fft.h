@@ -120,6 +120,29 @@ template <typename T, bool INV> struct DFT<T, 4, INV> {
     }
 };
 
+// Second half of the radix-8 butterfly: X[k] = E[k] + W8^k O[k], X[k+4] = E[k] - W8^k O[k] from the
+// length-4 DFTs E of the even and O of the odd inputs (only X[0..3] when nout = 4).
+template <typename T, bool INV>
+__device__ __forceinline__ void combine8(const cplx<T>* e, const cplx<T>* o, cplx<T>* v, int nout) {
+    const T c = (T)0.70710678118654752440084436210484903928;
+    // W8^1 = c (1 - i) forward, c (1 + i) inverse; W8^2 = -i / +i; W8^3 = -c (1 + i) / c (-1 + i)
+    cplx<T> o1 = INV ? mk<T>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
+                     : mk<T>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+    cplx<T> o2 = INV ? cmul_i<T>(o[2]) : cmul_mi<T>(o[2]);
+    cplx<T> o3 = INV ? mk<T>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
+                     : mk<T>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+    v[0] = cadd<T>(e[0], o[0]);
+    v[1] = cadd<T>(e[1], o1);
+    v[2] = cadd<T>(e[2], o2);
+    v[3] = cadd<T>(e[3], o3);
+    if (nout == 8) {
+        v[4] = csub<T>(e[0], o[0]);
+        v[5] = csub<T>(e[1], o1);
+        v[6] = csub<T>(e[2], o2);
+        v[7] = csub<T>(e[3], o3);
+    }
+}
+
 template <typename T, bool INV> struct DFT<T, 8, INV> {
     __device__ __forceinline__ static void run(cplx<T>* v) {
         // even / odd split into two length-4 DFTs, then X[k] = E[k] +- W8^k O[k]
@@ -127,21 +150,7 @@ template <typename T, bool INV> struct DFT<T, 8, INV> {
         cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
         DFT<T, 4, INV>::run(e);
         DFT<T, 4, INV>::run(o);
-        const T c = (T)0.70710678118654752440084436210484903928;
-        // W8^1 = c (1 - i) forward, c (1 + i) inverse; W8^2 = -i / +i; W8^3 = -c (1 + i) / c (-1 + i)
-        cplx<T> o1 = INV ? mk<T>(c * (o[1].x - o[1].y), c * (o[1].x + o[1].y))
-                         : mk<T>(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
-        cplx<T> o2 = INV ? cmul_i<T>(o[2]) : cmul_mi<T>(o[2]);
-        cplx<T> o3 = INV ? mk<T>(-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y))
-                         : mk<T>(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
-        v[0] = cadd<T>(e[0], o[0]);
-        v[4] = csub<T>(e[0], o[0]);
-        v[1] = cadd<T>(e[1], o1);
-        v[5] = csub<T>(e[1], o1);
-        v[2] = cadd<T>(e[2], o2);
-        v[6] = csub<T>(e[2], o2);
-        v[3] = cadd<T>(e[3], o3);
-        v[7] = csub<T>(e[3], o3);
+        combine8<T, INV>(e, o, v, 8);
     }
 };
 
@@ -216,9 +225,64 @@ template <typename T, int R1, int R2, bool INV> struct DFTC {
     }
 };
 
+// Pruned butterflies of the zero-padded transforms.  DFTHalfIn: inputs R/2 .. R-1 are zero (the
+// first pass of a transform whose upper half is padding).  DFTHalfOut: only outputs 0 .. R/2-1 are
+// kept (the last pass of a transform whose upper half is discarded).  Even radices 2, 4, 8; the
+// kept values equal the full butterfly's.
+template <typename T, int R, bool INV> struct DFTHalfIn;
+template <typename T, bool INV> struct DFTHalfIn<T, 2, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) { v[1] = v[0]; }
+};
+template <typename T, bool INV> struct DFTHalfIn<T, 4, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        // (a, b, 0, 0): X0 = a + b, X2 = a - b, X1 = a - i b, X3 = a + i b (forward)
+        const cplx<T> a = v[0], b = v[1];
+        const cplx<T> ib = INV ? cmul_i<T>(b) : cmul_mi<T>(b);
+        v[0] = cadd<T>(a, b);
+        v[2] = csub<T>(a, b);
+        v[1] = cadd<T>(a, ib);
+        v[3] = csub<T>(a, ib);
+    }
+};
+template <typename T, bool INV> struct DFTHalfIn<T, 8, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};  // v[4], v[6] are zero
+        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};  // v[5], v[7] are zero
+        DFTHalfIn<T, 4, INV>::run(e);
+        DFTHalfIn<T, 4, INV>::run(o);
+        combine8<T, INV>(e, o, v, 8);
+    }
+};
+template <typename T, int R, bool INV> struct DFTHalfOut;
+template <typename T, bool INV> struct DFTHalfOut<T, 2, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) { v[0] = cadd<T>(v[0], v[1]); }
+};
+template <typename T, bool INV> struct DFTHalfOut<T, 4, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        cplx<T> t0 = cadd<T>(v[0], v[2]), t1 = csub<T>(v[0], v[2]);
+        cplx<T> t2 = cadd<T>(v[1], v[3]), t3 = csub<T>(v[1], v[3]);
+        cplx<T> it3 = INV ? cmul_i<T>(t3) : cmul_mi<T>(t3);
+        v[0] = cadd<T>(t0, t2);
+        v[1] = cadd<T>(t1, it3);
+    }
+};
+template <typename T, bool INV> struct DFTHalfOut<T, 8, INV> {
+    __device__ __forceinline__ static void run(cplx<T>* v) {
+        cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        DFT<T, 4, INV>::run(e);
+        DFT<T, 4, INV>::run(o);
+        combine8<T, INV>(e, o, v, 4);
+    }
+};
+
 // ---- passes -----------------------------------------------------------------------------------
 // tw: root table tw[m] = exp(-2 pi i m / L), m < L (forward); the inverse conjugates it.
-template <typename T, int L, int E, int TP, bool INV, int NS, int R>
+// PRUNE bit 1: this is the first pass and inputs r >= R/2 of every butterfly are zero; bit 2: this is
+// the last pass and only outputs r < R/2 are used.  Only even radices 2, 4, 8 are pruned.
+template <int R> __host__ __device__ constexpr bool prunable() { return R == 2 || R == 4 || R == 8; }
+
+template <typename T, int L, int E, int TP, bool INV, int NS, int R, int PRUNE = 0>
 __device__ __forceinline__ void pass_compute(cplx<T>* v, int t, const cplx<T>* __restrict__ tw) {
 #pragma unroll
     for (int b = 0; b < E / R; ++b) {
@@ -231,7 +295,11 @@ __device__ __forceinline__ void pass_compute(cplx<T>* v, int t, const cplx<T>* _
                 v[b * R + r] = INV ? cmulc<T>(v[b * R + r], w) : cmul<T>(v[b * R + r], w);
             }
         }
-        if constexpr (R == 16) {
+        if constexpr ((PRUNE & 1) && prunable<R>()) {
+            DFTHalfIn<T, R, INV>::run(v + b * R);
+        } else if constexpr ((PRUNE & 2) && prunable<R>()) {
+            DFTHalfOut<T, R, INV>::run(v + b * R);
+        } else if constexpr (R == 16) {
             DFTC<T, 4, 4, INV>::run(v + b * R, tw, L / 16);
         } else if constexpr (R == 32) {
             DFTC<T, 4, 8, INV>::run(v + b * R, tw, L / 32);
@@ -262,34 +330,39 @@ __device__ __forceinline__ void pass_load(cplx<T>* v, int t, Acc& acc) {
     }
 }
 
-template <typename T, int L, int E, int TP, bool INV, int NS, class RL> struct Runner;
+template <typename T, int L, int E, int TP, bool INV, int NS, int PRUNE, class RL> struct Runner;
 
-template <typename T, int L, int E, int TP, bool INV, int NS, int R>
-struct Runner<T, L, E, TP, INV, NS, RList<R>> {
+template <typename T, int L, int E, int TP, bool INV, int NS, int PRUNE, int R>
+struct Runner<T, L, E, TP, INV, NS, PRUNE, RList<R>> {
     template <class Acc>
     __device__ __forceinline__ static void run(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc&) {
-        pass_compute<T, L, E, TP, INV, NS, R>(v, t, tw);
+        // a single-pass transform prunes only one side (input pruning wins)
+        constexpr int P1 = (NS == 1 && (PRUNE & 1)) ? 1 : (PRUNE & 2);
+        pass_compute<T, L, E, TP, INV, NS, R, P1>(v, t, tw);
     }
 };
 
-template <typename T, int L, int E, int TP, bool INV, int NS, int R, int R2, int... Rest>
-struct Runner<T, L, E, TP, INV, NS, RList<R, R2, Rest...>> {
+template <typename T, int L, int E, int TP, bool INV, int NS, int PRUNE, int R, int R2, int... Rest>
+struct Runner<T, L, E, TP, INV, NS, PRUNE, RList<R, R2, Rest...>> {
     template <class Acc>
     __device__ __forceinline__ static void run(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
-        pass_compute<T, L, E, TP, INV, NS, R>(v, t, tw);
+        pass_compute<T, L, E, TP, INV, NS, R, (NS == 1) ? (PRUNE & 1) : 0>(v, t, tw);
         __syncthreads();
         pass_store<T, L, E, TP, NS, R>(v, t, acc);
         __syncthreads();
         pass_load<T, L, E, TP, R2>(v, t, acc);
-        Runner<T, L, E, TP, INV, NS * R, RList<R2, Rest...>>::run(v, t, tw, acc);
+        Runner<T, L, E, TP, INV, NS * R, PRUNE, RList<R2, Rest...>>::run(v, t, tw, acc);
     }
 };
 
 // Full transform on registers: input v[b R1 + r] = x[t + b TP + r L/R1] (R1 = first radix of the
-// list), output v[b Rl + r] = X[t + b TP + r L/Rl] (Rl = last radix).
-template <typename T, int L, bool INV, class RL, class Acc, int E = Plan1D<L>::E>
+// list), output v[b Rl + r] = X[t + b TP + r L/Rl] (Rl = last radix).  PRUNE bit 1: the inputs
+// x[L/2 .. L-1] are zero (the caller leaves v[b R1 + r], r >= R1/2, unset or zero); bit 2: only
+// X[0 .. L/2-1] are wanted (v[b Rl + r], r >= Rl/2, are left undefined).  Either applies only when the
+// first (bit 1) or last (bit 2) radix is 2, 4 or 8.
+template <typename T, int L, bool INV, class RL, class Acc, int E = Plan1D<L>::E, int PRUNE = 0>
 __device__ __forceinline__ void fft_regs(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
-    Runner<T, L, E, L / E, INV, 1, RL>::run(v, t, tw, acc);
+    Runner<T, L, E, L / E, INV, 1, PRUNE, RL>::run(v, t, tw, acc);
 }
 
 // LDS accessor of the column-tile kernels: element pos of column c, columns interleaved.

@@ -168,7 +168,10 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
 }
 
 // ---------------------------------------------------------------------------------------------------
-template <typename T, int L, int MODE, int V = 0>
+// PR bit 1: n_in <= L/2, so the forward transform's first butterflies see a zero upper half; bit 2:
+// n_out <= L/2, so the inverse transform's last butterflies produce only the lower half (set by the
+// host; the fused pass always has both).
+template <typename T, int L, int MODE, int V = 0, int PR = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PlanV<L, V>::waves)))
 k_col(ColPass a) {
     using P = PlanV<L, V>;
@@ -225,7 +228,10 @@ k_col(ColPass a) {
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
             const int row = j + r * (L / R1);
-            v[b * R1 + r] = (valid && row < a.n_in) ? in[(long long)row * a.in_row] : mk<T>((T)0, (T)0);
+            if (MODE != COL_INV && (PR & 1) && prunable<R1>() && 2 * r >= R1)
+                v[b * R1 + r] = mk<T>((T)0, (T)0);  // padding (row >= L/2 >= n_in)
+            else
+                v[b * R1 + r] = (valid && row < a.n_in) ? in[(long long)row * a.in_row] : mk<T>((T)0, (T)0);
         }
     }
     // COL_CONV: the spectrum values this thread multiplies by are loaded now, behind the data loads,
@@ -246,15 +252,15 @@ k_col(ColPass a) {
         }
     }
     if constexpr (MODE == COL_INV) {
-        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, Acc, E, PR & 2>(v, t, tw, acc);
     } else {
-        fft_regs<T, L, false, RF, Acc, E>(v, t, tw, acc);
+        fft_regs<T, L, false, RF, Acc, E, PR & 1>(v, t, tw, acc);
     }
     if constexpr (MODE == COL_CONV) {
         const T sc = (T)a.scale;
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = cscale<T>(v[e], kv[e] * sc);
-        fft_regs<T, L, true, RI, Acc, E>(v, t, tw, acc);
+        fft_regs<T, L, true, RI, Acc, E, PR & 2>(v, t, tw, acc);
     }
     using ROut = typename std::conditional<MODE == COL_FWD, RF, RI>::type;
     constexpr int RO = Last<ROut>::value;
@@ -265,6 +271,7 @@ k_col(ColPass a) {
 #pragma unroll
             for (int r = 0; r < RO; ++r) {
                 const int row = j + r * (L / RO);
+                if (MODE != COL_FWD && (PR & 2) && prunable<RO>() && 2 * r >= RO) continue;  // not computed
                 if (row < a.n_out) out[(long long)row * a.out_row] = v[b * RO + r];
             }
         }
@@ -373,7 +380,18 @@ template <typename T, int L, int MODE, int V = 0> static int do_col(const ColPas
     }
     dim3 grid(ceil_div(a.ncols, TB), a.nouter, a.ncomp);
     if (MODE == COL_CONV) grid = dim3(ceil_div(a.ncols, TB) * a.nouter * a.ncomp);
-    hipLaunchKernelGGL((k_col<T, L, MODE, V>), grid, dim3(TB * TP), 0, s, a);
+    const bool half_in = 2 * a.n_in <= L, half_out = 2 * a.n_out <= L;
+    if (MODE == COL_CONV) {
+        if (!half_in || !half_out) {
+            set_error("column pass: the fused pass needs n_in, n_out <= L/2");
+            return NSLGF_EINVAL;
+        }
+        hipLaunchKernelGGL((k_col<T, L, MODE, V, 3>), grid, dim3(TB * TP), 0, s, a);
+    } else if ((MODE == COL_FWD && half_in) || (MODE == COL_INV && half_out)) {
+        hipLaunchKernelGGL((k_col<T, L, MODE, V, MODE == COL_FWD ? 1 : 2>), grid, dim3(TB * TP), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_col<T, L, MODE, V, 0>), grid, dim3(TB * TP), 0, s, a);
+    }
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
