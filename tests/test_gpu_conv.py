@@ -183,3 +183,6 @@ def test_invalid_arguments():
         nslgf.lgf_convolve(big, 1.0)
     with pytest.raises(ValueError):
         nslgf.lgf_convolve(torch.zeros((4, 4, 4), dtype=torch.float64), 1.0)
+    # empty boxes are refused
+    with pytest.raises((nslgf.NslgfError, ValueError)):
+        nslgf.lgf_convolve(torch.zeros((0, 4, 4), dtype=torch.float64, device=DEV), 1.0)

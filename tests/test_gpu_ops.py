@@ -42,6 +42,13 @@ def test_if_apply_rejects_negative_alpha():
     t = torch.zeros((3, 4, 4, 4), dtype=torch.float64, device=DEV)
     with pytest.raises(nslgf.NslgfError):
         nslgf.if_apply(t, -0.1)
+    # a diffusion so wide that the kernel radius exceeds the supported one is refused, not truncated
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.if_apply(t, 1.0e4)
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.if_apply(t, float("nan"))
+    with pytest.raises(nslgf.NslgfError):
+        nslgf.if_apply(torch.zeros((7, 4, 4, 4), dtype=torch.float64, device=DEV), 0.1)  # ncomp > 6
 
 
 OPS = {
