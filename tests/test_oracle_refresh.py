@@ -1,0 +1,80 @@
+"""Pins of the oracle's velocity refresh and its cadence (Sec. 4.4, Appendix D): the truncation error
+d(k) against the masked integrating factor applied by brute force, its closed forms, the monotone
+cadence, and the refresh leaving a velocity whose vorticity lies inside the support unchanged."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import ive
+
+from oracle import ifherk, intfac, refresh, stencils
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.4, 1.5])
+def test_trunc_error_is_the_masked_deficit(alpha):
+    """M E(a) M applied to 1 on a box is, at every point, the product over the axes of
+    1 - d(i + 1) - d(n - i) (the kernel mass beyond the near and the far face): the brute-force 3D
+    sum of the masked integrating factor fixes both the sum and its index convention."""
+    shape = (9, 11, 13)  # nz, ny, nx
+    got = intfac.apply(np.ones(shape), alpha)
+    f = [np.array([1.0 - refresh.trunc_error(alpha, i + 1) - refresh.trunc_error(alpha, n - i) for i in range(n)])
+         for n in shape]
+    expect = f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+    assert np.abs(got - expect).max() < 2e-14
+
+
+def test_trunc_error_closed_forms():
+    for a in (1e-3, 0.1, 2.0, 30.0):
+        # kernel mass is 1 and symmetric: the tail beyond the centre is (1 - w_0) / 2
+        assert abs(refresh.trunc_error(a, 1) - 0.5 * (1.0 - ive(0, 2 * a))) < 1e-15
+    # small a: the leading term of e^{-2a} I_k(2a) is a^k / k!
+    a = 1e-4
+    for k in (1, 2, 5):
+        assert abs(refresh.trunc_error(a, k) / (a ** k / math.factorial(k)) - 1.0) < 3 * a
+    # large a: the difference of two Poisson(a) variables is nearly Gaussian with variance 2a
+    a = 200.0
+    for k in (5, 20, 40):
+        gauss = 0.5 * math.erfc((k - 0.5) / math.sqrt(4 * a))
+        assert abs(refresh.trunc_error(a, k) - gauss) < 2e-3 * gauss
+    assert refresh.trunc_error(0.0, 3) == 0.0
+    with pytest.raises(ValueError):
+        refresh.trunc_error(0.1, 0)
+
+
+def test_refresh_interval_is_the_last_step_within_eps():
+    beta, n_buf, umax = 0.05, 4, 0.7
+    for eps in (1e-8, 1e-7, 1e-5):
+        q = refresh.refresh_interval(beta, n_buf, umax, eps)
+        assert q >= 1
+        assert refresh.estimate(beta, q, n_buf, umax) <= eps < refresh.estimate(beta, q + 1, n_buf, umax)
+    # tighter eps or a thinner buffer never allows more steps
+    qs = [refresh.refresh_interval(beta, n_buf, umax, e) for e in (1e-5, 1e-7, 1e-8)]
+    assert qs[0] >= qs[1] >= qs[2]
+    assert refresh.refresh_interval(beta, 2, umax, 1e-6) < refresh.refresh_interval(beta, 4, umax, 1e-6)
+    # one step already too much, or nothing to refresh
+    assert refresh.refresh_interval(beta, 0, umax, 1e-12) == 0
+    assert refresh.refresh_interval(beta, n_buf, 0.0, 1e-12, q_cap=77) == 77
+
+
+def test_refresh_keeps_a_velocity_with_vorticity_inside_the_support():
+    """u = Vor2Vel(C f) with f compact inside the support: C u equals C f on the support (D C f = 0
+    makes -C Cbar L^{-1} the identity there), so the refresh recomputes the same u."""
+    n, dx, n_buf = 16, 0.4, 3
+    rng = np.random.default_rng(5)
+    f = np.zeros((3, n, n, n))
+    f[:, 5:-5, 5:-5, 5:-5] = rng.standard_normal((3, n - 10, n - 10, n - 10))
+    u = ifherk.vor2vel(stencils.curl(f, dx), dx)
+    assert np.abs(refresh.velocity_refresh(u, dx, n_buf) - u).max() < 1e-12 * np.abs(u).max()
+    # a velocity with vorticity outside the support changes, and the result is divergence free
+    g = rng.standard_normal((3, n, n, n))
+    v = refresh.velocity_refresh(g, dx, n_buf)
+    assert np.abs(v - g).max() > 0.1
+    assert np.abs(stencils.div(v, dx)[1:-1, 1:-1, 1:-1]).max() < 1e-11 * np.abs(v).max() / dx
+
+
+def test_component_max_on_the_solution_domain():
+    u = np.zeros((3, 10, 10, 10))
+    u[1, 5, 5, 5] = -0.3
+    u[2, 0, 5, 5] = 9.0  # outside the solution domain of n_buf = 1
+    assert refresh.component_max(u, 1) == 0.3
+    assert refresh.component_max(u, 0) == 9.0
