@@ -345,6 +345,27 @@ def main():
                                   "speedup_vs_fp64": round(ms / ms32s, 3), **step_err}
         del u0, s64, s32, w32, diff
         torch.cuda.empty_cache()
+        # velocity refresh (Sec. 4.4) at 256^3 FP64 and its cadence for this step (Appendix D estimate)
+        ur = u.clone()
+        nslgf.velocity_refresh(ur, dx, 16)
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        r0.record(stream)
+        for _ in range(5):
+            nslgf.velocity_refresh(ur, dx, 16)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        ms_ref = r0.elapsed_time(r1) / 5
+        umax = nslgf.max_component_abs(u, 16)
+        beta = dt / (dx * dx * re)
+        cadence = {}
+        for rel_eps in (1e-10, 1e-8, 1e-6):
+            q = nslgf.refresh_interval(beta, 16, umax, rel_eps * umax)
+            cadence[f"{rel_eps:g}"] = {"q_max": q, "refresh_ms_per_step": round(ms_ref / q, 4) if q else None}
+        secondary["velocity_refresh"] = {"ms": round(ms_ref, 4), "n_buf": 16, "beta": beta, "umax": umax,
+                                         "cadence_by_eps_over_umax": cadence}
+        del ur
+        torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
                                 "fp32": batched_measure(nslgf, torch, torch.float32)}

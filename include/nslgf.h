@@ -157,6 +157,51 @@ int herk_step_batched(nslgf_t h, nslgf_state *const *sts, int n, void *stream);
 int vor2vel(nslgf_t h, const void *w, void *u, int nx, int ny, int nz, double dx, int dtype, void *stream);
 
 /*
+ * Truncation error of the masked integrating factor (Appendix D, Eq. if_finite_error): for a uniform
+ * unit field on a half-space whose mask keeps the points k >= 1 along one axis, the deficit of
+ * M E(alpha) M at the point k is the 1D kernel mass at distances >= k,
+ *     d_alpha(k) = sum_{n >= k} e^{-2 alpha} I_n(2 alpha).
+ * (The printed index of the sum is garbled; this is the sum the stated mask gives.)  Host only, no
+ * handle.  NSLGF_EINVAL for alpha < 0 or not finite, k < 1, or a null out.
+ */
+int if_trunc_error(double alpha, int k, double *out);
+
+/*
+ * Velocity refresh cadence (Sec. 4.4 with Appendix D): q steps apply integrating factors that compose
+ * to E(q beta), beta = dt / (dx^2 Re), and the solution domain starts n_buf points inside the box, so
+ * the error there after q steps is estimated by umax d_{q beta}(n_buf + 1), umax the largest magnitude
+ * of any velocity component on the solution domain.  *q_max = the largest q <= q_cap whose estimate
+ * is <= eps (q_cap when umax or beta is 0; 0 when one step already exceeds eps).  Host only.
+ * NSLGF_EINVAL for beta < 0, n_buf < 0, umax < 0, eps <= 0, q_cap < 1 or a null q_max.
+ */
+int refresh_interval(double beta, int n_buf, double umax, double eps, int q_cap, int *q_max);
+
+/*
+ * *out = the largest |u^(q)| over the three components of the face field u [3][nz][ny][nx] on the box
+ * shrunk by n_buf points (the umax of refresh_interval).  Synchronises `stream`.
+ */
+int max_component_abs(nslgf_t h, const void *u, int nx, int ny, int nz, int n_buf, int dtype, double *out,
+                      void *stream);
+
+/*
+ * Velocity refresh (Sec. 4.4): the velocity on the box is recomputed from the vorticity on the support
+ * domain (the box shrunk by n_buf points) with Vor2Vel, in place:
+ *     w = M_supp C u,  a = -L^{-1} w,  u = Cbar a.
+ * u: face velocity [3][nz][ny][nx].  Uses handle-owned temporaries (two 3-component fields).
+ */
+int velocity_refresh(nslgf_t h, void *u, int nx, int ny, int nz, int n_buf, double dx, int dtype, void *stream);
+
+/*
+ * nsteps IF-HERK steps of st (herk_step each), refreshing the velocity with velocity_refresh after
+ * every q_max steps (Sec. 4.4); q_max = refresh_interval(dt / (dx^2 Re), n_buf, umax, eps, q_cap) with
+ * umax = max_component_abs of st->u, taken at the start and again after each refresh (each takes a
+ * stream synchronisation).  The refresh works in st->work.  *refreshes (may be null) = the number of
+ * refreshes done.  NSLGF_EINVAL for nsteps < 0, eps <= 0, q_cap < 1, or when q_max is 0 (the buffer
+ * is too thin for eps; the footnote of Sec. 4.4 excludes that case).
+ */
+int herk_run(nslgf_t h, nslgf_state *st, int nsteps, double eps, int q_cap, int *refreshes, void *stream);
+
+/*
  * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
  *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
  *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])

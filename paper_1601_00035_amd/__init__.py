@@ -71,6 +71,11 @@ def lib():
                     "nslgf_profile_read": [vp, i, ctypes.c_char_p, i, ctypes.POINTER(ctypes.c_longlong),
                                            ctypes.POINTER(d)],
                     "nslgf_copy": [vp, vp, vp, ctypes.c_size_t, i, vp],
+                    "if_trunc_error": [d, i, ctypes.POINTER(d)],
+                    "refresh_interval": [d, i, d, d, i, ctypes.POINTER(i)],
+                    "max_component_abs": [vp, vp, i, i, i, i, i, ctypes.POINTER(d), vp],
+                    "velocity_refresh": [vp, vp, i, i, i, i, d, i, vp],
+                    "herk_run": [vp, ctypes.POINTER(_State), i, d, i, ctypes.POINTER(i), vp],
                 }
                 for name, args in sig.items():
                     f = getattr(L, name)
@@ -220,6 +225,42 @@ def max_cell_speed(u: torch.Tensor) -> float:
     return out.value
 
 
+def if_trunc_error(alpha: float, k: int) -> float:
+    """d_alpha(k) = sum_{n >= k} e^{-2 alpha} I_n(2 alpha): the masked integrating factor's deficit for a
+    uniform unit field at the k-th point inside a face (host evaluation)."""
+    out = ctypes.c_double()
+    _check("if_trunc_error", lib().if_trunc_error(float(alpha), int(k), ctypes.byref(out)))
+    return out.value
+
+
+def refresh_interval(beta: float, n_buf: int, umax: float, eps: float, q_cap: int = 10000) -> int:
+    """q_max: the largest number of steps whose estimated truncation error on the solution domain,
+    umax d_{q beta}(n_buf + 1), stays within eps (host evaluation)."""
+    out = ctypes.c_int()
+    _check("refresh_interval", lib().refresh_interval(float(beta), int(n_buf), float(umax), float(eps), int(q_cap),
+                                                      ctypes.byref(out)))
+    return out.value
+
+
+def max_component_abs(u: torch.Tensor, n_buf: int) -> float:
+    """Largest |u^(q)| on the box shrunk by n_buf points (synchronises the stream)."""
+    _dev(u, "u")
+    _, nz, ny, nx = u.shape
+    out = ctypes.c_double()
+    _check("max_component_abs", lib().max_component_abs(handle(u.device.index), u.data_ptr(), nx, ny, nz, int(n_buf),
+                                                        _dtype(u), ctypes.byref(out), _stream(u)))
+    return out.value
+
+
+def velocity_refresh(u: torch.Tensor, dx: float, n_buf: int) -> torch.Tensor:
+    """In place: u = Cbar a, a = -L^{-1} w, w = M_supp C u (support = box shrunk by n_buf points)."""
+    _dev(u, "u")
+    _, nz, ny, nx = u.shape
+    _check("velocity_refresh", lib().velocity_refresh(handle(u.device.index), u.data_ptr(), nx, ny, nz, int(n_buf),
+                                                      float(dx), _dtype(u), _stream(u)))
+    return u
+
+
 FFT_PLAN_AUTOTUNE = -2
 
 
@@ -299,6 +340,14 @@ class HerkState:
 
     def step(self):
         _check("herk_step", lib().herk_step(handle(self.u.device.index), ctypes.byref(self.c), _stream(self.u)))
+
+    def run(self, nsteps: int, eps: float, q_cap: int = 10000) -> int:
+        """nsteps steps with a velocity refresh after every q_max steps (q_max from eps); returns the
+        number of refreshes."""
+        n = ctypes.c_int()
+        _check("herk_run", lib().herk_run(handle(self.u.device.index), ctypes.byref(self.c), int(nsteps), float(eps),
+                                          int(q_cap), ctypes.byref(n), _stream(self.u)))
+        return n.value
 
 
 def herk_step_batched(states: list) -> None:

@@ -127,7 +127,7 @@ struct nslgf_ctx {
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
-    nslgf::DevBuf if_tmp1, if_tmp2, tmp3, partial;
+    nslgf::DevBuf if_tmp1, if_tmp2, tmp3, tmp3b, partial;
 };
 
 namespace nslgf {
@@ -928,6 +928,118 @@ int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx
     NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
     NSLGF_TRY(run_conv_shared(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
     NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s));
+    return NSLGF_OK;
+}
+
+// u = Cbar a, a = -L^{-1} w, w = M_supp C u, through two 3-component temporaries.
+static int refresh_into(nslgf_t h, void* u, int nx, int ny, int nz, int n_buf, double dx, int dtype, void* wbuf,
+                        void* abuf, hipStream_t s) {
+    ConvPlan* p = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
+    NSLGF_PROF(h, "curl_masked", s, launch_masked_curl(dtype, u, wbuf, n_buf, nx, ny, nz, dx, s));
+    NSLGF_TRY(run_conv_shared(h, *p, wbuf, abuf, 3, -dx * dx, s));
+    NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, abuf, u, 3, nx, ny, nz, dx, s));
+    return NSLGF_OK;
+}
+
+static int max_abs_host(nslgf_t h, const void* u, int nx, int ny, int nz, int n_buf, int dtype, double* out,
+                        hipStream_t s) {
+    const int nb = 1024;
+    NSLGF_TRY(h->partial.ensure(nb * sizeof(double)));
+    NSLGF_TRY(launch_max_abs(dtype, u, n_buf, nx, ny, nz, (double*)h->partial.p, nb, s));
+    std::vector<double> host(nb);
+    NSLGF_HIP_CHECK(hipMemcpyAsync(host.data(), h->partial.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    double m = 0.0;
+    for (double v : host) m = v > m ? v : m;
+    *out = m;
+    return NSLGF_OK;
+}
+
+int if_trunc_error(double alpha, int k, double* out) {
+    NSLGF_CHECK_ARG(out != nullptr, "if_trunc_error: null output");
+    NSLGF_CHECK_ARG(std::isfinite(alpha) && alpha >= 0.0, "if_trunc_error: alpha must be a finite value >= 0");
+    NSLGF_CHECK_ARG(k >= 1, "if_trunc_error: k must be >= 1");
+    *out = if_trunc_error_host(alpha, k);
+    return NSLGF_OK;
+}
+
+int refresh_interval(double beta, int n_buf, double umax, double eps, int q_cap, int* q_max) {
+    NSLGF_CHECK_ARG(q_max != nullptr, "refresh_interval: null output");
+    NSLGF_CHECK_ARG(std::isfinite(beta) && beta >= 0.0, "refresh_interval: beta must be a finite value >= 0");
+    NSLGF_CHECK_ARG(n_buf >= 0, "refresh_interval: n_buf must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(umax) && umax >= 0.0, "refresh_interval: umax must be a finite value >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(eps) && eps > 0.0, "refresh_interval: eps must be > 0");
+    NSLGF_CHECK_ARG(q_cap >= 1, "refresh_interval: q_cap must be >= 1");
+    *q_max = refresh_interval_host(beta, n_buf, umax, eps, q_cap);
+    return NSLGF_OK;
+}
+
+int max_component_abs(nslgf_t h, const void* u, int nx, int ny, int nz, int n_buf, int dtype, double* out,
+                      void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(u && out, "max_component_abs: null pointer");
+    NSLGF_CHECK_ARG(n_buf >= 0, "max_component_abs: n_buf must be >= 0");
+    return max_abs_host(h, u, nx, ny, nz, n_buf, dtype, out, (hipStream_t)stream);
+}
+
+int velocity_refresh(nslgf_t h, void* u, int nx, int ny, int nz, int n_buf, double dx, int dtype, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(u != nullptr, "velocity_refresh: null pointer");
+    NSLGF_CHECK_ARG(n_buf >= 0, "velocity_refresh: n_buf must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "velocity_refresh: dx must be > 0");
+    const size_t bytes = (size_t)3 * nx * ny * nz * dtype_size(dtype);
+    NSLGF_TRY(h->tmp3.ensure(bytes));
+    NSLGF_TRY(h->tmp3b.ensure(bytes));
+    return refresh_into(h, u, nx, ny, nz, n_buf, dx, dtype, h->tmp3b.p, h->tmp3.p, (hipStream_t)stream);
+}
+
+int herk_run(nslgf_t h, nslgf_state* st, int nsteps, double eps, int q_cap, int* refreshes, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(st != nullptr, "herk_run: null state");
+    NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+    NSLGF_TRY(check_dtype(st->dtype));
+    NSLGF_CHECK_ARG(st->u && st->d && st->work, "herk_run: null u, d or work");
+    NSLGF_CHECK_ARG(nsteps >= 0, "herk_run: nsteps must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(eps) && eps > 0.0, "herk_run: eps must be > 0");
+    NSLGF_CHECK_ARG(q_cap >= 1, "herk_run: q_cap must be >= 1");
+    NSLGF_CHECK_ARG(std::isfinite(st->dt) && st->dt > 0 && std::isfinite(st->dx) && st->dx > 0 &&
+                        std::isfinite(st->re) && st->re > 0 && st->n_buf >= 0,
+                    "herk_run: dt, dx and re must be > 0 and n_buf >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int nx = st->nx, ny = st->ny, nz = st->nz, dt_ = st->dtype;
+    const double beta = st->dt / (st->dx * st->dx * st->re);
+    // the refresh works in the state's IF temporaries (6 components), which no stage keeps
+    const StateLayout L = state_layout(nx, ny, nz);
+    const size_t es = dtype_size(dt_);
+    char* wbase = (char*)st->work + L.t1 * es;
+    char* abase = wbase + (size_t)3 * nx * ny * nz * es;
+    auto interval = [&](int* q) -> int {
+        double umax = 0.0;
+        NSLGF_TRY(max_abs_host(h, st->u, nx, ny, nz, st->n_buf, dt_, &umax, s));
+        *q = refresh_interval_host(beta, st->n_buf, umax, eps, q_cap);
+        if (*q == 0) {
+            set_error("herk_run: the buffer is too thin for eps (one step already exceeds it)");
+            return NSLGF_EINVAL;
+        }
+        return NSLGF_OK;
+    };
+    int q_max = 0, count = 0, nref = 0;
+    NSLGF_TRY(interval(&q_max));
+    for (int n = 0; n < nsteps; ++n) {
+        NSLGF_TRY(herk_step(h, st, stream));
+        if (++count == q_max) {
+            NSLGF_TRY(refresh_into(h, st->u, nx, ny, nz, st->n_buf, st->dx, dt_, wbase, abase, s));
+            ++nref;
+            count = 0;
+            NSLGF_TRY(interval(&q_max));
+        }
+    }
+    if (refreshes) *refreshes = nref;
     return NSLGF_OK;
 }
 

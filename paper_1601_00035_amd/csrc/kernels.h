@@ -108,6 +108,12 @@ struct IfCombine {
 int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
                  int radius, hipStream_t s);
 
+// ---- velocity refresh cadence (refresh.hip) -----------------------------------------------------
+// d_a(k) = sum_{n >= k} e^{-2a} I_n(2a) (k >= 1, a >= 0)
+double if_trunc_error_host(double alpha, int k);
+// largest q <= q_cap with umax d_{q beta}(n_buf + 1) <= eps
+int refresh_interval_host(double beta, int n_buf, double umax, double eps, int q_cap);
+
 // ---- stencils (stencils.hip) --------------------------------------------------------------------
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
                    hipStream_t s);
@@ -136,6 +142,11 @@ int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, d
                  long long n, hipStream_t s);
 // plain 16-byte-vector copy of `bytes` (multiple of 16)
 int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
+// e = M_supp C f (edges closer than nbuf points to a box face set to 0)
+int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, int nx, int ny, int nz, double dx, hipStream_t s);
+// per-workgroup maxima of |u^(q)| over the three components on the box shrunk by nbuf points
+int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
+                   hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);

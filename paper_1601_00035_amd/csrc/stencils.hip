@@ -123,11 +123,14 @@ __global__ void __launch_bounds__(256) k_div(const T* f, T* c, int nx, int ny, i
     c[idx] = in_supp ? v : (T)0;
 }
 
+// e = C f on the box; with nbuf > 0, e = M_supp C f: edges closer than nbuf points to a box face
+// (outside the support domain, the box shrunk by nbuf points) are set to 0.
 template <typename T>
-__global__ void __launch_bounds__(256) k_curl(const T* f, T* e, int nx, int ny, int nz, T idx_) {
+__global__ void __launch_bounds__(256) k_curl(const T* f, T* e, int nx, int ny, int nz, T idx_, int nbuf) {
     NSLGF_CELL_INDEX
     Vec3<T> F = vec3(f, nx, ny, nz);
-    for (int q = 0; q < 3; ++q) e[q * n + idx] = curl_at(F, q, i, j, k, idx_);
+    const bool in_supp = i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf;
+    for (int q = 0; q < 3; ++q) e[q * n + idx] = in_supp ? curl_at(F, q, i, j, k, idx_) : (T)0;
 }
 
 template <typename T>
@@ -268,6 +271,31 @@ __global__ void __launch_bounds__(256) k_max_speed(const T* u, int nx, int ny, i
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Largest |u^(q)| over the three components on the solution domain (the box shrunk by nbuf points);
+// one partial maximum per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(256) k_max_abs(const T* u, int nx, int ny, int nz, int nbuf, double* partial) {
+    const long long n = (long long)nx * ny * nz;
+    __shared__ double red[256];
+    double m = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < 3 * n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long p = idx % n;
+        const int i = (int)(p % nx);
+        const int j = (int)((p / nx) % ny);
+        const int k = (int)(p / ((long long)nx * ny));
+        if (i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf)
+            m = fmax(m, fabs((double)u[idx]));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // ---------------------------------------------------------------------------------------------------
 template <typename T>
 static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
@@ -277,7 +305,7 @@ static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int 
     switch (op) {
         case NSLGF_OP_GRAD: hipLaunchKernelGGL(k_grad<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_DIV: hipLaunchKernelGGL(k_div<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
-        case NSLGF_OP_CURL: hipLaunchKernelGGL(k_curl<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
+        case NSLGF_OP_CURL: hipLaunchKernelGGL(k_curl<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
         case NSLGF_OP_CURL_BAR: hipLaunchKernelGGL(k_curl_bar<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_NONLINEAR: hipLaunchKernelGGL(k_nonlinear<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_LAPLACIAN:
@@ -348,6 +376,29 @@ int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, d
     else
         hipLaunchKernelGGL(k_axpby<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (double*)out, (const double*)x, a,
                            (const double*)y, b, (const double*)z, c, n);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, int nx, int ny, int nz, double dx, hipStream_t s) {
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_curl<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)f, (float*)e, nx, ny,
+                           nz, (float)(1.0 / dx), nbuf);
+    else
+        hipLaunchKernelGGL(k_curl<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)f, (double*)e, nx,
+                           ny, nz, 1.0 / dx, nbuf);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
+                   hipStream_t s) {
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_max_abs<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, nbuf,
+                           dev_partial);
+    else
+        hipLaunchKernelGGL(k_max_abs<double>, dim3(nblocks), dim3(256), 0, s, (const double*)u, nx, ny, nz, nbuf,
+                           dev_partial);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
