@@ -4,7 +4,9 @@ staggered box.  Test infrastructure only.
     I = 1/2 int x cross w,   K = int u . (x cross w),   E = 1/2 int |w|^2,   J = int u . w,
     X = 1/2 int ((x cross w) . I / |I|^2) x,            (u_inf = 0)
 
-with the vorticity w = C u on the edges of the box and zero outside it (the footnote of Sec. 6.2).
+with the vorticity w = M_supp C u: zero outside the box (the footnote of Sec. 6.2) and on the edges
+closer than n_buf points to a face, where the curl of the zero-extended velocity is not the flow's
+vorticity (the velocity does not vanish at the faces, so the outermost edges see a spurious jump).
 
 Discretisation (a reading; the paper does not spell it out): every integral is a sum over the box
 times dx^3.  I, E and X are linear or quadratic in w alone, so each of their terms is taken at the
@@ -20,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import stencils
+from . import ifherk, stencils
 
 
 def _coords(shape, dx, origin, back):
@@ -67,9 +69,10 @@ def integrals(u: np.ndarray, w: np.ndarray, dx: float, origin) -> dict:
     return {"I": I, "K": K, "E": E, "J": J, "X": X}
 
 
-def of_velocity(u: np.ndarray, dx: float, origin) -> dict:
-    """The integrals of a face velocity u with its own vorticity w = C u."""
-    return integrals(u, stencils.curl(u, dx), dx, origin)
+def of_velocity(u: np.ndarray, dx: float, origin, n_buf: int) -> dict:
+    """The integrals of a face velocity u with its own vorticity w = M_supp C u (support = box shrunk
+    by n_buf points)."""
+    return integrals(u, ifherk.inner_mask(u.shape[1:], n_buf) * stencils.curl(u, dx), dx, origin)
 
 
 def box_origin(shape, dx):

@@ -8,6 +8,7 @@ import pytest
 
 import workloads
 from oracle import diagnostics as dg
+from oracle import ifherk
 
 R, SIG, DX, N = 1.0, 0.3, 0.05, 96
 
@@ -62,6 +63,25 @@ def test_uniform_velocity_ties_cell_centre_sums_to_edge_sums(ring_w):
     rot = np.stack([np.cross(om, np.stack(pos[q]), axis=0)[q] for q in range(3)])
     r3 = dg.integrals(rot, w, DX, o)
     assert abs(r3["J"] - 2 * om @ np.array(r3["I"])) < 1e-9 * abs(r3["J"])
+
+
+def test_integrals_of_the_vor2vel_velocity():
+    """Vor2Vel then the masked curl gives back the sampled vorticity inside the box (C Cbar (-L^{-1})
+    is the identity on a divergence-free w), so the integrals of u = Vor2Vel(w) with one masked layer
+    equal those of w; without the mask the curl of the truncated velocity at the outermost edges
+    dominates them."""
+    n, dx = 24, 4.4 / 24
+    w = workloads.ring_edge_vorticity(n, dx, workloads.Ring(R=1.0, sigma=0.3))
+    o = dg.box_origin(w.shape[1:], dx)
+    u = ifherk.vor2vel(w, dx)
+    ref = dg.integrals(u, w, dx, o)
+    got = dg.of_velocity(u, dx, o, 1)
+    for key in ("K", "E"):
+        assert abs(got[key] / ref[key] - 1) < 1e-5, key
+    assert abs(got["I"][2] / ref["I"][2] - 1) < 1e-5
+    assert abs(dg.of_velocity(u, dx, o, 0)["I"][2] / ref["I"][2] - 1) > 0.5
+    # K > 0 is the kinetic energy of the ring (Sec. 6.2), J = 0 without swirl
+    assert got["K"] > 0 and abs(got["J"]) < 1e-9 * got["K"]
 
 
 def test_saffman_speed_constants():
