@@ -366,6 +366,27 @@ def main():
                                          "cadence_by_eps_over_umax": cadence}
         del ur
         torch.cuda.empty_cache()
+        # vortex-ring integrals (Sec. 6.2) and the ring speed over the first step against Saffman's
+        # thin-ring formula (Sec. 6.3): U = Gamma / (4 pi R) (log(8 R / sigma) - beta_0)
+        origin = (-(n - 1) / 2.0 * dx,) * 3
+        ud = nslgf.vor2vel(w, dx)
+        d0 = nslgf.flow_diagnostics(ud, dx, origin, 16)
+        sd = nslgf.HerkState(ud, dx, dt, re, "A", n_buf=16)
+        sd.step()
+        d1 = nslgf.flow_diagnostics(ud, dx, origin, 16)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            nslgf.flow_diagnostics(ud, dx, origin, 16)
+        ms_diag = (time.perf_counter() - t0) / 5 * 1e3
+        uz = (d1["X"][2] - d0["X"][2]) / dt
+        beta0 = 0.5 * (1.0 - 0.5772156649015329 + math.log(2.0))
+        us = ring.gamma / (4 * math.pi * ring.R) * (math.log(8 * ring.R / ring.sigma) - beta0)
+        secondary["ring_diagnostics"] = {"ms_incl_sync": round(ms_diag, 4), "I_z": d0["I"][2], "K": d0["K"],
+                                         "E": d0["E"], "J": d0["J"], "U_z_first_step": uz, "U_saffman": us,
+                                         "rel_diff": (uz - us) / us,
+                                         "I_z_change_first_step": d1["I"][2] / d0["I"][2] - 1}
+        del ud, sd
+        torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
                                 "fp32": batched_measure(nslgf, torch, torch.float32)}

@@ -202,6 +202,24 @@ int velocity_refresh(nslgf_t h, void *u, int nx, int ny, int nz, int n_buf, doub
 int herk_run(nslgf_t h, nslgf_state *st, int nsteps, double eps, int q_cap, int *refreshes, void *stream);
 
 /*
+ * Volume integrals of an isolated vortex ring (Sec. 6.2, Eq. int_quantities, u_inf = 0) of the face
+ * velocity u [3][nz][ny][nx], with the vorticity w = M_supp C u: zero outside the box and on the edges
+ * closer than n_buf points to a face (n_buf >= 1 removes the outermost edges, where the curl of the
+ * zero-extended velocity sees a spurious jump):
+ *     out[0..2] impulse I = 1/2 int x cross w     out[3] kinetic energy K = int u . (x cross w)
+ *     out[4] enstrophy E = 1/2 int |w|^2          out[5] helicity J = int u . w
+ *     out[6..8] centroid X = 1/2 int ((x cross w) . I / |I|^2) x   (NaN when I = 0)
+ * Each integral is a sum over the box times dx^3.  I, E and X take every term at the edge of the
+ * vorticity component it contains; K and J average u (two faces) and w (four edges) to the cell
+ * centres.  origin[3] = coordinates of vertex (0, 0, 0); face (q) sits half a cell back on the two
+ * other axes, edge (q) half a cell back along q.  The ring speed is the centroid's rate of change,
+ * U = dX/dt (by differences of X between steps).  Sums in FP64 for both dtypes, reduced in a fixed
+ * order (deterministic).  Synchronises `stream`.
+ */
+int flow_diagnostics(nslgf_t h, const void *u, int nx, int ny, int nz, int n_buf, double dx, const double *origin,
+                     int dtype, double *out, void *stream);
+
+/*
  * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
  *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
  *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])

@@ -76,6 +76,7 @@ def lib():
                     "max_component_abs": [vp, vp, i, i, i, i, i, ctypes.POINTER(d), vp],
                     "velocity_refresh": [vp, vp, i, i, i, i, d, i, vp],
                     "herk_run": [vp, ctypes.POINTER(_State), i, d, i, ctypes.POINTER(i), vp],
+                    "flow_diagnostics": [vp, vp, i, i, i, i, d, ctypes.POINTER(d), i, ctypes.POINTER(d), vp],
                 }
                 for name, args in sig.items():
                     f = getattr(L, name)
@@ -259,6 +260,20 @@ def velocity_refresh(u: torch.Tensor, dx: float, n_buf: int) -> torch.Tensor:
     _check("velocity_refresh", lib().velocity_refresh(handle(u.device.index), u.data_ptr(), nx, ny, nz, int(n_buf),
                                                       float(dx), _dtype(u), _stream(u)))
     return u
+
+
+def flow_diagnostics(u: torch.Tensor, dx: float, origin, n_buf: int) -> dict:
+    """Impulse I, energy K, enstrophy E, helicity J and centroid X of the face velocity u (vorticity
+    C u on the box shrunk by n_buf points, zero elsewhere); origin = coordinates of vertex (0, 0, 0).
+    Synchronises the stream."""
+    _dev(u, "u")
+    _, nz, ny, nx = u.shape
+    org = (ctypes.c_double * 3)(*[float(v) for v in origin])
+    out = (ctypes.c_double * 9)()
+    _check("flow_diagnostics", lib().flow_diagnostics(handle(u.device.index), u.data_ptr(), nx, ny, nz, int(n_buf),
+                                                      float(dx), org, _dtype(u), out, _stream(u)))
+    v = list(out)
+    return {"I": v[0:3], "K": v[3], "E": v[4], "J": v[5], "X": v[6:9]}
 
 
 FFT_PLAN_AUTOTUNE = -2

@@ -1043,6 +1043,42 @@ int herk_run(nslgf_t h, nslgf_state* st, int nsteps, double eps, int q_cap, int*
     return NSLGF_OK;
 }
 
+int flow_diagnostics(nslgf_t h, const void* u, int nx, int ny, int nz, int n_buf, double dx, const double* origin,
+                     int dtype, double* out, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(u && origin && out, "flow_diagnostics: null pointer");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "flow_diagnostics: dx must be > 0");
+    NSLGF_CHECK_ARG(n_buf >= 0, "flow_diagnostics: n_buf must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(origin[0]) && std::isfinite(origin[1]) && std::isfinite(origin[2]),
+                    "flow_diagnostics: origin must be finite");
+    const int nb = 1024;
+    NSLGF_TRY(h->partial.ensure((size_t)nb * kDiagnosticSums * sizeof(double)));
+    hipStream_t s = (hipStream_t)stream;
+    NSLGF_PROF(h, "diagnostics", s, launch_diagnostics(dtype, u, n_buf, nx, ny, nz, dx, origin, (double*)h->partial.p, nb, s));
+    std::vector<double> host((size_t)nb * kDiagnosticSums);
+    NSLGF_HIP_CHECK(hipMemcpyAsync(host.data(), h->partial.p, host.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    double sum[kDiagnosticSums] = {};
+    for (int b = 0; b < nb; ++b)  // fixed order: the result does not depend on scheduling
+        for (int v = 0; v < kDiagnosticSums; ++v) sum[v] += host[(size_t)b * kDiagnosticSums + v];
+    const double dv = dx * dx * dx;
+    double I[3];
+    for (int q = 0; q < 3; ++q) I[q] = 0.5 * dv * sum[q];
+    const double I2 = I[0] * I[0] + I[1] * I[1] + I[2] * I[2];
+    for (int q = 0; q < 3; ++q) out[q] = I[q];
+    out[3] = dv * sum[13];        // K
+    out[4] = 0.5 * dv * sum[12];  // E
+    out[5] = dv * sum[14];        // J
+    for (int p = 0; p < 3; ++p) {  // X (undefined without impulse: NaN)
+        double m = 0.0;
+        for (int q = 0; q < 3; ++q) m += I[q] * sum[3 + 3 * q + p];
+        out[6 + p] = I2 > 0.0 ? 0.5 * dv * m / I2 : std::nan("");
+    }
+    return NSLGF_OK;
+}
+
 int stencil_apply(nslgf_t h, int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
                   void* stream) {
     NSLGF_ENTER(h);

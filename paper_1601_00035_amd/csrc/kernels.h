@@ -147,6 +147,11 @@ int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, int nx, int 
 // per-workgroup maxima of |u^(q)| over the three components on the box shrunk by nbuf points
 int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
                    hipStream_t s);
+// 15 raw sums of the vortex-ring integrals per workgroup into dev_partial[nblocks][15] (order in
+// stencils.hip), vorticity restricted to the box shrunk by nbuf; origin = coordinates of vertex (0, 0, 0)
+constexpr int kDiagnosticSums = 15;
+int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double dx, const double origin[3],
+                       double* dev_partial, int nblocks, hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);

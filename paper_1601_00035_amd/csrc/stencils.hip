@@ -296,6 +296,82 @@ __global__ void __launch_bounds__(256) k_max_abs(const T* u, int nx, int ny, int
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Volume integrals of an isolated vortex ring (Sec. 6.2, Eq. int_quantities) as 15 raw sums over the
+// box, one set of partial sums per workgroup (partial[blockIdx.x * kDiagnosticSums + v]):
+//   0..2   S_q    = sum (x cross w)_q              (I = dx^3 S / 2)
+//   3..11  M_qp   = sum (x cross w)_q x_p          (X = dx^3 sum_q I_q M_q. / (2 |I|^2))
+//   12     sum |w|^2                               (E = dx^3 sum / 2)
+//   13     sum u_c . (x_c cross w_c)               (K = dx^3 sum)
+//   14     sum u_c . w_c                           (J = dx^3 sum)
+// with w = M_supp C u: zero outside the box and on edges closer than nbuf points to a face (there the
+// curl of the zero-extended velocity sees a spurious jump).  The terms of S, M and |w|^2 are taken at the edge of
+// each vorticity component (edge (q) is half a cell back along axis q); K and J average u (two faces)
+// and w (four edges) to the cell centres.  Point (i, j, k) with offsets -1/2 on the flagged axes sits
+// at origin + (i, j, k) dx - dx/2 on those axes.
+template <typename T>
+__device__ __forceinline__ double edge_w(const Vec3<T>& U, int q, int i, int j, int k, int nx, int ny, int nz, T idx,
+                                         int nbuf) {
+    if (i < nbuf || j < nbuf || k < nbuf || i >= nx - nbuf || j >= ny - nbuf || k >= nz - nbuf) return 0.0;
+    return (double)curl_at(U, q, i, j, k, idx);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_diagnostics(const T* u, int nx, int ny, int nz, int nbuf, T idx, double dx,
+                                                     double ox, double oy, double oz, double* partial) {
+    const long long n = (long long)nx * ny * nz;
+    const Vec3<T> U = vec3(u, nx, ny, nz);
+    double acc[kDiagnosticSums];
+#pragma unroll
+    for (int v = 0; v < kDiagnosticSums; ++v) acc[v] = 0.0;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(p % nx);
+        const int j = (int)((p / nx) % ny);
+        const int k = (int)(p / ((long long)nx * ny));
+        const double xi = ox + i * dx, yj = oy + j * dx, zk = oz + k * dx;
+        const double h = 0.5 * dx;
+        // the three edges (i, j, k) and their positions: edge (q) is half a cell back along q
+        const double w[3] = {edge_w(U, 0, i, j, k, nx, ny, nz, idx, nbuf), edge_w(U, 1, i, j, k, nx, ny, nz, idx, nbuf),
+                             edge_w(U, 2, i, j, k, nx, ny, nz, idx, nbuf)};
+        const double pe[3][3] = {{xi - h, yj, zk}, {xi, yj - h, zk}, {xi, yj, zk - h}};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int a = (q + 1) % 3, b = (q + 2) % 3;
+            // (x cross w)_q = x_a w_b - x_b w_a, each term at its own edge
+            const double tb = pe[b][a] * w[b], ta = pe[a][b] * w[a];
+            acc[q] += tb - ta;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[3 + 3 * q + c] += tb * pe[b][c] - ta * pe[a][c];
+        }
+        acc[12] += w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        // cell centre
+        const double uc[3] = {0.5 * ((double)U.c[0](i, j, k) + (double)U.c[0](i - 1, j, k)),
+                              0.5 * ((double)U.c[1](i, j, k) + (double)U.c[1](i, j - 1, k)),
+                              0.5 * ((double)U.c[2](i, j, k) + (double)U.c[2](i, j, k - 1))};
+        const double wc[3] = {
+            0.25 * (w[0] + edge_w(U, 0, i, j - 1, k, nx, ny, nz, idx, nbuf) + edge_w(U, 0, i, j, k - 1, nx, ny, nz, idx, nbuf) +
+                    edge_w(U, 0, i, j - 1, k - 1, nx, ny, nz, idx, nbuf)),
+            0.25 * (w[1] + edge_w(U, 1, i, j, k - 1, nx, ny, nz, idx, nbuf) + edge_w(U, 1, i - 1, j, k, nx, ny, nz, idx, nbuf) +
+                    edge_w(U, 1, i - 1, j, k - 1, nx, ny, nz, idx, nbuf)),
+            0.25 * (w[2] + edge_w(U, 2, i - 1, j, k, nx, ny, nz, idx, nbuf) + edge_w(U, 2, i, j - 1, k, nx, ny, nz, idx, nbuf) +
+                    edge_w(U, 2, i - 1, j - 1, k, nx, ny, nz, idx, nbuf))};
+        const double xc[3] = {xi - h, yj - h, zk - h};
+        const double xw[3] = {xc[1] * wc[2] - xc[2] * wc[1], xc[2] * wc[0] - xc[0] * wc[2],
+                              xc[0] * wc[1] - xc[1] * wc[0]};
+        acc[13] += uc[0] * xw[0] + uc[1] * xw[1] + uc[2] * xw[2];
+        acc[14] += uc[0] * wc[0] + uc[1] * wc[1] + uc[2] * wc[2];
+    }
+    __shared__ double red[kDiagnosticSums][256];
+#pragma unroll
+    for (int v = 0; v < kDiagnosticSums; ++v) red[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int v = 0; v < kDiagnosticSums; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + s];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < kDiagnosticSums) partial[(long long)blockIdx.x * kDiagnosticSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
 // ---------------------------------------------------------------------------------------------------
 template <typename T>
 static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
@@ -399,6 +475,18 @@ int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, d
     else
         hipLaunchKernelGGL(k_max_abs<double>, dim3(nblocks), dim3(256), 0, s, (const double*)u, nx, ny, nz, nbuf,
                            dev_partial);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double dx, const double origin[3],
+                       double* dev_partial, int nblocks, hipStream_t s) {
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_diagnostics<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, nbuf,
+                           (float)(1.0 / dx), dx, origin[0], origin[1], origin[2], dev_partial);
+    else
+        hipLaunchKernelGGL(k_diagnostics<double>, dim3(nblocks), dim3(256), 0, s, (const double*)u, nx, ny, nz, nbuf,
+                           1.0 / dx, dx, origin[0], origin[1], origin[2], dev_partial);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
