@@ -115,6 +115,42 @@ def test_stokes_case_gpu():
     assert rel(u.cpu().numpy(), expect) < 1e-7
 
 
+@pytest.mark.parametrize("scheme", ["A", "B", "C"])
+def test_temporal_order_gpu(scheme, paper_values):
+    """The GPU step alone (no oracle run): velocity and pressure errors at a fixed time against a
+    dt/16 run fall with the orders of Table 1 (A: 2, 2; B: 3, 2; C: 3, 1), for a compactly supported
+    initial velocity on a small box."""
+    import math
+    n, dx, re, n_buf = 16, 0.3, 100.0, 2
+    a = np.zeros((3, n, n, n))
+    a[:, 5:-5, 5:-5, 5:-5] = workloads.random_field((3, n - 10, n - 10, n - 10), 7)
+    u0 = stencils.curl_bar(a, dx)
+    u0 = u0 * (0.5 / np.abs(u0).max())
+    T = ifherk.dt_from_cfl(u0, dx, 0.5)
+
+    def run(m):
+        u = torch.from_numpy(u0).to(DEV)
+        st = nslgf.HerkState(u, dx, T / m, re, scheme, n_buf=n_buf)
+        for _ in range(m):
+            st.step()
+        return u.cpu().numpy(), st.d.cpu().numpy()
+
+    ref, dref = run(16)
+    eu, ed = [], []
+    for m in (2, 4, 8):
+        u, d = run(m)
+        eu.append(np.abs(u - ref).max())
+        ed.append(np.abs(d - dref).max())
+    want = paper_values["scheme_orders"][scheme]
+    for var, e in (("y", eu), ("z", ed)):
+        p = want[var]
+        # apparent orders against a finite reference (2, 4, 8 steps against 16)
+        ex = [2.0 ** (-p * k) - 16.0 ** (-p) for k in (1, 2, 3)]
+        expect = (math.log2(ex[0] / ex[1]), math.log2(ex[1] / ex[2]))
+        got = (math.log2(e[0] / e[1]), math.log2(e[1] / e[2]))
+        assert all(abs(g - x) < 0.3 for g, x in zip(got, expect)), (var, got, expect)
+
+
 @pytest.mark.parametrize("case", ["step128", "conv256"])
 def test_full_size_step_properties(case):
     """Full-size steps in the benchmark's configuration (FP64, Scheme A, n_buf 16): the 128^3 ring
