@@ -41,7 +41,7 @@ GIB = float(1 << 30)
 # (pressure); its dispatches are grouped by grid size (a launch over c components has c times the
 # grid) and weighted by that mix.  if_xy runs four different launches per step (and nowhere else), so
 # its dispatches are averaged as they come.
-KERNELS = {"conv_z_fused": "nslgf::k_col<double, 512, 2, 2>", "if_xy": "nslgf::k_if_xy<double,"}
+KERNELS = {"conv_z_fused": "nslgf::k_col<double, 512, 2, 2,", "if_xy": "nslgf::k_if_xy<double,"}
 STEP_MIX = {"conv_z_fused": {3: 1, 1: 3}, "if_xy": None}
 
 
