@@ -387,6 +387,20 @@ def main():
                                          "I_z_change_first_step": d1["I"][2] / d0["I"][2] - 1}
         del ud, sd
         torch.cuda.empty_cache()
+        # active-domain block weights (Sec. 4.3) of the 256^3 ring: how much of the box the support,
+        # solution and expanded-solution blocks keep (blocks of 16^3 cells, one buffer block)
+        mu, nu = nslgf.block_weights(u, dx, 16, 16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            nslgf.block_weights(u, dx, 16, 16)
+        ms_bw = (time.perf_counter() - t0) / 5 * 1e3
+        frac = {}
+        for eps in (1e-2, 1e-4, 1e-6):
+            _, sp, so, xs = nslgf.classify_blocks(mu, nu, eps, eps, 1)
+            frac[f"{eps:g}"] = {"supp": round(float(sp.mean()), 4), "xsoln": round(float(xs.mean()), 4)}
+        secondary["active_domain"] = {"block": 16, "blocks": int(mu.size), "ms_incl_sync": round(ms_bw, 4),
+                                      "fraction_of_box_by_eps": frac}
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
                                 "fp32": batched_measure(nslgf, torch, torch.float32)}

@@ -220,6 +220,29 @@ int flow_diagnostics(nslgf_t h, const void *u, int nx, int ny, int nz, int n_buf
                      int dtype, double *out, void *stream);
 
 /*
+ * Block weights of the active domain (Sec. 4.3, Eq. weight_fun) for the face velocity u [3][nz][ny][nx]:
+ * the box is tiled by blocks of nb^3 cells from its origin (Sec. 4.2; the last block along an axis may
+ * be shorter), giving a block grid bx = ceil(nx/nb), by, bz; for each block (x fastest)
+ *     mu = max |(C u)^(q)| over its edges and components,   nu = max |G^T Ntilde(u)| over its cells,
+ * both over the points at least n_buf away from every box face (the values the finite box has
+ * contaminated are left out, as the section does before taking the weights).  mu, nu: host arrays of
+ * bx * by * bz doubles, owned by the caller.  Synchronises `stream`.
+ */
+int block_weights(nslgf_t h, const void *u, int nx, int ny, int nz, int nb, int n_buf, double dx, int dtype,
+                  double *mu, double *nu, void *stream);
+
+/*
+ * Active-domain classification (Sec. 4.3, Eqs. d_supp, d_soln; Sec. 4.2, Eq. def_xsoln), host only:
+ *     W = max(mu / max(mu), nu / max(nu))  (a term with a zero maximum counts as 0),
+ *     supp = W > eps_supp,  soln = W > eps_soln,
+ *     xsoln = every block at most n_xb blocks from a soln block along each of the three axes.
+ * Arrays of bx * by * bz (x fastest), owned by the caller; W may be null; the masks get 0 or 1.
+ * Comparing the masks with those of the previous step tells whether the domain must be re-initialised.
+ */
+int classify_blocks(const double *mu, const double *nu, int bx, int by, int bz, double eps_supp, double eps_soln,
+                    int n_xb, double *W, unsigned char *supp, unsigned char *soln, unsigned char *xsoln);
+
+/*
  * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
  *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
  *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])

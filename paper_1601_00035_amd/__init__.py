@@ -14,6 +14,7 @@ import ctypes
 import os
 import threading
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -77,6 +78,8 @@ def lib():
                     "velocity_refresh": [vp, vp, i, i, i, i, d, i, vp],
                     "herk_run": [vp, ctypes.POINTER(_State), i, d, i, ctypes.POINTER(i), vp],
                     "flow_diagnostics": [vp, vp, i, i, i, i, d, ctypes.POINTER(d), i, ctypes.POINTER(d), vp],
+                    "block_weights": [vp, vp, i, i, i, i, i, d, i, vp, vp, vp],
+                    "classify_blocks": [vp, vp, i, i, i, d, d, i, vp, vp, vp, vp],
                 }
                 for name, args in sig.items():
                     f = getattr(L, name)
@@ -274,6 +277,35 @@ def flow_diagnostics(u: torch.Tensor, dx: float, origin, n_buf: int) -> dict:
                                                       float(dx), org, _dtype(u), out, _stream(u)))
     v = list(out)
     return {"I": v[0:3], "K": v[3], "E": v[4], "J": v[5], "X": v[6:9]}
+
+
+def block_weights(u: torch.Tensor, dx: float, nb: int, n_buf: int):
+    """(mu, nu) per block of nb^3 cells as numpy arrays [bz, by, bx]: the largest |C u| component and
+    |G^T Ntilde(u)| over the block, away from the box faces by n_buf points (synchronises the stream)."""
+    _dev(u, "u")
+    _, nz, ny, nx = u.shape
+    # (the library rejects nb < 1 before it writes anything)
+    shape = (-(-nz // nb), -(-ny // nb), -(-nx // nb)) if nb >= 1 else (1, 1, 1)
+    mu = np.zeros(shape)
+    nu = np.zeros(shape)
+    _check("block_weights", lib().block_weights(handle(u.device.index), u.data_ptr(), nx, ny, nz, int(nb), int(n_buf),
+                                                float(dx), _dtype(u), mu.ctypes.data, nu.ctypes.data, _stream(u)))
+    return mu, nu
+
+
+def classify_blocks(mu, nu, eps_supp: float, eps_soln: float, n_xb: int):
+    """(W, supp, soln, xsoln) block arrays from the weights (host evaluation)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    nu = np.ascontiguousarray(nu, dtype=np.float64)
+    if mu.shape != nu.shape or mu.ndim != 3:
+        raise ValueError("mu and nu must be block arrays [bz, by, bx] of one shape")
+    bz, by, bx = mu.shape
+    W = np.zeros(mu.shape)
+    masks = [np.zeros(mu.shape, dtype=np.uint8) for _ in range(3)]
+    _check("classify_blocks", lib().classify_blocks(mu.ctypes.data, nu.ctypes.data, bx, by, bz, float(eps_supp),
+                                                    float(eps_soln), int(n_xb), W.ctypes.data,
+                                                    *[m.ctypes.data for m in masks]))
+    return (W, *masks)
 
 
 FFT_PLAN_AUTOTUNE = -2

@@ -1079,6 +1079,45 @@ int flow_diagnostics(nslgf_t h, const void* u, int nx, int ny, int nz, int n_buf
     return NSLGF_OK;
 }
 
+int block_weights(nslgf_t h, const void* u, int nx, int ny, int nz, int nb, int n_buf, double dx, int dtype, double* mu,
+                  double* nu, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(u && mu && nu, "block_weights: null pointer");
+    NSLGF_CHECK_ARG(nb >= 1 && nb <= 256, "block_weights: nb must be 1..256");
+    NSLGF_CHECK_ARG(n_buf >= 0, "block_weights: n_buf must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "block_weights: dx must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const long long M = (long long)nx * ny * nz;
+    const long long nblocks = (long long)((nx + nb - 1) / nb) * ((ny + nb - 1) / nb) * ((nz + nb - 1) / nb);
+    NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
+    NSLGF_TRY(h->partial.ensure((size_t)2 * nblocks * sizeof(double)));
+    double* dmu = (double*)h->partial.p;
+    NSLGF_PROF(h, "nonlinear", s, launch_stencil(NSLGF_OP_NONLINEAR, dtype, u, h->tmp3.p, 3, nx, ny, nz, dx, s));
+    NSLGF_PROF(h, "block_weights", s,
+               launch_block_weights(dtype, u, h->tmp3.p, nx, ny, nz, nb, n_buf, dx, dmu, dmu + nblocks, s));
+    NSLGF_HIP_CHECK(hipMemcpyAsync(mu, dmu, nblocks * sizeof(double), hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipMemcpyAsync(nu, dmu + nblocks, nblocks * sizeof(double), hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    return NSLGF_OK;
+}
+
+int classify_blocks(const double* mu, const double* nu, int bx, int by, int bz, double eps_supp, double eps_soln,
+                    int n_xb, double* W, unsigned char* supp, unsigned char* soln, unsigned char* xsoln) {
+    NSLGF_CHECK_ARG(mu && nu && supp && soln && xsoln, "classify_blocks: null pointer");
+    NSLGF_CHECK_ARG(bx >= 1 && by >= 1 && bz >= 1, "classify_blocks: the block grid must be non-empty");
+    NSLGF_CHECK_ARG(std::isfinite(eps_supp) && std::isfinite(eps_soln) && eps_supp >= 0 && eps_soln >= 0,
+                    "classify_blocks: thresholds must be finite and >= 0");
+    NSLGF_CHECK_ARG(n_xb >= 0, "classify_blocks: n_xb must be >= 0");
+    const long long n = (long long)bx * by * bz;
+    for (long long b = 0; b < n; ++b)
+        NSLGF_CHECK_ARG(std::isfinite(mu[b]) && std::isfinite(nu[b]) && mu[b] >= 0 && nu[b] >= 0,
+                        "classify_blocks: weights must be finite and >= 0");
+    classify_blocks_host(mu, nu, bx, by, bz, eps_supp, eps_soln, n_xb, W, supp, soln, xsoln);
+    return NSLGF_OK;
+}
+
 int stencil_apply(nslgf_t h, int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
                   void* stream) {
     NSLGF_ENTER(h);

@@ -114,6 +114,12 @@ double if_trunc_error_host(double alpha, int k);
 // largest q <= q_cap with umax d_{q beta}(n_buf + 1) <= eps
 int refresh_interval_host(double beta, int n_buf, double umax, double eps, int q_cap);
 
+// ---- active domain (domain.hip) ---------------------------------------------------------------------
+// W = max(mu / max mu, nu / max nu) (W may be null), supp = W > eps_supp, soln = W > eps_soln,
+// xsoln = soln dilated by n_xb blocks along every axis (arrays of bx * by * bz, x fastest)
+void classify_blocks_host(const double* mu, const double* nu, int bx, int by, int bz, double eps_supp, double eps_soln,
+                          int n_xb, double* W, unsigned char* supp, unsigned char* soln, unsigned char* xsoln);
+
 // ---- stencils (stencils.hip) --------------------------------------------------------------------
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
                    hipStream_t s);
@@ -152,6 +158,10 @@ int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, d
 constexpr int kDiagnosticSums = 15;
 int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double dx, const double origin[3],
                        double* dev_partial, int nblocks, hipStream_t s);
+// per block of nb^3 cells: mu = max |(C u)^(q)|, nu = max |Dbar nl| (nl = Ntilde(u) on the box), over the
+// points at least nbuf away from every box face; dev_mu, dev_nu hold one value per block (x fastest)
+int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int ny, int nz, int nb, int nbuf, double dx,
+                         double* dev_mu, double* dev_nu, hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);

@@ -372,6 +372,46 @@ __global__ void __launch_bounds__(256) k_diagnostics(const T* u, int nx, int ny,
     if ((int)threadIdx.x < kDiagnosticSums) partial[(long long)blockIdx.x * kDiagnosticSums + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Block weights of the active domain (Sec. 4.3, Eq. weight_fun), one workgroup per block of nb^3
+// cells (blocks tile the box from its origin; the last along an axis may be shorter): mu = the largest
+// |(C u)^(q)| over the block's edges, nu = the largest |Dbar Ntilde(u)| over its cells (nl holds
+// Ntilde(u) on the box), both over the points at least nbuf away from every box face.
+template <typename T>
+__global__ void __launch_bounds__(256) k_block_weights(const T* u, const T* nl, int nx, int ny, int nz, int nb, int nbuf,
+                                                       T idx, double* mu, double* nu) {
+    const int bxn = (nx + nb - 1) / nb, byn = (ny + nb - 1) / nb;
+    const int b = (int)blockIdx.x;
+    const int bi = b % bxn, bj = (b / bxn) % byn, bk = b / (bxn * byn);
+    const Vec3<T> U = vec3(u, nx, ny, nz);
+    const Vec3<T> F = vec3(nl, nx, ny, nz);
+    double m1 = 0.0, m2 = 0.0;
+    const int cells = nb * nb * nb;
+    for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+        const int i = bi * nb + c % nb, j = bj * nb + (c / nb) % nb, k = bk * nb + c / (nb * nb);
+        if (i < nbuf || j < nbuf || k < nbuf || i >= nx - nbuf || j >= ny - nbuf || k >= nz - nbuf) continue;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) m1 = fmax(m1, fabs((double)curl_at(U, q, i, j, k, idx)));
+        const T d = (F.c[0](i, j, k) - F.c[0](i - 1, j, k) + F.c[1](i, j, k) - F.c[1](i, j - 1, k) + F.c[2](i, j, k) -
+                     F.c[2](i, j, k - 1)) * idx;
+        m2 = fmax(m2, fabs((double)d));
+    }
+    __shared__ double r1[256], r2[256];
+    r1[threadIdx.x] = m1;
+    r2[threadIdx.x] = m2;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + s]);
+            r2[threadIdx.x] = fmax(r2[threadIdx.x], r2[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        mu[b] = r1[0];
+        nu[b] = r2[0];
+    }
+}
+
 // ---------------------------------------------------------------------------------------------------
 template <typename T>
 static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
@@ -487,6 +527,19 @@ int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int n
     else
         hipLaunchKernelGGL(k_diagnostics<double>, dim3(nblocks), dim3(256), 0, s, (const double*)u, nx, ny, nz, nbuf,
                            1.0 / dx, dx, origin[0], origin[1], origin[2], dev_partial);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int ny, int nz, int nb, int nbuf, double dx,
+                         double* dev_mu, double* dev_nu, hipStream_t s) {
+    const long long nblocks = (long long)((nx + nb - 1) / nb) * ((ny + nb - 1) / nb) * ((nz + nb - 1) / nb);
+    if (dtype == NSLGF_F32)
+        hipLaunchKernelGGL(k_block_weights<float>, dim3((unsigned)nblocks), dim3(256), 0, s, (const float*)u,
+                           (const float*)nl, nx, ny, nz, nb, nbuf, (float)(1.0 / dx), dev_mu, dev_nu);
+    else
+        hipLaunchKernelGGL(k_block_weights<double>, dim3((unsigned)nblocks), dim3(256), 0, s, (const double*)u,
+                           (const double*)nl, nx, ny, nz, nb, nbuf, 1.0 / dx, dev_mu, dev_nu);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

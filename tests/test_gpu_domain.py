@@ -1,0 +1,62 @@
+"""GPU parity of the active-domain block weights (Sec. 4.3, Eq. weight_fun) against the oracle through
+the C ABI, their closed form for a rigid rotation, and the classification of a ring's blocks."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_00035_amd as nslgf
+import workloads
+from oracle import blocks, ifherk
+from oracle import diagnostics as dg
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.mark.parametrize("shape,nb,n_buf", [((24, 24, 24), 4, 2), ((20, 26, 22), 5, 1), ((16, 16, 16), 16, 0)])
+def test_block_weights_parity(shape, nb, n_buf):
+    nz, ny, nx = shape
+    dx = 4.4 / min(shape)
+    m = max(shape)
+    w = workloads.ring_edge_vorticity(m, dx, workloads.Ring(R=1.0, sigma=0.3, eps=0.05, seed=4))
+    o = (m - nx) // 2, (m - ny) // 2, (m - nz) // 2
+    w = np.ascontiguousarray(w[:, o[2]:o[2] + nz, o[1]:o[1] + ny, o[0]:o[0] + nx])
+    u = ifherk.vor2vel(w, dx)
+    mu_r, nu_r = blocks.weights(u, dx, nb, n_buf)
+    mu, nu = nslgf.block_weights(torch.from_numpy(u).to(DEV), dx, nb, n_buf)
+    assert mu.shape == mu_r.shape
+    assert np.abs(mu - mu_r).max() <= 1e-12 * mu_r.max()
+    assert np.abs(nu - nu_r).max() <= 1e-12 * nu_r.max()
+    mu32, nu32 = nslgf.block_weights(torch.from_numpy(u).to(DEV, torch.float32), dx, nb, n_buf)
+    assert np.abs(mu32 - mu_r).max() <= 1e-5 * mu_r.max()
+    assert np.abs(nu32 - nu_r).max() <= 1e-5 * nu_r.max()
+    # the classification of the GPU weights equals the oracle's wherever W is not within rounding of eps
+    eps = 1e-3
+    W_r, s_r, _, x_r = blocks.classify(mu_r, nu_r, eps, eps, 1)
+    W, s, _, x = nslgf.classify_blocks(mu, nu, eps, eps, 1)
+    clear = np.abs(W_r - eps) > 1e-9
+    assert np.array_equal(s[clear], s_r[clear])
+    assert np.abs(W - W_r).max() < 1e-11
+
+
+def test_block_weights_rigid_rotation():
+    shape, dx, nb, n_buf = (20, 16, 24), 0.25, 4, 3
+    om = np.array([0.3, -0.8, 0.5])
+    o = dg.box_origin(shape, dx)
+    u = []
+    for q in range(3):
+        X, Y, Z = dg._coords(shape, dx, o, [0 if a == q else 1 for a in range(3)])
+        u.append((om[1] * Z - om[2] * Y, om[2] * X - om[0] * Z, om[0] * Y - om[1] * X)[q])
+    u = torch.from_numpy(np.stack(u)).to(DEV)
+    mu, nu = nslgf.block_weights(u, dx, nb, n_buf)
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.abs(mu[inner] - 2 * np.abs(om).max()).max() < 1e-12
+    assert np.abs(nu[inner] - 4 * om @ om).max() < 1e-11
+
+
+def test_block_weights_errors():
+    u = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device=DEV)
+    for nb, n_buf, dx in ((0, 1, 0.1), (4, -1, 0.1), (4, 1, 0.0)):
+        with pytest.raises(nslgf.NslgfError):
+            nslgf.block_weights(u, dx, nb, n_buf)
