@@ -55,3 +55,12 @@ def classify(mu: np.ndarray, nu: np.ndarray, eps_supp: float, eps_soln: float, n
         xsoln[max(0, k - n_xb):min(bz, k + n_xb + 1), max(0, j - n_xb):min(by, j + n_xb + 1),
               max(0, i - n_xb):min(bx, i + n_xb + 1)] = 1
     return W, supp, soln, xsoln
+
+
+def cell_mask(block_mask: np.ndarray, nb: int, shape) -> np.ndarray:
+    """0/1 cell array of the box from a block mask [bz, by, bx] of nb^3-cell blocks (the union of the
+    blocks, Sec. 4.2)."""
+    m = np.repeat(np.repeat(np.repeat(block_mask.astype(np.float64), nb, axis=0), nb, axis=1), nb, axis=2)
+    nz, ny, nx = shape
+    return np.ascontiguousarray(m[:nz, :ny, :nx])
+

@@ -73,8 +73,10 @@ def inner_mask(shape, n_buf: int) -> np.ndarray:
 
 
 def step(u: np.ndarray, dt: float, dx: float, re: float, scheme: str = "A", nonlinear: bool = True,
-         n_buf: int = 0):
-    """One IF-HERK step.  Returns (u_{k+1}, d_{k+1}); both restricted to the box."""
+         n_buf: int = 0, soln_mask: np.ndarray | None = None, supp_mask: np.ndarray | None = None):
+    """One IF-HERK step.  Returns (u_{k+1}, d_{k+1}); both restricted to the box.  soln_mask and
+    supp_mask (0/1 cell arrays of the box, e.g. unions of blocks, Sec. 4.2) replace the box shrunk by
+    n_buf as the solution domain (nonlinear term) and the support domain (pressure source)."""
     at, ct = shifted(scheme)
     s = len(ct) - 1
     beta = dt / (dx * dx * re)
@@ -83,6 +85,8 @@ def step(u: np.ndarray, dt: float, dx: float, re: float, scheme: str = "A", nonl
         return intfac.apply_vec(x, (ct[i] - ct[i - 1]) * beta)
 
     msk = inner_mask(u.shape[1:], n_buf)
+    m_soln = msk if soln_mask is None else soln_mask
+    m_supp = msk if supp_mask is None else supp_mask
     q = {1: u}
     w = {}
     u_prev = u
@@ -93,13 +97,13 @@ def step(u: np.ndarray, dt: float, dx: float, re: float, scheme: str = "A", nonl
             for j in range(1, i):
                 w[(i, j)] = H(i - 1, w[(i - 1, j)])
         if nonlinear:
-            g = -at[i, i] * dt * msk * stencils.nonlinear(u_prev, dx)
+            g = -at[i, i] * dt * m_soln * stencils.nonlinear(u_prev, dx)
         else:
             g = np.zeros_like(u)
         r = q[i] + g
         for j in range(1, i):
             r = r + dt * at[i, j] * w[(i, j)]
-        dhat = lgf_solve(msk * stencils.div(r, dx), dx)
+        dhat = lgf_solve(m_supp * stencils.div(r, dx), dx)
         gd = stencils.grad(dhat, dx)
         u_prev = H(i, r - gd)
         w[(i, i)] = (g - gd) / (at[i, i] * dt)

@@ -2,7 +2,7 @@
 for a rigid rotation, the footprint of a point vortex, and the block counts of the expanded domain."""
 import numpy as np
 
-from oracle import blocks, stencils
+from oracle import blocks, ifherk, stencils
 from oracle import diagnostics as dg
 
 
@@ -59,3 +59,30 @@ def test_expanded_domain_clipped_at_the_box():
     # a higher solution threshold keeps the support but drops the block from D_soln
     W, supp, soln, xsoln = blocks.classify(mu, nu, 0.5, 1.0, 2)
     assert supp.sum() == 2 and soln.sum() == 0 and xsoln.sum() == 0
+
+
+def test_block_domains_in_the_step():
+    """The solution and support domains as unions of blocks (Sec. 4.2, 4.3) inside the IF-HERK step:
+    blocks equal to the box shrunk by n_buf reproduce the n_buf step exactly; a solution domain that
+    misses every block where the flow is leaves no nonlinear term, so the step is the Stokes step; a
+    support domain that misses the source gives no pressure."""
+    n, dx, nb = 16, 0.3, 4
+    f = np.zeros((3, n, n, n))
+    f[:, 6:10, 6:10, 6:10] = np.random.default_rng(3).standard_normal((3, 4, 4, 4))
+    u = stencils.curl_bar(f, dx)
+    dt, re = 0.05, 50.0
+    inner = np.zeros((4, 4, 4), dtype=np.uint8)
+    inner[1:3, 1:3, 1:3] = 1
+    m = blocks.cell_mask(inner, nb, (n, n, n))
+    ref = ifherk.step(u, dt, dx, re, "A", n_buf=4)
+    got = ifherk.step(u, dt, dx, re, "A", soln_mask=m, supp_mask=m)
+    assert np.array_equal(ref[0], got[0]) and np.array_equal(ref[1], got[1])
+    corner = np.zeros((4, 4, 4), dtype=np.uint8)
+    corner[0, 0, 0] = 1
+    mc = blocks.cell_mask(corner, nb, (n, n, n))
+    stokes = ifherk.step(u, dt, dx, re, "A", nonlinear=False)
+    got = ifherk.step(u, dt, dx, re, "A", soln_mask=mc, supp_mask=m)
+    assert np.abs(got[0] - stokes[0]).max() < 1e-13 * np.abs(u).max()
+    got = ifherk.step(u, dt, dx, re, "A", soln_mask=m, supp_mask=mc)
+    assert np.abs(got[1]).max() < 1e-12 * np.abs(ref[1]).max()
+
