@@ -122,6 +122,16 @@ typedef struct nslgf_state {
     void *work;
     int stage_done; /* managed by herk_stage */
     int reserved;
+    /* Optional active domain as unions of blocks (Sec. 4.2, 4.3): device arrays of one byte per block of
+     * block^3 cells tiling the box from its origin (bx = ceil(nx / block), by, bz; x fastest; 1 = in the
+     * domain).  When set they replace the box shrunk by n_buf: supp_blocks for the pressure source,
+     * soln_blocks for the nonlinear term.  The caller owns them (e.g. the masks of classify_blocks,
+     * copied to the device) and keeps them unchanged while steps that use them run.  block must be
+     * 1..256 when either is set. */
+    const unsigned char *supp_blocks;
+    const unsigned char *soln_blocks;
+    int block;
+    int reserved2;
 } nslgf_state;
 
 /* Bytes of device workspace one state needs for its box and dtype. */

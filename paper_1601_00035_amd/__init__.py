@@ -36,7 +36,9 @@ class _State(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("n_buf", ctypes.c_int), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("re", ctypes.c_double), ("t", ctypes.c_double), ("u", ctypes.c_void_p), ("d", ctypes.c_void_p),
-                ("work", ctypes.c_void_p), ("stage_done", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("work", ctypes.c_void_p), ("stage_done", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("supp_blocks", ctypes.c_void_p), ("soln_blocks", ctypes.c_void_p), ("block", ctypes.c_int),
+                ("reserved2", ctypes.c_int)]
 
 
 _lib = None
@@ -380,6 +382,27 @@ class HerkState:
 
     def set_dt(self, dt: float):
         self.c.dt = float(dt)
+
+    def set_blocks(self, supp, soln, block: int):
+        """Active domain as unions of blocks of block^3 cells (0/1 arrays [bz, by, bx], e.g. from
+        classify_blocks): supp restricts the pressure source, soln the nonlinear term; None for both
+        returns to the box shrunk by n_buf."""
+        if supp is None and soln is None:
+            self._blocks = None
+            self.c.supp_blocks = self.c.soln_blocks = None
+            self.c.block = 0
+            return
+        nz, ny, nx = self.u.shape[1:]
+        shape = (-(-nz // block), -(-ny // block), -(-nx // block))
+        t = []
+        for m in (supp, soln):
+            a = np.ascontiguousarray(np.asarray(m, dtype=np.uint8))
+            if a.shape != shape:
+                raise ValueError(f"block mask shape {a.shape}, expected {shape}")
+            t.append(torch.from_numpy(a).to(self.u.device))
+        self._blocks = t  # keeps the device copies alive
+        self.c.supp_blocks, self.c.soln_blocks = t[0].data_ptr(), t[1].data_ptr()
+        self.c.block = int(block)
 
     def stage(self, i: int):
         _check("herk_stage", lib().herk_stage(handle(self.u.device.index), ctypes.byref(self.c), int(i),

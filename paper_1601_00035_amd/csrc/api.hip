@@ -199,6 +199,8 @@ struct DivSource {
     const void* f;
     int nbuf;
     double idx;
+    const unsigned char* blocks = nullptr;  // support blocks (replace the nbuf rule when set)
+    int nb = 0;
 };
 static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int ncomp, double scale, hipStream_t s,
                     void* A1, void* A2, const DivSource* div = nullptr);
@@ -423,6 +425,8 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
         r.div_nz = p.nz;
         r.div_nbuf = div->nbuf;
         r.div_idx = div->idx;
+        r.div_blocks = div->blocks;
+        r.div_nb = div->nb;
     }
     NSLGF_PROF(h, "conv_x_r2c", s, launch_row_r2c(p.Px, dt, r, s));
     ColPass c{};
@@ -736,6 +740,8 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
                         std::isfinite(st->re) && st->re > 0,
                     "herk_stage: dt, dx and re must be > 0");
     NSLGF_CHECK_ARG(st->n_buf >= 0, "herk_stage: n_buf must be >= 0");
+    NSLGF_CHECK_ARG(!(st->supp_blocks || st->soln_blocks) || (st->block >= 1 && st->block <= 256),
+                    "herk_stage: block masks need a block size of 1..256 cells");
     if (stage == 1) st->stage_done = 0;
     if (stage != st->stage_done + 1 || stage < 1 || stage > 3) {
         set_error("herk_stage: stages must be called in order 1, 2, 3");
@@ -764,6 +770,8 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     NSLGF_TRY(build_plan(h, nx, ny, nz, dt_, s, &plan));
     StageCoef c{};
     c.nbuf = st->n_buf;
+    c.soln_blocks = st->soln_blocks;
+    c.nb = st->block;
     c.c_g = -at[stage][stage] * dt;
     const double inv = 1.0 / (at[stage][stage] * dt);
     if (stage == 1) {
@@ -785,7 +793,7 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
     }
     // pressure source M_supp Dbar r, formed while the convolution's first pass loads
-    const DivSource dsrc{r, st->n_buf, 1.0 / st->dx};
+    const DivSource dsrc{r, st->n_buf, 1.0 / st->dx, st->supp_blocks, st->block};
     NSLGF_TRY(run_conv(h, *plan, nullptr, dhat, 1, st->dx * st->dx, s, a1, a2, &dsrc));
     // u^i = H^i (r^i - G dhat^i) and w^{i,i} = (g^i - G dhat^i) / (a~_ii dt) = (r^i - G dhat^i - q^i -
     // dt sum_j a~_ij w^{i,j}) / (a~_ii dt); the projection is applied while the IF loads (with H^i = I,
@@ -848,7 +856,9 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
                                         (unsigned long long)st->scheme, (unsigned long long)st->n_buf,
                                         bits(st->dx), bits(st->dt), bits(st->re),
                                         (unsigned long long)(uintptr_t)st->u, (unsigned long long)(uintptr_t)st->d,
-                                        (unsigned long long)(uintptr_t)st->work, (unsigned long long)(uintptr_t)p};
+                                        (unsigned long long)(uintptr_t)st->work, (unsigned long long)(uintptr_t)p,
+                                        (unsigned long long)(uintptr_t)st->supp_blocks,
+                                        (unsigned long long)(uintptr_t)st->soln_blocks, (unsigned long long)st->block};
         key.insert(key.end(), std::begin(k), std::end(k));
     }
     if (!h->batch || h->batch->key != key) {

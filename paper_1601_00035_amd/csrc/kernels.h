@@ -9,6 +9,17 @@ namespace nslgf {
 // Validates a handle and makes its device current (used by entry points outside api.hip).
 int enter_handle(nslgf_t h);
 
+// Whether cell (i, j, k) of an nx x ny x nz box lies in the domain: the box shrunk by nbuf cells, or,
+// when blocks is set, the union of the blocks of nb^3 cells marked 1 there (Sec. 4.2; x fastest).
+__device__ __forceinline__ bool in_domain(int i, int j, int k, int nx, int ny, int nz, int nbuf,
+                                          const unsigned char* blocks, int nb) {
+    if (blocks) {
+        const int bx = (nx + nb - 1) / nb, by = (ny + nb - 1) / nb;
+        return blocks[((k / nb) * by + j / nb) * bx + i / nb] != 0;
+    }
+    return i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf;
+}
+
 // ---- FFT passes (lgf_conv.hip) ----------------------------------------------------------------
 // Supported padded lengths P (2,3,5-smooth, even) of the zero-padded convolution.
 bool fft_length_supported(int P);
@@ -37,6 +48,10 @@ struct RowPass {
     const void* div_src;
     int div_ny, div_nz, div_nbuf;
     double div_idx;  // 1 / dx
+    // when set, the support is these blocks of div_nb^3 cells (1 = support block, x fastest) instead of
+    // the box shrunk by div_nbuf
+    const unsigned char* div_blocks;
+    int div_nb;
 };
 int launch_row_r2c(int P, int dtype, const RowPass& a, hipStream_t s);
 int launch_row_c2r(int P, int dtype, const RowPass& a, hipStream_t s);
@@ -129,7 +144,9 @@ struct StageCoef {
     double c_q;          // coefficient of q in r (1)
     double c_w1, c_w2;   // dt * a~_{i1}, dt * a~_{i2}
     double c_g;          // -a~_{ii} dt
-    int nbuf;            // the nonlinear term is restricted to the box shrunk by nbuf cells
+    int nbuf;            // the nonlinear term is restricted to the box shrunk by nbuf cells, or,
+    const unsigned char* soln_blocks;  // when set, to these blocks of nb^3 cells (1 = solution block, x fastest)
+    int nb;
     int copy_q;          // 1: copy u into q first and use it as q (stage 1: q^1 = u_k)
 };
 // r = c_q q + c_w1 w1 + c_w2 w2 + c_g M_soln Ntilde(u); (w pointers may be null)

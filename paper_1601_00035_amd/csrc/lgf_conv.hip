@@ -23,8 +23,9 @@ namespace nslgf {
 // ---------------------------------------------------------------------------------------------------
 // Masked divergence of a face field at (x, y, z), in the order of operations of the divergence kernel.
 template <typename T>
-__device__ __forceinline__ T masked_div_at(const T* f, int x, int y, int z, int nx, int ny, int nz, int nbuf, T idx) {
-    if (x < nbuf || x >= nx - nbuf || y < nbuf || y >= ny - nbuf || z < nbuf || z >= nz - nbuf) return (T)0;
+__device__ __forceinline__ T masked_div_at(const T* f, int x, int y, int z, int nx, int ny, int nz, int nbuf,
+                                           const unsigned char* blocks, int nb, T idx) {
+    if (!in_domain(x, y, z, nx, ny, nz, nbuf, blocks, nb)) return (T)0;
     const long long n = (long long)nx * ny * nz;
     const long long c = ((long long)z * ny + y) * nx + x;
     const T f0m = x > 0 ? f[c - 1] : (T)0;
@@ -68,10 +69,11 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
                 const T* f = (const T*)a.div_src;
                 const T idx = (T)a.div_idx;
                 const T re = (valid && m < a.n_io)
-                                 ? masked_div_at<T>(f, m, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, idx)
+                                 ? masked_div_at<T>(f, m, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, a.div_blocks, a.div_nb, idx)
                                  : (T)0;
                 const T im = (valid && m + 1 < a.n_io)
-                                 ? masked_div_at<T>(f, m + 1, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, idx)
+                                 ? masked_div_at<T>(f, m + 1, y, z, a.n_io, a.div_ny, a.div_nz, a.div_nbuf, a.div_blocks, a.div_nb,
+                                                   idx)
                                  : (T)0;
                 v[b * R1 + r] = mk<T>(re, im);
             } else if constexpr (PAIRS) {

@@ -169,8 +169,7 @@ __global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1
                                                    StageCoef c, int copy_q, int nx, int ny, int nz) {
     NSLGF_CELL_INDEX
     Vec3<T> U = vec3(u, nx, ny, nz);
-    const bool in_soln = i >= c.nbuf && i < nx - c.nbuf && j >= c.nbuf && j < ny - c.nbuf && k >= c.nbuf &&
-                         k < nz - c.nbuf;
+    const bool in_soln = in_domain(i, j, k, nx, ny, nz, c.nbuf, c.soln_blocks, c.nb);
     T nl[3] = {0, 0, 0};
     if (in_soln) {
         if (i >= 1 && i < nx - 1 && j >= 1 && j < ny - 1 && k >= 1 && k < nz - 1)

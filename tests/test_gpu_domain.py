@@ -60,3 +60,51 @@ def test_block_weights_errors():
     for nb, n_buf, dx in ((0, 1, 0.1), (4, -1, 0.1), (4, 1, 0.0)):
         with pytest.raises(nslgf.NslgfError):
             nslgf.block_weights(u, dx, nb, n_buf)
+
+
+@pytest.mark.parametrize("scheme", ["A", "C"])
+def test_step_with_block_domains(scheme):
+    """IF-HERK steps whose support and solution domains are unions of blocks (Sec. 4.2, 4.3) taken from
+    the classification of the flow's own weights, against the oracle's step with the same cell masks."""
+    n, dx, ring, re, cfl = workloads.small_ring_case(24, seed=6)
+    w = workloads.ring_edge_vorticity(n, dx, ring)
+    u0 = ifherk.vor2vel(w, dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    nb = 4
+    mu, nu = blocks.weights(u0, dx, nb, 1)
+    _, supp, soln, _ = blocks.classify(mu, nu, 1e-4, 1e-1, 1)
+    assert 0 < soln.sum() < supp.sum() < supp.size
+    cs, cn = blocks.cell_mask(supp, nb, u0.shape[1:]), blocks.cell_mask(soln, nb, u0.shape[1:])
+    u_ref, d_ref = ifherk.step(u0, dt, dx, re, scheme, soln_mask=cn, supp_mask=cs)
+    u = torch.from_numpy(u0).to(DEV)
+    st = nslgf.HerkState(u, dx, dt, re, scheme, n_buf=0)
+    st.set_blocks(supp, soln, nb)
+    st.step()
+    assert np.abs(u.cpu().numpy() - u_ref).max() <= 1e-12 * np.abs(u_ref).max()
+    assert np.abs(st.d.cpu().numpy() - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+
+
+def test_blocks_equal_to_the_buffer_form():
+    """Blocks covering exactly the box shrunk by n_buf give the n_buf step bit for bit (same kernels,
+    same arithmetic), one by one and in the batched graph."""
+    n, dx, ring, re, cfl = workloads.small_ring_case(24, seed=7)
+    u0 = torch.from_numpy(ifherk.vor2vel(workloads.ring_edge_vorticity(n, dx, ring), dx)).to(DEV)
+    dt = cfl * dx / nslgf.max_cell_speed(u0)
+    inner = np.zeros((6, 6, 6), dtype=np.uint8)
+    inner[1:5, 1:5, 1:5] = 1
+    a, b, c = u0.clone(), u0.clone(), u0.clone()
+    sa = nslgf.HerkState(a, dx, dt, re, "B", n_buf=4)
+    sb = nslgf.HerkState(b, dx, dt, re, "B", n_buf=0)
+    sb.set_blocks(inner, inner, 4)
+    sc = nslgf.HerkState(c, dx, dt, re, "B", n_buf=0)
+    sc.set_blocks(inner, inner, 4)
+    sa.step()
+    sb.step()
+    nslgf.herk_step_batched([sc])
+    assert torch.equal(a, b) and torch.equal(sa.d, sb.d)
+    assert torch.equal(a, c) and torch.equal(sa.d, sc.d)
+    with pytest.raises(ValueError):
+        sb.set_blocks(inner[:5], inner, 4)
+    sb.c.block = 0
+    with pytest.raises(nslgf.NslgfError):
+        sb.step()
