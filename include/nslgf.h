@@ -5,7 +5,9 @@
  * method for viscous incompressible flow on unbounded staggered grids (Liska & Colonius):
  * the free-space LGF convolution that inverts the 7-point Laplacian, the integrating factor
  * E(alpha) of the discrete heat equation, and the stages of the integrating-factor half-explicit
- * Runge-Kutta (IF-HERK) step with its exact projection.
+ * Runge-Kutta (IF-HERK) step with its exact projection; around them, the velocity refresh and its
+ * cadence, the active-domain block weights and classification, and the volume integrals of an
+ * isolated vortex ring.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -24,6 +26,8 @@
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default stream).  Calls enqueue
  *   work and return without synchronising; results are ready in stream order.  Table builds and
  *   workspace allocations happen on first use and synchronise the stream once.
+ *   Calls that return host values (max_cell_speed, max_component_abs, flow_diagnostics,
+ *   block_weights, herk_run) synchronise the stream; calls without a handle run on the host only.
  * Errors.  Every call returns NSLGF_OK (0) or a negative code; nothing aborts and no exception
  *   crosses the ABI.  nslgf_last_error() gives a thread-local message for the last failure.
  *   A handle is not thread-safe: one host thread at a time per handle.
