@@ -94,3 +94,35 @@ def run(u: np.ndarray, nsteps: int, dt: float, dx: float, re: float, scheme: str
             if qs[-1] == 0:
                 raise ValueError("the buffer is too thin for eps: one step already exceeds it")
     return u, d, refreshes, qs
+
+
+def run_adaptive(u: np.ndarray, nsteps: int, dt: float, dx: float, re: float, scheme: str, n_buf: int, nb: int,
+                 eps_supp: float, eps_soln: float, n_xb: int):
+    """nsteps IF-HERK steps on an active domain of blocks (Sec. 4.3): at the beginning of every step the
+    block weights of u (values closer than n_buf to a box face left out) give D_supp and D_soln; the
+    step restricts the pressure source to D_supp and the nonlinear term to D_soln; when either differs
+    from the previous step's, the velocity is re-initialised from the vorticity on the new support,
+    u = Cbar a, a = -L^{-1} M_supp C u (Eq. vel_refresh).  The first classification only sets the
+    domain.  Returns (u, d, number of re-initialisations, [W of each step], [xsoln touches the outer
+    block layer, per step])."""
+    from . import blocks
+
+    shape = u.shape[1:]
+    prev = None
+    reinit = 0
+    Ws, edge = [], []
+    d = np.zeros(shape)
+    for _ in range(nsteps):
+        mu, nu = blocks.weights(u, dx, nb, n_buf)
+        W, supp, soln, xsoln = blocks.classify(mu, nu, eps_supp, eps_soln, n_xb)
+        Ws.append(W)
+        edge.append(bool(xsoln[0].any() or xsoln[-1].any() or xsoln[:, 0].any() or xsoln[:, -1].any()
+                         or xsoln[:, :, 0].any() or xsoln[:, :, -1].any()))
+        cs = blocks.cell_mask(supp, nb, shape)
+        cn = blocks.cell_mask(soln, nb, shape)
+        if prev is not None and not (np.array_equal(prev[0], supp) and np.array_equal(prev[1], soln)):
+            u = ifherk.vor2vel(cs * stencils.curl(u, dx), dx)
+            reinit += 1
+        prev = (supp, soln)
+        u, d = ifherk.step(u, dt, dx, re, scheme, soln_mask=cn, supp_mask=cs)
+    return u, d, reinit, Ws, edge
