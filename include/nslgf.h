@@ -257,6 +257,22 @@ int classify_blocks(const double *mu, const double *nu, int bx, int by, int bz, 
                     int n_xb, double *W, unsigned char *supp, unsigned char *soln, unsigned char *xsoln);
 
 /*
+ * nsteps IF-HERK steps of st on an active domain of blocks (Sec. 4.3): at the beginning of every step
+ * the block weights of st->u (block_weights with blocks of block^3 cells, leaving out the points
+ * closer than st->n_buf to a box face) are classified (classify_blocks with eps_supp, eps_soln, n_xb)
+ * into D_supp and D_soln, which restrict the step's pressure source and nonlinear term (the state's
+ * supp_blocks / soln_blocks).  When either differs from the previous step's, the velocity is first
+ * re-initialised from the vorticity on the new support (u = Cbar a, a = -L^{-1} M_supp C u,
+ * Eq. vel_refresh); the first classification only sets the domain.  The masks live in handle memory:
+ * on return st->supp_blocks / soln_blocks point there, valid until the next herk_run_adaptive call on
+ * the handle or nslgf_destroy.  *reinits (may be null) = re-initialisations done; *edge_steps (may be
+ * null) = steps whose D_xsoln reached the outermost block layer of the box (the box would have to grow
+ * to hold the expanded domain).  Synchronises `stream` every step.
+ */
+int herk_run_adaptive(nslgf_t h, nslgf_state *st, int nsteps, int block, double eps_supp, double eps_soln, int n_xb,
+                      int *reinits, int *edge_steps, void *stream);
+
+/*
  * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
  *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
  *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])

@@ -81,6 +81,8 @@ def lib():
                     "herk_run": [vp, ctypes.POINTER(_State), i, d, i, ctypes.POINTER(i), vp],
                     "flow_diagnostics": [vp, vp, i, i, i, i, d, ctypes.POINTER(d), i, ctypes.POINTER(d), vp],
                     "block_weights": [vp, vp, i, i, i, i, i, d, i, vp, vp, vp],
+                    "herk_run_adaptive": [vp, ctypes.POINTER(_State), i, i, d, d, i, ctypes.POINTER(i),
+                                          ctypes.POINTER(i), vp],
                     "classify_blocks": [vp, vp, i, i, i, d, d, i, vp, vp, vp, vp],
                 }
                 for name, args in sig.items():
@@ -410,6 +412,17 @@ class HerkState:
 
     def step(self):
         _check("herk_step", lib().herk_step(handle(self.u.device.index), ctypes.byref(self.c), _stream(self.u)))
+
+    def run_adaptive(self, nsteps: int, block: int, eps_supp: float, eps_soln: float, n_xb: int = 1):
+        """nsteps steps on an active domain of blocks re-classified every step; returns (number of
+        re-initialisations, steps whose expanded domain reached the box's outer block layer)."""
+        nre, nedge = ctypes.c_int(), ctypes.c_int()
+        self._blocks = None  # the library's own masks replace any set by set_blocks
+        _check("herk_run_adaptive", lib().herk_run_adaptive(handle(self.u.device.index), ctypes.byref(self.c),
+                                                            int(nsteps), int(block), float(eps_supp), float(eps_soln),
+                                                            int(n_xb), ctypes.byref(nre), ctypes.byref(nedge),
+                                                            _stream(self.u)))
+        return nre.value, nedge.value
 
     def run(self, nsteps: int, eps: float, q_cap: int = 10000) -> int:
         """nsteps steps with a velocity refresh after every q_max steps (q_max from eps); returns the

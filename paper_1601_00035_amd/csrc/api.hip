@@ -127,7 +127,7 @@ struct nslgf_ctx {
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
-    nslgf::DevBuf if_tmp1, if_tmp2, tmp3, tmp3b, partial;
+    nslgf::DevBuf if_tmp1, if_tmp2, tmp3, tmp3b, partial, blockmask;
 };
 
 namespace nslgf {
@@ -943,10 +943,10 @@ int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx
 
 // u = Cbar a, a = -L^{-1} w, w = M_supp C u, through two 3-component temporaries.
 static int refresh_into(nslgf_t h, void* u, int nx, int ny, int nz, int n_buf, double dx, int dtype, void* wbuf,
-                        void* abuf, hipStream_t s) {
+                        void* abuf, hipStream_t s, const unsigned char* blocks = nullptr, int nb = 0) {
     ConvPlan* p = nullptr;
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
-    NSLGF_PROF(h, "curl_masked", s, launch_masked_curl(dtype, u, wbuf, n_buf, nx, ny, nz, dx, s));
+    NSLGF_PROF(h, "curl_masked", s, launch_masked_curl(dtype, u, wbuf, n_buf, blocks, nb, nx, ny, nz, dx, s));
     NSLGF_TRY(run_conv_shared(h, *p, wbuf, abuf, 3, -dx * dx, s));
     NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, abuf, u, 3, nx, ny, nz, dx, s));
     return NSLGF_OK;
@@ -1125,6 +1125,80 @@ int classify_blocks(const double* mu, const double* nu, int bx, int by, int bz, 
         NSLGF_CHECK_ARG(std::isfinite(mu[b]) && std::isfinite(nu[b]) && mu[b] >= 0 && nu[b] >= 0,
                         "classify_blocks: weights must be finite and >= 0");
     classify_blocks_host(mu, nu, bx, by, bz, eps_supp, eps_soln, n_xb, W, supp, soln, xsoln);
+    return NSLGF_OK;
+}
+
+int herk_run_adaptive(nslgf_t h, nslgf_state* st, int nsteps, int block, double eps_supp, double eps_soln, int n_xb,
+                      int* reinits, int* edge_steps, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(st != nullptr, "herk_run_adaptive: null state");
+    NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+    NSLGF_TRY(check_dtype(st->dtype));
+    NSLGF_CHECK_ARG(st->u && st->d && st->work, "herk_run_adaptive: null u, d or work");
+    NSLGF_CHECK_ARG(nsteps >= 0, "herk_run_adaptive: nsteps must be >= 0");
+    NSLGF_CHECK_ARG(block >= 1 && block <= 256, "herk_run_adaptive: block must be 1..256");
+    NSLGF_CHECK_ARG(std::isfinite(eps_supp) && std::isfinite(eps_soln) && eps_supp >= 0 && eps_soln >= 0,
+                    "herk_run_adaptive: thresholds must be finite and >= 0");
+    NSLGF_CHECK_ARG(n_xb >= 0, "herk_run_adaptive: n_xb must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(st->dx) && st->dx > 0 && st->n_buf >= 0,
+                    "herk_run_adaptive: dx must be > 0 and n_buf >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int nx = st->nx, ny = st->ny, nz = st->nz, dt_ = st->dtype;
+    const int bx = (nx + block - 1) / block, by = (ny + block - 1) / block, bz = (nz + block - 1) / block;
+    const long long nbk = (long long)bx * by * bz;
+    const long long M = (long long)nx * ny * nz;
+    NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dt_)));
+    NSLGF_TRY(h->partial.ensure((size_t)2 * nbk * sizeof(double)));
+    NSLGF_TRY(h->blockmask.ensure((size_t)2 * nbk));
+    unsigned char* dsupp = (unsigned char*)h->blockmask.p;
+    unsigned char* dsoln = dsupp + nbk;
+    double* dmu = (double*)h->partial.p;
+    std::vector<double> mu(nbk), nu(nbk);
+    std::vector<unsigned char> supp(nbk), soln(nbk), xsoln(nbk), psupp, psoln;
+    const StateLayout L = state_layout(nx, ny, nz);
+    const size_t es = dtype_size(dt_);
+    char* wbase = (char*)st->work + L.t1 * es;
+    char* abase = wbase + (size_t)3 * M * es;
+    int nre = 0, nedge = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        // the domain of this step from the block weights of u (Sec. 4.3)
+        NSLGF_PROF(h, "nonlinear", s, launch_stencil(NSLGF_OP_NONLINEAR, dt_, st->u, h->tmp3.p, 3, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "block_weights", s,
+                   launch_block_weights(dt_, st->u, h->tmp3.p, nx, ny, nz, block, st->n_buf, st->dx, dmu, dmu + nbk, s));
+        NSLGF_HIP_CHECK(hipMemcpyAsync(mu.data(), dmu, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        NSLGF_HIP_CHECK(hipMemcpyAsync(nu.data(), dmu + nbk, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+        classify_blocks_host(mu.data(), nu.data(), bx, by, bz, eps_supp, eps_soln, n_xb, nullptr, supp.data(),
+                             soln.data(), xsoln.data());
+        bool edge = false;
+        for (int k = 0; k < bz && !edge; ++k)
+            for (int j = 0; j < by && !edge; ++j)
+                for (int i = 0; i < bx && !edge; ++i)
+                    if ((i == 0 || j == 0 || k == 0 || i == bx - 1 || j == by - 1 || k == bz - 1) &&
+                        xsoln[((long long)k * by + j) * bx + i])
+                        edge = true;
+        nedge += edge ? 1 : 0;
+        const bool first = psupp.empty();
+        const bool changed = first || psupp != supp || psoln != soln;
+        if (changed) {
+            NSLGF_HIP_CHECK(hipMemcpyAsync(dsupp, supp.data(), nbk, hipMemcpyHostToDevice, s));
+            NSLGF_HIP_CHECK(hipMemcpyAsync(dsoln, soln.data(), nbk, hipMemcpyHostToDevice, s));
+            NSLGF_HIP_CHECK(hipStreamSynchronize(s));  // the host masks are reused below
+            psupp = supp;
+            psoln = soln;
+        }
+        if (changed && !first) {
+            // re-initialise: u from the vorticity on the new support (Eq. vel_refresh)
+            NSLGF_TRY(refresh_into(h, st->u, nx, ny, nz, st->n_buf, st->dx, dt_, wbase, abase, s, dsupp, block));
+            ++nre;
+        }
+        st->supp_blocks = dsupp;
+        st->soln_blocks = dsoln;
+        st->block = block;
+        NSLGF_TRY(herk_step(h, st, stream));
+    }
+    if (reinits) *reinits = nre;
+    if (edge_steps) *edge_steps = nedge;
     return NSLGF_OK;
 }
 

@@ -165,8 +165,10 @@ int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, d
                  long long n, hipStream_t s);
 // plain 16-byte-vector copy of `bytes` (multiple of 16)
 int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
-// e = M_supp C f (edges closer than nbuf points to a box face set to 0)
-int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, int nx, int ny, int nz, double dx, hipStream_t s);
+// e = M_supp C f (edges closer than nbuf points to a box face set to 0, or, when blocks is set, edges
+// outside the marked blocks of nb^3 cells)
+int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsigned char* blocks, int nb, int nx, int ny,
+                       int nz, double dx, hipStream_t s);
 // per-workgroup maxima of |u^(q)| over the three components on the box shrunk by nbuf points
 int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
                    hipStream_t s);

@@ -123,13 +123,14 @@ __global__ void __launch_bounds__(256) k_div(const T* f, T* c, int nx, int ny, i
     c[idx] = in_supp ? v : (T)0;
 }
 
-// e = C f on the box; with nbuf > 0, e = M_supp C f: edges closer than nbuf points to a box face
-// (outside the support domain, the box shrunk by nbuf points) are set to 0.
+// e = C f on the box; with nbuf > 0 or support blocks, e = M_supp C f: edges outside the support
+// domain (the box shrunk by nbuf points, or the union of the marked blocks of nb^3 cells) are set to 0.
 template <typename T>
-__global__ void __launch_bounds__(256) k_curl(const T* f, T* e, int nx, int ny, int nz, T idx_, int nbuf) {
+__global__ void __launch_bounds__(256) k_curl(const T* f, T* e, int nx, int ny, int nz, T idx_, int nbuf,
+                                              const unsigned char* blocks, int nb) {
     NSLGF_CELL_INDEX
     Vec3<T> F = vec3(f, nx, ny, nz);
-    const bool in_supp = i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf;
+    const bool in_supp = in_domain(i, j, k, nx, ny, nz, nbuf, blocks, nb);
     for (int q = 0; q < 3; ++q) e[q * n + idx] = in_supp ? curl_at(F, q, i, j, k, idx_) : (T)0;
 }
 
@@ -420,7 +421,7 @@ static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int 
     switch (op) {
         case NSLGF_OP_GRAD: hipLaunchKernelGGL(k_grad<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_DIV: hipLaunchKernelGGL(k_div<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
-        case NSLGF_OP_CURL: hipLaunchKernelGGL(k_curl<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
+        case NSLGF_OP_CURL: hipLaunchKernelGGL(k_curl<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0, nullptr, 0); break;
         case NSLGF_OP_CURL_BAR: hipLaunchKernelGGL(k_curl_bar<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_NONLINEAR: hipLaunchKernelGGL(k_nonlinear<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_LAPLACIAN:
@@ -495,13 +496,14 @@ int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, d
     return NSLGF_OK;
 }
 
-int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, int nx, int ny, int nz, double dx, hipStream_t s) {
+int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsigned char* blocks, int nb, int nx, int ny,
+                       int nz, double dx, hipStream_t s) {
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_curl<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)f, (float*)e, nx, ny,
-                           nz, (float)(1.0 / dx), nbuf);
+                           nz, (float)(1.0 / dx), nbuf, blocks, nb);
     else
         hipLaunchKernelGGL(k_curl<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)f, (double*)e, nx,
-                           ny, nz, 1.0 / dx, nbuf);
+                           ny, nz, 1.0 / dx, nbuf, blocks, nb);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

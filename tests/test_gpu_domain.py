@@ -108,3 +108,27 @@ def test_blocks_equal_to_the_buffer_form():
     sb.c.block = 0
     with pytest.raises(nslgf.NslgfError):
         sb.step()
+
+
+def test_run_adaptive():
+    """Four steps on an active domain re-classified every step (Sec. 4.3) against the oracle: the same
+    domains (the thresholds sit clear of every block weight), the same re-initialisations, and the
+    same velocity and pressure."""
+    from oracle import refresh
+
+    n, dx, ring, re, cfl = workloads.small_ring_case(24, seed=6)
+    u0 = ifherk.vor2vel(workloads.ring_edge_vorticity(n, dx, ring), dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    args = dict(nb=4, eps_supp=1e-4, eps_soln=1e-1, n_xb=1)
+    u_ref, d_ref, nre, Ws, edge = refresh.run_adaptive(u0, 4, dt, dx, 100.0, "A", 1, **args)
+    for W in Ws:
+        assert np.abs(W - args["eps_supp"]).min() > 1e-9 and np.abs(W - args["eps_soln"]).min() > 1e-9
+    assert nre >= 1
+    u = torch.from_numpy(u0).to(DEV)
+    st = nslgf.HerkState(u, dx, dt, 100.0, "A", n_buf=1)
+    got = st.run_adaptive(4, args["nb"], args["eps_supp"], args["eps_soln"], args["n_xb"])
+    assert got == (nre, sum(edge))
+    assert np.abs(u.cpu().numpy() - u_ref).max() <= 1e-12 * np.abs(u_ref).max()
+    assert np.abs(st.d.cpu().numpy() - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+    with pytest.raises(nslgf.NslgfError):
+        st.run_adaptive(1, 0, 1e-4, 1e-1)
