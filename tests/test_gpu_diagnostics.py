@@ -91,3 +91,29 @@ def test_ring_speed_against_saffman():
     # the sampled vorticity's closed forms: I_z = pi Gamma (R^2 + sigma^2 / 2), E ~ Gamma^2 R / (2 sigma^2)
     assert abs(x0["I"][2] / (math.pi * (ring.R ** 2 + ring.sigma ** 2 / 2)) - 1) < 1e-4
     assert abs(x0["E"] / (ring.R / (2 * ring.sigma ** 2)) - 1) < 0.02
+
+
+def test_saffman_error_term():
+    """The ring speed over the first step for eps = sigma / R = 0.2, 0.1, 0.05 at a fixed sigma / dx = 4.8
+    (Sec. 6.3): U_z stays below Saffman's speed and the gap (U_S - U_z) R / Gamma shrinks like the
+    formula's error term O(eps^2 log eps), whose ratio between successive halvings of eps is 2.8 and
+    3.1 (measured: 2.8 and 2.8)."""
+    gaps = []
+    for eps, n, n_buf in ((0.2, 128, 16), (0.1, 256, 16), (0.05, 256, 8)):
+        dx = eps / 4.8
+        ring = workloads.Ring(R=1.0, sigma=eps)
+        u = nslgf.vor2vel(torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring)).to(DEV), dx)
+        origin = dg.box_origin((n, n, n), dx)
+        x0 = nslgf.flow_diagnostics(u, dx, origin, n_buf)
+        dt = 0.5 * dx / nslgf.max_cell_speed(u)
+        st = nslgf.HerkState(u, dx, dt, 500.0, "A", n_buf=n_buf)
+        st.step()
+        x1 = nslgf.flow_diagnostics(u, dx, origin, n_buf)
+        uz = (x1["X"][2] - x0["X"][2]) / dt
+        gaps.append(dg.saffman_speed(1.0, 1.0, eps) - uz)
+        print(f"eps {eps}: U_z {uz:.6f}, gap {gaps[-1]:.4e}")
+        del st, u
+        torch.cuda.empty_cache()
+    assert all(g > 0 for g in gaps)
+    for a, b in zip(gaps, gaps[1:]):
+        assert 2.0 < a / b < 4.0, gaps
