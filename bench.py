@@ -399,8 +399,32 @@ def main():
         for eps in (1e-2, 1e-4, 1e-6):
             _, sp, so, xs = nslgf.classify_blocks(mu, nu, eps, eps, 1)
             frac[f"{eps:g}"] = {"supp": round(float(sp.mean()), 4), "xsoln": round(float(xs.mean()), 4)}
+        # steps on that active domain, re-classified every step with re-initialisation on a change
+        # (Sec. 4.3), against plain steps of the same state
+        ua = u.clone()
+        sa = nslgf.HerkState(ua, dx, dt, re, "A", n_buf=16)
+        sa.run_adaptive(1, 16, 1e-6, 1e-3, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nre, nedge = sa.run_adaptive(3, 16, 1e-6, 1e-3, 1)
+        torch.cuda.synchronize()
+        ms_ad = (time.perf_counter() - t0) / 3 * 1e3
+        sp = nslgf.HerkState(ua.clone(), dx, dt, re, "A", n_buf=16)
+        sp.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            sp.step()
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) / 3 * 1e3
         secondary["active_domain"] = {"block": 16, "blocks": int(mu.size), "ms_incl_sync": round(ms_bw, 4),
-                                      "fraction_of_box_by_eps": frac}
+                                      "fraction_of_box_by_eps": frac,
+                                      "adaptive_steps": {"eps_supp": 1e-6, "eps_soln": 1e-3, "n_xb": 1, "steps": 3,
+                                                         "ms_per_step": round(ms_ad, 4), "reinits": nre,
+                                                         "edge_steps": nedge,
+                                                         "plain_step_ms": round(ms_plain, 4)}}
+        del ua, sa, sp
+        torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
                                 "fp32": batched_measure(nslgf, torch, torch.float32)}
