@@ -78,3 +78,19 @@ def test_component_max_on_the_solution_domain():
     u[2, 0, 5, 5] = 9.0  # outside the solution domain of n_buf = 1
     assert refresh.component_max(u, 1) == 0.3
     assert refresh.component_max(u, 0) == 9.0
+
+
+def test_repeated_masked_factors_follow_the_single_factor_estimate():
+    """Sec. 4.4: q masked applications of E(a) are well approximated by one masked E(q a), so the deficit
+    of a uniform field a few points inside a face follows d_{q a}(k).  Brute force: at k = 5 and 7 the
+    repeated deficit stays within 0 to 20 % above the estimate for q up to 6 (at the face itself, k = 1,
+    the repeated truncation loses up to 40 % more)."""
+    alpha, shape = 0.3, (9, 9, 40)
+    h = np.ones(shape)
+    for q in range(1, 7):
+        h = intfac.apply(h, alpha)
+        line = h[4, 4, :]
+        for k in (5, 7):
+            rep = (line[20] - line[k - 1]) / line[20]
+            est = refresh.trunc_error(q * alpha, k)
+            assert 1.0 - 1e-9 <= rep / est <= 1.2, (q, k, rep, est)
