@@ -51,3 +51,23 @@ def test_state_bytes():
     assert b64 >= 25 * 512 * 8 and b64 == 2 * b32
     assert L.nslgf_state_bytes(0, 8, 8, 0) == 0
     assert L.nslgf_state_bytes(8, 300, 8, 0) == 0
+
+
+def test_null_handle_is_rejected_without_a_device():
+    """Every handle-taking entry point of the refresh, ring-integral and active-domain calls returns
+    NSLGF_EINVAL for a null handle before it touches a device (host-only check)."""
+    L = nslgf.lib()
+    d = ctypes.c_double()
+    i = ctypes.c_int()
+    buf = (ctypes.c_double * 16)()
+    org = (ctypes.c_double * 3)()
+    calls = [
+        L.max_component_abs(None, None, 8, 8, 8, 1, 0, ctypes.byref(d), None),
+        L.velocity_refresh(None, None, 8, 8, 8, 1, 0.1, 0, None),
+        L.herk_run(None, None, 1, 1e-6, 10, ctypes.byref(i), None),
+        L.herk_run_adaptive(None, None, 1, 4, 1e-4, 1e-2, 1, ctypes.byref(i), ctypes.byref(i), None),
+        L.flow_diagnostics(None, None, 8, 8, 8, 1, 0.1, org, 0, buf, None),
+        L.block_weights(None, None, 8, 8, 8, 4, 1, 0.1, 0, buf, buf, None),
+    ]
+    assert all(c == -1 for c in calls), calls
+    assert b"null handle" in L.nslgf_last_error()
