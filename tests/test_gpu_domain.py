@@ -132,3 +132,20 @@ def test_run_adaptive():
     assert np.abs(st.d.cpu().numpy() - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
     with pytest.raises(nslgf.NslgfError):
         st.run_adaptive(1, 0, 1e-4, 1e-1)
+
+
+def test_run_adaptive_fp32():
+    """The FP32 form of the adaptive run takes the same domain decisions as FP64 (the block weights sit
+    far from the thresholds at FP32 resolution) and stays within FP32 rounding of it."""
+    n, dx, ring, re, cfl = workloads.small_ring_case(24, seed=6)
+    u0 = ifherk.vor2vel(workloads.ring_edge_vorticity(n, dx, ring), dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    out = {}
+    for dtype in (torch.float64, torch.float32):
+        u = torch.from_numpy(u0).to(DEV, dtype)
+        st = nslgf.HerkState(u, dx, dt, 100.0, "A", n_buf=1)
+        counts = st.run_adaptive(4, 4, 1e-4, 1e-1, 1)
+        out[dtype] = (counts, u.double().cpu().numpy())
+    assert out[torch.float32][0] == out[torch.float64][0]
+    ref = out[torch.float64][1]
+    assert np.abs(out[torch.float32][1] - ref).max() <= 1e-5 * np.abs(ref).max()
