@@ -95,3 +95,21 @@ def test_run_errors():
         nslgf.velocity_refresh(u, -1.0, 2)
     with pytest.raises(nslgf.NslgfError):
         nslgf.velocity_refresh(u, dx, -1)
+
+
+def test_run_with_refresh_fp32():
+    """The FP32 run refreshes after the same steps as FP64 (eps sits between the estimates after two
+    and three steps, a factor of five apart) and stays within FP32 rounding of it."""
+    n, dx, u0, re, dt = _ring()
+    n_buf = 3
+    beta = dt / (dx * dx * re)
+    umax = refresh.component_max(u0, n_buf)
+    eps = math.sqrt(refresh.estimate(beta, 2, n_buf, umax) * refresh.estimate(beta, 3, n_buf, umax))
+    out = {}
+    for dtype in (torch.float64, torch.float32):
+        u = torch.from_numpy(u0).to(DEV, dtype)
+        st = nslgf.HerkState(u, dx, dt, re, "A", n_buf=n_buf)
+        out[dtype] = (st.run(5, eps), u.double().cpu().numpy())
+    assert out[torch.float32][0] == out[torch.float64][0] == 2
+    ref = out[torch.float64][1]
+    assert rel(out[torch.float32][1], ref) < 1e-5
