@@ -149,3 +149,23 @@ def test_run_adaptive_fp32():
     assert out[torch.float32][0] == out[torch.float64][0]
     ref = out[torch.float64][1]
     assert np.abs(out[torch.float32][1] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_full_size_refresh_weights_and_integrals():
+    """At the benchmark's 256^3 FP64 ring (the launch shapes the bench times), properties that hold at
+    any size: the refresh returns a Vor2Vel velocity whose vorticity lies inside the support; the
+    largest block weight mu equals the largest |C u| over the trusted points (same curl arithmetic);
+    the impulse of the velocity matches the sampled ring's closed form."""
+    import math
+
+    n, dx, ring, re, cfl = workloads.ring_case("conv256")
+    w = torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring)).to(DEV)
+    u = nslgf.vor2vel(w, dx)
+    v = nslgf.velocity_refresh(u.clone(), dx, 16)
+    assert ((v - u).abs().max() / u.abs().max()).item() < 1e-10
+    mu, nu = nslgf.block_weights(u, dx, 16, 16)
+    cu = nslgf.stencil("curl", u, dx)[:, 16:-16, 16:-16, 16:-16]
+    assert mu.max() == cu.abs().max().item()
+    assert nu.max() > 0 and mu.shape == (16, 16, 16)
+    r = nslgf.flow_diagnostics(u, dx, dg.box_origin((n, n, n), dx), 16)
+    assert abs(r["I"][2] / (math.pi * (ring.R ** 2 + ring.sigma ** 2 / 2)) - 1) < 1e-4
