@@ -117,3 +117,29 @@ def test_saffman_error_term():
     assert all(g > 0 for g in gaps)
     for a, b in zip(gaps, gaps[1:]):
         assert 2.0 < a / b < 4.0, gaps
+
+
+def test_long_run_impulse_and_speed():
+    """A hundred steps of the 128^3 ring through the whole GPU path (herk_run with its refresh cadence):
+    the impulse stays conserved (Sec. 6.2) and the mean ring speed lies between Saffman's speed for
+    the initial core and for the core grown by viscous diffusion, sigma^2 + 4 nu t (Sec. 6.3 and its
+    footnote on the early-time core size)."""
+    import math
+
+    n, dx, ring, re, cfl = workloads.ring_case("step128")
+    u = nslgf.vor2vel(torch.from_numpy(workloads.ring_edge_vorticity(n, dx, ring)).to(DEV), dx)
+    origin = dg.box_origin((n, n, n), dx)
+    x0 = nslgf.flow_diagnostics(u, dx, origin, 16)
+    dt = cfl * dx / nslgf.max_cell_speed(u)
+    st = nslgf.HerkState(u, dx, dt, re, "A", n_buf=16)
+    st.run(100, 1e-8)
+    assert torch.isfinite(u).all().item()
+    x1 = nslgf.flow_diagnostics(u, dx, origin, 16)
+    t = st.t
+    mean_u = (x1["X"][2] - x0["X"][2]) / t
+    s_grown = math.sqrt(ring.sigma ** 2 + 4.0 / re * t)
+    hi = dg.saffman_speed(ring.gamma, ring.R, ring.sigma)
+    lo = dg.saffman_speed(ring.gamma, ring.R, s_grown)
+    print(f"t {t:.3f}: mean U_z {mean_u:.5f}, Saffman {lo:.5f} .. {hi:.5f}, I_z {x0['I'][2]:.9f} -> {x1['I'][2]:.9f}")
+    assert abs(x1["I"][2] / x0["I"][2] - 1) < 1e-5
+    assert lo < mean_u < hi
