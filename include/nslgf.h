@@ -48,7 +48,8 @@ enum nslgf_status {
     NSLGF_ENOMEM = -2,       /* device allocation failed */
     NSLGF_EHIP = -3,         /* a HIP runtime call failed */
     NSLGF_EUNSUPPORTED = -4, /* valid request this build does not handle */
-    NSLGF_ESTATE = -5        /* stages called out of order */
+    NSLGF_ESTATE = -5,       /* stages called out of order */
+    NSLGF_ENONFINITE = -6    /* a guarded step or herk_check found a non-finite value (NaN or Inf) */
 };
 
 enum nslgf_dtype { NSLGF_F64 = 0, NSLGF_F32 = 1 };
@@ -114,6 +115,16 @@ int if_apply(nslgf_t h, const void *src, void *dst, int ncomp, int nx, int ny, i
  * nonlinear term and the pressure source are restricted to the box shrunk by n_buf cells on every
  * side (the solution and support domains of Sec. 5, Eqs. rhs_final and dpoisson_final).
  * stage_done counts the stages already applied (0 before the first stage).
+ *
+ * Step guard (optional, guard != 0): after the projection of every stage a check kernel takes, in FP64
+ * whatever the dtype, the largest |Dbar u^i| over the cells at least `margin` cells from every box
+ * face and counts the non-finite values of u^i (and of d in the last stage); margin = guard_margin
+ * when > 0, else n_buf + r_i + 1 with r_i the radius of the stage's integrating factor (inside the
+ * support domain the projection leaves no divergence, and H^i carries the buffer's divergence r_i
+ * cells inwards).  The last stage reads the result back (one stream synchronisation), stores the
+ * largest value of the three stages in div_max and returns NSLGF_ENONFINITE if any value was not
+ * finite.  With block domains (supp_blocks) set, choose guard_margin so that the checked cells lie in
+ * the support.
  */
 typedef struct nslgf_state {
     int nx, ny, nz;
@@ -125,7 +136,7 @@ typedef struct nslgf_state {
     void *d;
     void *work;
     int stage_done; /* managed by herk_stage */
-    int reserved;
+    int guard;      /* 1: check every stage's projection in FP64 and test for non-finite values */
     /* Optional active domain as unions of blocks (Sec. 4.2, 4.3): device arrays of one byte per block of
      * block^3 cells tiling the box from its origin (bx = ceil(nx / block), by, bz; x fastest; 1 = in the
      * domain).  When set they replace the box shrunk by n_buf: supp_blocks for the pressure source,
@@ -135,7 +146,8 @@ typedef struct nslgf_state {
     const unsigned char *supp_blocks;
     const unsigned char *soln_blocks;
     int block;
-    int reserved2;
+    int guard_margin; /* cells left out next to the box faces by the guard's divergence check (0: automatic) */
+    double div_max;   /* out (guarded steps): largest FP64 |Dbar u^i| over the checked cells, all stages */
 } nslgf_state;
 
 /* Bytes of device workspace one state needs for its box and dtype. */
@@ -156,11 +168,22 @@ int herk_stage(nslgf_t h, nslgf_state *st, int stage, void *stream);
 int herk_step(nslgf_t h, nslgf_state *st, void *stream);
 
 /*
+ * FP64 check of a state's fields (the projection's divergence check kept in FP64 for both dtypes):
+ * *div_max = max |Dbar u| over the cells at least max(margin, 1) cells from every box face, the
+ * difference quotients formed in FP64 from the stored values of u; non-finite values of u and d are
+ * counted over the whole box.  Returns NSLGF_ENONFINITE (with *div_max set to the maximum over the
+ * finite values) if there is any, else NSLGF_OK.  Synchronises `stream`.
+ */
+int herk_check(nslgf_t h, const nslgf_state *st, int margin, double *div_max, void *stream);
+
+/*
  * One IF-HERK step of each of n independent states (boxes of any supported sizes and dtypes, each
  * with its own u, d and work; none may share them), as one launch: the first call captures the n
  * steps into a HIP graph with one branch per state (up to 16 concurrent branches) and later calls
  * with the same states and step parameters replay it.  Results equal n herk_step calls bit for bit.
  * Advances every st->t by its dt.  Builds missing LGF spectra first (synchronising the stream).
+ * Guarded states are checked inside the graph and read back after it (one synchronisation); the call
+ * returns NSLGF_ENONFINITE if any of them saw a non-finite value.
  */
 int herk_step_batched(nslgf_t h, nslgf_state *const *sts, int n, void *stream);
 
@@ -263,9 +286,9 @@ int classify_blocks(const double *mu, const double *nu, int bx, int by, int bz, 
  * into D_supp and D_soln, which restrict the step's pressure source and nonlinear term (the state's
  * supp_blocks / soln_blocks).  When either differs from the previous step's, the velocity is first
  * re-initialised from the vorticity on the new support (u = Cbar a, a = -L^{-1} M_supp C u,
- * Eq. vel_refresh); the first classification only sets the domain.  The masks live in handle memory:
- * on return st->supp_blocks / soln_blocks point there, valid until the next herk_run_adaptive call on
- * the handle or nslgf_destroy.  *reinits (may be null) = re-initialisations done; *edge_steps (may be
+ * Eq. vel_refresh); the first classification only sets the domain.  The masks of the run live in handle
+ * memory; on return (also on failure) st->supp_blocks, soln_blocks and block are as on entry, so later
+ * herk_step calls use the state's own domain again.  *reinits (may be null) = re-initialisations done; *edge_steps (may be
  * null) = steps whose D_xsoln reached the outermost block layer of the box (the box would have to grow
  * to hold the expanded domain).  Synchronises `stream` every step.
  */

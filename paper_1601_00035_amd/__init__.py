@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libnslgf.so")
 F64, F32 = 0, 1
 SCHEME = {"A": 0, "B": 1, "C": 2}
 OP = {"grad": 0, "div": 1, "curl": 2, "curl_bar": 3, "nonlinear": 4, "laplacian": 5}
-_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE"}
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "ESTATE", -6: "ENONFINITE"}
+ENONFINITE = -6
 
 
 class NslgfError(RuntimeError):
@@ -36,9 +37,9 @@ class _State(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("scheme", ctypes.c_int), ("n_buf", ctypes.c_int), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
                 ("re", ctypes.c_double), ("t", ctypes.c_double), ("u", ctypes.c_void_p), ("d", ctypes.c_void_p),
-                ("work", ctypes.c_void_p), ("stage_done", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("work", ctypes.c_void_p), ("stage_done", ctypes.c_int), ("guard", ctypes.c_int),
                 ("supp_blocks", ctypes.c_void_p), ("soln_blocks", ctypes.c_void_p), ("block", ctypes.c_int),
-                ("reserved2", ctypes.c_int)]
+                ("guard_margin", ctypes.c_int), ("div_max", ctypes.c_double)]
 
 
 _lib = None
@@ -64,6 +65,7 @@ def lib():
                     "if_apply": [vp, vp, vp, i, i, i, i, d, i, vp],
                     "herk_stage": [vp, ctypes.POINTER(_State), i, vp],
                     "herk_step": [vp, ctypes.POINTER(_State), vp],
+                    "herk_check": [vp, ctypes.POINTER(_State), i, ctypes.POINTER(d), vp],
                     "herk_step_batched": [vp, ctypes.POINTER(ctypes.POINTER(_State)), i, vp],
                     "vor2vel": [vp, vp, vp, i, i, i, d, i, vp],
                     "stencil_apply": [vp, i, vp, vp, i, i, i, i, d, i, vp],
@@ -367,7 +369,7 @@ class HerkState:
     library workspace, plus the step parameters."""
 
     def __init__(self, u: torch.Tensor, dx: float, dt: float, re: float, scheme: str = "A", n_buf: int = 0,
-                 t: float = 0.0):
+                 t: float = 0.0, guard: bool = False, guard_margin: int = 0):
         _dev(u, "u")
         _, nz, ny, nx = u.shape
         self.u = u
@@ -376,11 +378,25 @@ class HerkState:
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=u.device)
         self.c = _State(nx=nx, ny=ny, nz=nz, dtype=_dtype(u), scheme=SCHEME[scheme], n_buf=int(n_buf), dx=float(dx),
                         dt=float(dt), re=float(re), t=float(t), u=u.data_ptr(), d=self.d.data_ptr(),
-                        work=self.work.data_ptr(), stage_done=0, reserved=0)
+                        work=self.work.data_ptr(), stage_done=0, guard=1 if guard else 0,
+                        guard_margin=int(guard_margin))
 
     @property
     def t(self) -> float:
         return self.c.t
+
+    @property
+    def div_max(self) -> float:
+        """Largest FP64 |Dbar u^i| of the last guarded step (over the stages and the checked cells)."""
+        return self.c.div_max
+
+    def check(self, margin: int) -> float:
+        """FP64 max |Dbar u| over the cells at least margin cells from every face; raises NslgfError
+        (code ENONFINITE) if u or d holds a non-finite value.  Synchronises the stream."""
+        out = ctypes.c_double()
+        _check("herk_check", lib().herk_check(handle(self.u.device.index), ctypes.byref(self.c), int(margin),
+                                              ctypes.byref(out), _stream(self.u)))
+        return out.value
 
     def set_dt(self, dt: float):
         self.c.dt = float(dt)
@@ -417,7 +433,8 @@ class HerkState:
         """nsteps steps on an active domain of blocks re-classified every step; returns (number of
         re-initialisations, steps whose expanded domain reached the box's outer block layer)."""
         nre, nedge = ctypes.c_int(), ctypes.c_int()
-        self._blocks = None  # the library's own masks replace any set by set_blocks
+        # the run classifies into handle memory and leaves the state's own domain (set_blocks or n_buf)
+        # in place when it returns
         _check("herk_run_adaptive", lib().herk_run_adaptive(handle(self.u.device.index), ctypes.byref(self.c),
                                                             int(nsteps), int(block), float(eps_supp), float(eps_soln),
                                                             int(n_xb), ctypes.byref(nre), ctypes.byref(nedge),

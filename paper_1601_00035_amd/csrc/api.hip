@@ -124,6 +124,7 @@ struct nslgf_ctx {
         for (auto e : batch_events) (void)hipEventDestroy(e);
         if (capture) (void)hipStreamDestroy(capture);
     }
+    bool capturing = false;  // a batch graph is being captured (no host round trips)
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
@@ -602,6 +603,13 @@ static StateLayout state_layout(int nx, int ny, int nz) {
     return L;
 }
 
+// The step guard's two accumulators (FP64 divergence maximum, non-finite count) sit after the workspace.
+constexpr size_t kGuardBytes = 256;
+static size_t state_guard_offset(int nx, int ny, int nz, int dtype) {
+    const size_t b = state_layout(nx, ny, nz).total * dtype_size(dtype);
+    return (b + 255) / 256 * 256;
+}
+
 // Shifted tableau a~, c~ (1-based, c~_0 = 0) of the three-stage schemes (Sec. 3.1, 3.2).
 static void tableau(int scheme, double at[4][4], double ct[4]) {
     const double s3 = std::sqrt(3.0);
@@ -631,6 +639,20 @@ static void tableau(int scheme, double at[4][4], double ct[4]) {
         for (int j = 1; j <= 3; ++j) at[i][j] = (i < 3) ? A[i][j - 1] : b[j - 1];
         ct[i] = (i < 3) ? c[i] : 1.0;
     }
+}
+
+// Reads a guarded step's accumulators back (synchronising the stream): st->div_max, and
+// NSLGF_ENONFINITE if a non-finite value was seen.
+static int read_guard(nslgf_state* st, const unsigned long long* acc, hipStream_t s) {
+    unsigned long long host[2];
+    NSLGF_HIP_CHECK(hipMemcpyAsync(host, acc, sizeof host, hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    std::memcpy(&st->div_max, &host[0], sizeof(double));
+    if (host[1]) {
+        set_error("herk_step: " + std::to_string(host[1]) + " non-finite values in the step's velocity or pressure");
+        return NSLGF_ENONFINITE;
+    }
+    return NSLGF_OK;
 }
 
 }  // namespace nslgf
@@ -694,9 +716,12 @@ int lgf_table(nslgf_t h, int nx, int ny, int nz, int dtype, void* stream) {
     NSLGF_TRY(check_box(nx, ny, nz));
     NSLGF_TRY(check_dtype(dtype));
     auto key = std::make_tuple(nx, ny, nz, dtype, h->fft_plan);
-    h->plans.erase(key);
+    if (h->plans.erase(key)) h->batch.reset();  // a captured batch graph holds the erased plan's buffers
     ConvPlan* p = nullptr;
-    return build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p);
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p));
+    // the dtype's twiddle tables too, so that every buffer a convolution of this box reads exists
+    const void *a, *b, *c, *d;
+    return plan_twiddles(h, *p, dtype, &a, &b, &c, &d);
 }
 
 int lgf_convolve(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, int dtype,
@@ -726,7 +751,7 @@ int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, i
 
 size_t nslgf_state_bytes(int nx, int ny, int nz, int dtype) {
     if (nx < 1 || ny < 1 || nz < 1 || nx > 256 || ny > 256 || nz > 256) return 0;
-    return state_layout(nx, ny, nz).total * dtype_size(dtype);
+    return state_guard_offset(nx, ny, nz, dtype) + kGuardBytes;
 }
 
 int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
@@ -818,6 +843,42 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         st->t += dt;
     }
     st->stage_done = stage;
+    if (st->guard) {
+        // FP64 divergence of the projected u^i on the support away from the buffer (and, last stage, the
+        // non-finite test of d too)
+        unsigned long long* acc = (unsigned long long*)(w + state_guard_offset(nx, ny, nz, dt_));
+        if (stage == 1) NSLGF_TRY(launch_guard_reset(acc, s));
+        double wts[kIfMaxRadius + 1];
+        const int rad = alpha > 0.0 ? if_weights(alpha, dt_, wts, kIfMaxRadius) : 0;
+        const int margin = st->guard_margin > 0 ? st->guard_margin : st->n_buf + std::max(rad, 0) + 1;
+        NSLGF_PROF(h, "guard", s, launch_guard(dt_, st->u, stage == 3 ? st->d : nullptr, nx, ny, nz, margin, st->dx,
+                                               acc, s));
+        if (stage == 3 && !h->capturing) NSLGF_TRY(read_guard(st, acc, s));
+    }
+    return NSLGF_OK;
+}
+
+int herk_check(nslgf_t h, const nslgf_state* st, int margin, double* div_max, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(st != nullptr && div_max != nullptr, "herk_check: null state or output");
+    NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+    NSLGF_TRY(check_dtype(st->dtype));
+    NSLGF_CHECK_ARG(st->u && st->d, "herk_check: null u or d");
+    NSLGF_CHECK_ARG(std::isfinite(st->dx) && st->dx > 0, "herk_check: dx must be > 0");
+    NSLGF_CHECK_ARG(margin >= 0, "herk_check: margin must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    NSLGF_TRY(h->partial.ensure(2 * sizeof(unsigned long long)));
+    unsigned long long* acc = (unsigned long long*)h->partial.p;
+    NSLGF_TRY(launch_guard_reset(acc, s));
+    NSLGF_PROF(h, "guard", s, launch_guard(st->dtype, st->u, st->d, st->nx, st->ny, st->nz, margin, st->dx, acc, s));
+    unsigned long long host[2];
+    NSLGF_HIP_CHECK(hipMemcpyAsync(host, acc, sizeof host, hipMemcpyDeviceToHost, s));
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    std::memcpy(div_max, &host[0], sizeof(double));
+    if (host[1]) {
+        set_error("herk_check: " + std::to_string(host[1]) + " non-finite values in u or d");
+        return NSLGF_ENONFINITE;
+    }
     return NSLGF_OK;
 }
 
@@ -831,7 +892,7 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
     NSLGF_CHECK_ARG(sts != nullptr && n >= 1 && n <= 4096, "herk_step_batched: need 1..4096 states");
     hipStream_t s = (hipStream_t)stream;
     std::vector<unsigned long long> key;
-    key.reserve((size_t)n * 16);
+    key.reserve((size_t)n * 19);
     auto bits = [](double v) {
         unsigned long long b;
         std::memcpy(&b, &v, sizeof b);
@@ -857,8 +918,10 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
                                         bits(st->dx), bits(st->dt), bits(st->re),
                                         (unsigned long long)(uintptr_t)st->u, (unsigned long long)(uintptr_t)st->d,
                                         (unsigned long long)(uintptr_t)st->work, (unsigned long long)(uintptr_t)p,
+                                        (unsigned long long)(uintptr_t)p->khat.p,
                                         (unsigned long long)(uintptr_t)st->supp_blocks,
-                                        (unsigned long long)(uintptr_t)st->soln_blocks, (unsigned long long)st->block};
+                                        (unsigned long long)(uintptr_t)st->soln_blocks, (unsigned long long)st->block,
+                                        (unsigned long long)st->guard, (unsigned long long)st->guard_margin};
         key.insert(key.end(), std::begin(k), std::end(k));
     }
     if (!h->batch || h->batch->key != key) {
@@ -888,7 +951,9 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
         if (rc == NSLGF_OK && hipEventRecord(h->batch_events[0], h->capture) != hipSuccess) rc = NSLGF_EHIP;
         for (int b = 0; rc == NSLGF_OK && b < nb; ++b)
             if (hipStreamWaitEvent(h->branches[b], h->batch_events[0], 0) != hipSuccess) rc = NSLGF_EHIP;
+        h->capturing = true;
         for (int i = 0; rc == NSLGF_OK && i < n; ++i) rc = herk_step(h, sts[i], h->branches[i % nb]);
+        h->capturing = false;
         for (int b = 0; rc == NSLGF_OK && b < nb; ++b) {
             if (hipEventRecord(h->batch_events[b + 1], h->branches[b]) != hipSuccess ||
                 hipStreamWaitEvent(h->capture, h->batch_events[b + 1], 0) != hipSuccess)
@@ -918,11 +983,19 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
         ProfScope ps(h, "batch_graph", s);
         NSLGF_HIP_CHECK(hipGraphLaunch(h->batch->exec, s));
     }
+    int rc = NSLGF_OK;
     for (int i = 0; i < n; ++i) {
         sts[i]->t += sts[i]->dt;
         sts[i]->stage_done = 3;
+        if (sts[i]->guard) {
+            const unsigned long long* acc = (const unsigned long long*)((const char*)sts[i]->work +
+                                                                        state_guard_offset(sts[i]->nx, sts[i]->ny,
+                                                                                           sts[i]->nz, sts[i]->dtype));
+            const int g = read_guard(sts[i], acc, s);
+            if (rc == NSLGF_OK) rc = g;
+        }
     }
-    return NSLGF_OK;
+    return rc;
 }
 
 int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx, int dtype, void* stream) {
@@ -1160,6 +1233,18 @@ int herk_run_adaptive(nslgf_t h, nslgf_state* st, int nsteps, int block, double 
     char* wbase = (char*)st->work + L.t1 * es;
     char* abase = wbase + (size_t)3 * M * es;
     int nre = 0, nedge = 0;
+    // the state's own domain (its masks or the n_buf rule) is back in place on every return: the
+    // masks of this run live in handle memory that the next adaptive run reuses
+    struct RestoreMasks {
+        nslgf_state* st;
+        const unsigned char *supp, *soln;
+        int block;
+        ~RestoreMasks() {
+            st->supp_blocks = supp;
+            st->soln_blocks = soln;
+            st->block = block;
+        }
+    } restore{st, st->supp_blocks, st->soln_blocks, st->block};
     for (int step = 0; step < nsteps; ++step) {
         // the domain of this step from the block weights of u (Sec. 4.3)
         NSLGF_PROF(h, "nonlinear", s, launch_stencil(NSLGF_OP_NONLINEAR, dt_, st->u, h->tmp3.p, 3, nx, ny, nz, st->dx, s));

@@ -181,6 +181,11 @@ int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int n
 // points at least nbuf away from every box face; dev_mu, dev_nu hold one value per block (x fastest)
 int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int ny, int nz, int nb, int nbuf, double dx,
                          double* dev_mu, double* dev_nu, hipStream_t s);
+// step guard (guard.hip): acc[0] = max (bits of a nonnegative double) of the FP64 |Dbar u| over the cells at
+// least margin (>= 1) from every face, acc[1] += non-finite values of u (and d when set); reset clears both
+int launch_guard_reset(unsigned long long* acc, hipStream_t s);
+int launch_guard(int dtype, const void* u, const void* d, int nx, int ny, int nz, int margin, double dx,
+                 unsigned long long* acc, hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);

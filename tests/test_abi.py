@@ -46,9 +46,11 @@ def test_host_lgf_value_matches_oracle():
 def test_state_bytes():
     L = nslgf.lib()
     # 25 fields of the box (q, w1, w2, r, pressure, two 6-component IF temporaries) plus the
-    # one-component convolution workspaces
+    # one-component convolution workspaces, then 256 bytes of step-guard accumulators at a 256-byte
+    # boundary
     b64, b32 = L.nslgf_state_bytes(8, 8, 8, 0), L.nslgf_state_bytes(8, 8, 8, 1)
-    assert b64 >= 25 * 512 * 8 and b64 == 2 * b32
+    assert b64 >= 25 * 512 * 8 + 256 and b32 >= 25 * 512 * 4 + 256
+    assert b64 % 256 == 0 and b32 % 256 == 0 and b64 > b32
     assert L.nslgf_state_bytes(0, 8, 8, 0) == 0
     assert L.nslgf_state_bytes(8, 300, 8, 0) == 0
 
@@ -68,6 +70,7 @@ def test_null_handle_is_rejected_without_a_device():
         L.herk_run_adaptive(None, None, 1, 4, 1e-4, 1e-2, 1, ctypes.byref(i), ctypes.byref(i), None),
         L.flow_diagnostics(None, None, 8, 8, 8, 1, 0.1, org, 0, buf, None),
         L.block_weights(None, None, 8, 8, 8, 4, 1, 0.1, 0, buf, buf, None),
+        L.herk_check(None, None, 1, ctypes.byref(d), None),
     ]
     assert all(c == -1 for c in calls), calls
     assert b"null handle" in L.nslgf_last_error()

@@ -62,3 +62,20 @@ def test_batched_rejects_shared_buffers():
     st = nslgf.HerkState(u, dx, dt, re)
     with pytest.raises(nslgf.NslgfError):
         nslgf.herk_step_batched([st, st])
+
+
+def test_table_rebuild_recaptures_the_batch_graph():
+    """lgf_table rebuilds a box's plan (a new spectrum buffer); a batch captured before must not replay
+    with the freed spectrum: the next batched step is captured again and equals a plain step."""
+    u, dx, dt, re = _problem(24, 10, torch.float64)
+    st = nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2)
+    nslgf.herk_step_batched([st])
+    nslgf.lgf_table(24, 24, 24, torch.float64)
+    # allocations after the rebuild may land on the freed spectrum's memory; write over them
+    junk = [torch.full((24 ** 3 * 8,), float("nan"), dtype=torch.float64, device=DEV) for _ in range(4)]
+    solo = nslgf.HerkState(st.u.clone(), dx, dt, re, "A", n_buf=2)
+    solo.step()
+    nslgf.herk_step_batched([st])
+    torch.cuda.synchronize()
+    assert torch.equal(solo.u, st.u) and torch.equal(solo.d, st.d)
+    del junk

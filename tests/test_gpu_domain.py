@@ -169,3 +169,30 @@ def test_full_size_refresh_weights_and_integrals():
     assert nu.max() > 0 and mu.shape == (16, 16, 16)
     r = nslgf.flow_diagnostics(u, dx, dg.box_origin((n, n, n), dx), 16)
     assert abs(r["I"][2] / (math.pi * (ring.R ** 2 + ring.sigma ** 2 / 2)) - 1) < 1e-4
+
+
+def test_run_adaptive_leaves_the_state_domain_in_place():
+    """An adaptive run classifies into handle memory and restores the state's own masks when it
+    returns: a state given masks by set_blocks keeps them after its adaptive run, even after another
+    state's adaptive run on a larger box has reused (and grown) the handle's mask memory."""
+    n, dx, ring, re, cfl = workloads.small_ring_case(24, seed=6)
+    u0 = ifherk.vor2vel(workloads.ring_edge_vorticity(n, dx, ring), dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    inner = np.zeros((6, 6, 6), dtype=np.uint8)
+    inner[1:-1, 1:-1, 1:-1] = 1
+    b = torch.from_numpy(u0).to(DEV)
+    sb = nslgf.HerkState(b, dx, dt, 100.0, "A", n_buf=0)
+    sb.set_blocks(inner, inner, 4)
+    sb.run_adaptive(2, 4, 1e-4, 1e-1, 1)
+    assert sb.c.supp_blocks == sb._blocks[0].data_ptr() and sb.c.soln_blocks == sb._blocks[1].data_ptr()
+    assert sb.c.block == 4
+    m, dxm, rm, rem, cflm = workloads.small_ring_case(40, seed=7)
+    um = ifherk.vor2vel(workloads.ring_edge_vorticity(m, dxm, rm), dxm)
+    sc = nslgf.HerkState(torch.from_numpy(um).to(DEV), dxm, ifherk.dt_from_cfl(um, dxm, cflm), 100.0, "A", n_buf=1)
+    sc.run_adaptive(1, 2, 1e-4, 1e-1, 1)
+    assert sc.c.supp_blocks is None and sc.c.soln_blocks is None
+    ref = nslgf.HerkState(b.clone(), dx, dt, 100.0, "A", n_buf=0)
+    ref.set_blocks(inner, inner, 4)
+    ref.step()
+    sb.step()
+    assert torch.equal(ref.u, sb.u) and torch.equal(ref.d, sb.d)

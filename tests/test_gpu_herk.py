@@ -57,7 +57,7 @@ def test_step_parity_wide_integrating_factor(scheme):
     dt = ifherk.dt_from_cfl(u0, dx, cfl)
     re_v = dt / (dx * dx * 3.0)
     u_ref, d_ref = ifherk.step(u0, dt, dx, re_v, scheme, n_buf=2)
-    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+    for dtype, tol in ((torch.float64, 1e-12), (torch.float32, 1e-6)):
         u = torch.from_numpy(u0).to(DEV, dtype)
         st = nslgf.HerkState(u, dx, dt, re_v, scheme, n_buf=2)
         st.step()
@@ -80,7 +80,7 @@ def test_two_steps_and_fp32():
     st32 = nslgf.HerkState(u32, dx, dt, re, "A", n_buf=2)
     st32.step()
     st32.step()
-    assert rel(u32.double().cpu().numpy(), u2) < 1e-5
+    assert rel(u32.double().cpu().numpy(), u2) < 1e-6
 
 
 def test_stage_order_enforced():
@@ -171,3 +171,24 @@ def test_full_size_step_properties(case):
     assert np.abs(dv[inner]).max() < 1e-10 * np.abs(un).max() / dx
     c = n // 2
     assert un[2, c, c, c] > 0
+
+
+@pytest.mark.parametrize("scheme,n", [("A", 24), ("B", 28), ("C", 24), ("A", 32)])
+def test_one_step_fp32_against_oracle(scheme, n):
+    """One FP32 step against the FP64 oracle's plain recursion: the velocity within 1e-6 of max|u|
+    (the FP32 target).  The pressure is looser (1e-5): d comes from L^{-1} Dbar r, where r is within
+    FP32 rounding of a divergence-free field, so the FP32 rounding of r (about 6e-8 |u|) enters the
+    pressure source against a physical source of order a~ dt |u|^2 / dx^2 and the pressure error is
+    about 6e-8 sqrt(n) / (a~ CFL) of max|d| before the solve's own rounding (measured: u 1.6e-7 to
+    1.8e-7, d 4e-7 to 1.8e-6 over Schemes A, B, C at n = 24 to 32)."""
+    n, dx, w, re, cfl = _case(n, seed=11)
+    u0 = ifherk.vor2vel(w, dx)
+    dt = ifherk.dt_from_cfl(u0, dx, cfl)
+    u_ref, d_ref = ifherk.step(u0, dt, dx, re, scheme, n_buf=2)
+    u = torch.from_numpy(u0).to(DEV, torch.float32)
+    st = nslgf.HerkState(u, dx, dt, re, scheme, n_buf=2)
+    st.step()
+    eu = rel(u.double().cpu().numpy(), u_ref)
+    ed = rel(st.d.double().cpu().numpy(), d_ref)
+    assert eu < 1e-6, eu
+    assert ed < 1e-5, ed

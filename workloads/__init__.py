@@ -177,3 +177,18 @@ def surrogate_specs(count: int, seed: int = 0):
     sigma/R ~ U[0.1, 0.3] and Re ~ U[250, 1000]; the ring starts half a radius below the centre."""
     rng = np.random.default_rng(seed)
     return [(float(rng.uniform(0.1, 0.3)), float(rng.uniform(250.0, 1000.0)), 2000 + i) for i in range(count)]
+
+
+def compact_blob(shape, centres, radius: float, seed: int, ncomp: int = 3) -> np.ndarray:
+    """Compactly supported random field for parity tests on elongated boxes: i.i.d. N(0,1) values
+    times the smooth window (1 - r^2 / radius^2)^3 around each centre (index units, (k, j, i)),
+    zero where r >= radius, the windows of several centres added.  Returns float64
+    [ncomp, *shape]."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    win = np.zeros(shape)
+    for (ck, cj, ci) in centres:
+        r2 = ((k - ck) ** 2 + (j - cj) ** 2 + (i - ci) ** 2) / (radius * radius)
+        win += np.where(r2 < 1.0, (1.0 - r2) ** 3, 0.0)
+    return rng.standard_normal((ncomp,) + tuple(shape)) * win
