@@ -97,6 +97,25 @@ int lgf_convolve(nslgf_t h, const void *src, void *dst, int ncomp, int nx, int n
                  int dtype, void *stream);
 
 /*
+ * Allocation-free form of lgf_convolve, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same operation, plan and
+ * kernels (results equal lgf_convolve's bit for bit), with the two convolution workspaces taken from a
+ * fixed device array of NSLGF_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends; the call makes no hipMalloc, hipFree or other allocating call.  The box's
+ * plan must exist: call lgf_table(h, nx, ny, nz, dtype) first, under the same FFT-plan choice
+ * (NSLGF_ESTATE otherwise).  The workspaces take
+ *     ncomp * nz * (ny + Py) * XP * 2 * sizeof(dtype) bytes (+ alignment),  XP = Px/2 + 1 rounded up to 8,
+ * NSLGF_EINVAL beyond the array (it holds, for example, one FP64 component of a 128^3 box or three FP32
+ * components of a 96^3 box).
+ * Every call on a device shares that device's array and leaves its last contents there: calls that
+ * overlap in time on one device (concurrent streams, several host threads or handles) race; calls in
+ * one stream are ordered and safe.  Per-kernel profiling is not recorded for this call.
+ */
+#define NSLGF_NOALLOC_SCRATCH_BYTES (128u << 20)
+int lgf_convolve_noalloc(nslgf_t h, const void *src, void *dst, int ncomp, int nx, int ny, int nz, double dx,
+                         int dtype, void *stream);
+
+/*
  * Integrating factor (Sec. 2.3, Eqs. if_def and ddifussion_soln; kernel of Appendix B):
  *     dst_q(n) = sum_{m in box} prod_j w[|n_j - m_j|] src_q(m),  w[k] = e^{-2 alpha} I_k(2 alpha),
  * i.e. dst = M E(alpha) M src, the solution operator of the discrete heat equation over

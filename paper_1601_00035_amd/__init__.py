@@ -62,6 +62,7 @@ def lib():
                     "lgf_value": [i, i, i, ctypes.POINTER(d)],
                     "lgf_table": [vp, i, i, i, i, vp],
                     "lgf_convolve": [vp, vp, vp, i, i, i, i, d, i, vp],
+                    "lgf_convolve_noalloc": [vp, vp, vp, i, i, i, i, d, i, vp],
                     "if_apply": [vp, vp, vp, i, i, i, i, d, i, vp],
                     "herk_stage": [vp, ctypes.POINTER(_State), i, vp],
                     "herk_step": [vp, ctypes.POINTER(_State), vp],
@@ -176,6 +177,20 @@ def lgf_convolve(src: torch.Tensor, dx: float = 1.0, out: torch.Tensor | None = 
         raise ValueError("out must match src")
     _check("lgf_convolve", lib().lgf_convolve(handle(src.device.index), src.data_ptr(), out.data_ptr(), ncomp, nx, ny,
                                               nz, float(dx), _dtype(src), _stream(src)))
+    return out
+
+
+def lgf_convolve_noalloc(src: torch.Tensor, dx: float, out: torch.Tensor) -> torch.Tensor:
+    """lgf_convolve without any device allocation inside the library (workspaces in its fixed scratch
+    array); lgf_table must have been called for the box and dtype, and out is the caller's."""
+    _dev(src, "src")
+    _dev(out, "out")
+    ncomp, nx, ny, nz = _box(src)
+    if out.shape != src.shape or out.dtype != src.dtype:
+        raise ValueError("out must match src")
+    _check("lgf_convolve_noalloc", lib().lgf_convolve_noalloc(handle(src.device.index), src.data_ptr(),
+                                                              out.data_ptr(), ncomp, nx, ny, nz, float(dx),
+                                                              _dtype(src), _stream(src)))
     return out
 
 

@@ -125,6 +125,8 @@ struct nslgf_ctx {
         if (capture) (void)hipStreamDestroy(capture);
     }
     bool capturing = false;  // a batch graph is being captured (no host round trips)
+    bool no_alloc = false;   // inside lgf_convolve_noalloc: lookups that would allocate fail instead
+    void* scratch = nullptr; // this device's address of the library's fixed scratch array
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
@@ -133,9 +135,38 @@ struct nslgf_ctx {
 
 namespace nslgf {
 
+// Fixed device scratch of the allocation-free convolution: each device that loads the library holds
+// its own copy for the life of the process.  Host code never passes the array's name to a kernel (it
+// is a host-side stand-in there); it uses the device address taken by hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[NSLGF_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;  // device -> address of `scratch` on that device
+
+// Address of `scratch` on the current device `device` (taken once per device).
+static int scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(device);
+    if (it == g_scratch_addr.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            set_error(std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+            return NSLGF_EHIP;
+        }
+        it = g_scratch_addr.emplace(device, ptr).first;
+    }
+    *out = it->second;
+    return NSLGF_OK;
+}
+
 static int get_twiddles(nslgf_ctx* h, int L, int dtype, const void** out) {
     auto key = std::make_pair(L, dtype);
     auto it = h->twiddles.find(key);
+    if (it == h->twiddles.end() && h->no_alloc) {
+        set_error("lgf_convolve_noalloc: no twiddle table for this box and dtype; call lgf_table first");
+        return NSLGF_ESTATE;
+    }
     if (it == h->twiddles.end()) {
         void* d = nullptr;
         NSLGF_TRY(make_twiddles(L, dtype, &d));
@@ -692,6 +723,11 @@ int nslgf_create(nslgf_t* h, int device) {
         return NSLGF_ENOMEM;
     }
     c->device = device;
+    const int rc = scratch_address(device, &c->scratch);
+    if (rc != NSLGF_OK) {
+        delete c;
+        return rc;
+    }
     *h = c;
     return NSLGF_OK;
 }
@@ -736,6 +772,41 @@ int lgf_convolve(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int n
     ConvPlan* p = nullptr;
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, (hipStream_t)stream, &p));
     return run_conv_shared(h, *p, src, dst, ncomp, dx * dx, (hipStream_t)stream);
+}
+
+int lgf_convolve_noalloc(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
+                         int dtype, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(src && dst, "lgf_convolve_noalloc: null pointer");
+    NSLGF_CHECK_ARG(src != dst, "lgf_convolve_noalloc: src and dst must differ");
+    NSLGF_CHECK_ARG(ncomp >= 1 && ncomp <= 3, "lgf_convolve_noalloc: ncomp must be 1..3");
+    NSLGF_CHECK_ARG(std::isfinite(dx) && dx > 0, "lgf_convolve_noalloc: dx must be > 0");
+    auto it = h->plans.find(std::make_tuple(nx, ny, nz, dtype, h->fft_plan));
+    if (it == h->plans.end()) {
+        set_error("lgf_convolve_noalloc: no plan for this box and dtype; call lgf_table first");
+        return NSLGF_ESTATE;
+    }
+    ConvPlan& p = *it->second;
+    const size_t es = dtype_size(dtype);
+    const size_t a1 = (size_t)ncomp * conv_ws_elems_a1(p) * es;
+    const size_t a1r = (a1 + 255) / 256 * 256;
+    const size_t a2 = (size_t)ncomp * conv_ws_elems_a2(p) * es;
+    if (a1r + a2 > (size_t)NSLGF_NOALLOC_SCRATCH_BYTES) {
+        set_error("lgf_convolve_noalloc: the convolution needs " + std::to_string(a1r + a2) +
+                  " bytes of workspace, more than the scratch array's " +
+                  std::to_string((size_t)NSLGF_NOALLOC_SCRATCH_BYTES));
+        return NSLGF_EINVAL;
+    }
+    char* base = (char*)h->scratch;  // this device's address of `scratch`, taken when the handle was created
+    const bool prof = h->prof.on;     // profiling would create events
+    h->prof.on = false;
+    h->no_alloc = true;
+    const int rc = run_conv(h, p, src, dst, ncomp, dx * dx, (hipStream_t)stream, base, base + a1r);
+    h->no_alloc = false;
+    h->prof.on = prof;
+    return rc;
 }
 
 int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
