@@ -94,3 +94,102 @@ def test_repeated_masked_factors_follow_the_single_factor_estimate():
             rep = (line[20] - line[k - 1]) / line[20]
             est = refresh.trunc_error(q * alpha, k)
             assert 1.0 - 1e-9 <= rep / est <= 1.2, (q, k, rep, est)
+
+
+# ---- the multi-step drivers (Sec. 4.3, 4.4): control flow pinned on small boxes -------------------
+
+def _compact_velocity(n=12, lo=5, hi=7, dx=0.3, seed=8):
+    """u0 = Cbar a with a random potential on the cells [lo, hi)^3: divergence free, compact, and with
+    vorticity that the integrating factors carry outwards step by step."""
+    rng = np.random.default_rng(seed)
+    a = np.zeros((3, n, n, n))
+    a[:, lo:hi, lo:hi, lo:hi] = rng.standard_normal((3, hi - lo, hi - lo, hi - lo))
+    u = stencils.curl_bar(a, dx)
+    return u * (0.5 / np.abs(u).max()), dx
+
+
+def test_run_refreshes_after_every_q_cap_steps():
+    """With eps so large that every estimate passes, q_max = q_cap: five steps at q_cap = 2 are
+    step, step, refresh, step, step, refresh, step, and the refreshes are not no-ops here."""
+    u0, dx = _compact_velocity()
+    dt, re, n_buf = 0.2, 100.0, 2
+    u, d, nref, qs = refresh.run(u0, 5, dt, dx, re, "A", n_buf, eps=1e9, q_cap=2)
+    assert nref == 2 and qs == [2, 2, 2]
+    v = u0
+    for k in range(1, 6):
+        v, dv = ifherk.step(v, dt, dx, re, "A", n_buf=n_buf)
+        if k in (2, 4):
+            w = refresh.velocity_refresh(v, dx, n_buf)
+            assert np.abs(w - v).max() > 1e-6 * np.abs(v).max()
+            v = w
+    assert np.array_equal(u, v) and np.array_equal(d, dv)
+
+
+def test_run_refreshes_exactly_after_q_steps_for_eps_between_estimates():
+    """eps between the estimates after q and q + 1 steps (Appendix D) gives q_max = q: q - 1 steps take
+    no refresh and equal plain steps; q steps end with one refresh of the q-step velocity."""
+    u0, dx = _compact_velocity(seed=9)
+    dt, re, n_buf, q = 0.2, 100.0, 2, 3
+    beta = dt / (dx * dx * re)
+    um = refresh.component_max(u0, n_buf)
+    lo, hi = refresh.estimate(beta, q, n_buf, um), refresh.estimate(beta, q + 1, n_buf, um)
+    assert lo < hi
+    eps = math.sqrt(lo * hi)
+    plain = [u0]
+    for _ in range(q):
+        plain.append(ifherk.step(plain[-1], dt, dx, re, "A", n_buf=n_buf)[0])
+    u, _, nref, qs = refresh.run(u0, q - 1, dt, dx, re, "A", n_buf, eps)
+    assert nref == 0 and qs == [q] and np.array_equal(u, plain[q - 1])
+    u, _, nref, qs = refresh.run(u0, q, dt, dx, re, "A", n_buf, eps)
+    assert nref == 1 and qs[0] == q and len(qs) == 2
+    assert np.array_equal(u, refresh.velocity_refresh(plain[q], dx, n_buf))
+    with pytest.raises(ValueError):  # a buffer too thin for eps: no step can be taken
+        refresh.run(u0, 1, dt, dx, re, "A", n_buf, eps=1e-300)
+
+
+def test_run_adaptive_first_step_only_sets_the_domain():
+    """The first classification sets D_supp and D_soln without re-initialising: one adaptive step is the
+    plain step on the block masks of u0's weights."""
+    from oracle import blocks
+
+    u0, dx = _compact_velocity()
+    dt, re, nb, n_buf = 0.2, 100.0, 3, 1
+    u, d, nre, Ws, edge = refresh.run_adaptive(u0, 1, dt, dx, re, "A", n_buf, nb, 0.0, 1e-1, 0)
+    mu, nu = blocks.weights(u0, dx, nb, n_buf)
+    W, supp, soln, xsoln = blocks.classify(mu, nu, 0.0, 1e-1, 0)
+    assert nre == 0 and np.array_equal(Ws[0], W)
+    ref_u, ref_d = ifherk.step(u0, dt, dx, re, "A", soln_mask=blocks.cell_mask(soln, nb, u0.shape[1:]),
+                               supp_mask=blocks.cell_mask(supp, nb, u0.shape[1:]))
+    assert np.array_equal(u, ref_u) and np.array_equal(d, ref_d)
+
+
+def test_run_adaptive_reinitialises_from_the_new_support_when_the_domain_changes():
+    """A compact vortex blob in the central blocks: its support domain (W > 0) grows after the first
+    step, as the integrating factor carries vorticity into the neighbouring blocks.  The second step
+    must re-initialise u from the vorticity on the NEW support (Eq. vel_refresh) before stepping; the
+    count of re-initialisations equals the number of changes of the classified masks; the edge flags
+    say whether D_xsoln reached the outer block layer."""
+    from oracle import blocks
+
+    u0, dx = _compact_velocity()
+    shape = u0.shape[1:]
+    dt, re, nb, n_buf, es, eo = 0.2, 100.0, 3, 1, 0.0, 1e-1
+    u, d, nre, Ws, edge = refresh.run_adaptive(u0, 3, dt, dx, re, "A", n_buf, nb, es, eo, 0)
+    masks = [((W > es).astype(np.uint8), (W > eo).astype(np.uint8)) for W in Ws]
+    changes = sum(1 for k in range(1, 3) if not (np.array_equal(masks[k][0], masks[k - 1][0])
+                                                  and np.array_equal(masks[k][1], masks[k - 1][1])))
+    assert nre == changes >= 1
+    assert not np.array_equal(masks[1][0], masks[0][0])  # the support grew after the first step
+    for W, e in zip(Ws, edge):
+        sol = W > eo
+        assert e == bool(sol[0].any() or sol[-1].any() or sol[:, 0].any() or sol[:, -1].any()
+                         or sol[:, :, 0].any() or sol[:, :, -1].any())
+    # the two steps written out: step on the first masks, re-initialise from the new support, step
+    cm = [(blocks.cell_mask(s, nb, shape), blocks.cell_mask(o, nb, shape)) for s, o in masks]
+    v1, _ = ifherk.step(u0, dt, dx, re, "A", soln_mask=cm[0][1], supp_mask=cm[0][0])
+    new = ifherk.vor2vel(cm[1][0] * stencils.curl(v1, dx), dx)
+    old = ifherk.vor2vel(cm[0][0] * stencils.curl(v1, dx), dx)
+    assert np.abs(new - old).max() > 1e-6 * np.abs(new).max()  # the choice of support matters here
+    v2, d2 = ifherk.step(new, dt, dx, re, "A", soln_mask=cm[1][1], supp_mask=cm[1][0])
+    u2, dd2, nre2, _, _ = refresh.run_adaptive(u0, 2, dt, dx, re, "A", n_buf, nb, es, eo, 0)
+    assert nre2 == 1 and np.array_equal(u2, v2) and np.array_equal(dd2, d2)
