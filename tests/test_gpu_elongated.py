@@ -1,0 +1,62 @@
+"""Oracle parity on the code paths the 256^3 benchmark runs, reached on an elongated box small enough
+for the oracle: (nz, ny, nx) = (200, 136, 16).  Its z axis pads to 512 (the length-512 column plans
+and the fused z pass of the step's pressure solves), its planes have more than 128 rows (the fused
+x-y integrating-factor pass splits them into row tiles, with halo rows taken across the tile
+boundary and w^{i,i} written per owned row), and its z lines are long enough for the interior
+segments of the z integrating-factor pass.  Expected values: the oracle's integrating factor and
+plain-recursion IF-HERK steps (Schemes A and C), sampled by tests/golden/make_elongated.py (rows
+around the tile boundary in ten planes, 24 whole z lines, 4000 seeded points)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_00035_amd as nslgf
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_elongated as mk  # noqa: E402  (the generator's input recipe; it calls workloads only)
+
+Z = np.load(os.path.join(HERE, "golden", "elongated_box.npz"))
+IDX = Z["idx"]
+
+
+def _u0(dtype):
+    return torch.from_numpy(mk.initial_velocity()).to(DEV, dtype)
+
+
+def _samples(t, ncomp):
+    return t.double().cpu().numpy().reshape(ncomp, -1)[:, IDX]
+
+
+def test_golden_matches_the_recipe():
+    assert tuple(Z["shape"]) == mk.SHAPE and float(Z["dx"]) == mk.DX and float(Z["re"]) == mk.RE
+    from oracle import ifherk  # the step size of the recipe: CFL rule on the same input
+
+    assert float(Z["dt"]) == ifherk.dt_from_cfl(mk.initial_velocity(), mk.DX, mk.CFL)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-6)])
+def test_if_apply_elongated(dtype, tol):
+    out = nslgf.if_apply(_u0(dtype), float(Z["alpha_if"]))
+    err = np.abs(_samples(out, 3) - Z["if_samples"]).max() / float(Z["if_max"])
+    assert err < tol, err
+
+
+@pytest.mark.parametrize("scheme", ["A", "C"])
+@pytest.mark.parametrize("dtype,tol_u,tol_d", [(torch.float64, 1e-12, 1e-12), (torch.float32, 1e-6, 1e-5)])
+def test_step_elongated(scheme, dtype, tol_u, tol_d):
+    u = _u0(dtype)
+    st = nslgf.HerkState(u, float(Z["dx"]), float(Z["dt"]), float(Z["re"]), scheme, n_buf=int(Z["n_buf"]))
+    st.step()
+    eu = np.abs(_samples(u, 3) - Z[f"u_{scheme}"]).max() / float(Z[f"umax_{scheme}"])
+    ed = np.abs(_samples(st.d, 1)[0] - Z[f"d_{scheme}"]).max() / float(Z[f"dmax_{scheme}"])
+    assert eu < tol_u, eu
+    assert ed < tol_d, ed
+    # the full-field maxima agree too (the samples need not contain the extreme points)
+    assert abs(u.abs().max().item() / float(Z[f"umax_{scheme}"]) - 1) < 10 * tol_u

@@ -84,31 +84,72 @@ class Ring:
         wt = self.gamma / (math.pi * self.sigma ** 2) * np.exp(-((rho - rc) ** 2 + z * z) / self.sigma ** 2)
         return -wt * np.sin(th), wt * np.cos(th), np.zeros_like(wt)
 
+    def extent(self, cutoff: float = 9.0):
+        """(rmax, zmax): beyond rho = rmax or |z - zc| = zmax the Gaussian core is below
+        exp(-cutoff^2)."""
+        return self.R * (1.0 + 10.0 * abs(self.eps)) + cutoff * self.sigma, cutoff * self.sigma + abs(self.zc)
+
+
+@dataclass
+class BumpRing:
+    """The "fat" vortex ring of the refinement studies (Sec. 6.1, Eq. initial_omega_bump), axis z,
+    centred at the origin:
+
+        omega_theta(r, z) = Gamma / (alpha R^2) exp(-4 s^2 / (R^2 - s^2))  for s <= R, else 0,
+        s^2 = z^2 + (r - R)^2,  omega_z = 0,
+
+    with alpha = 0.54857674, the value printed with the equation.  The equation prints alpha as a
+    factor, but the stated purpose (omega_theta integrates to Gamma over a meridional half-plane) needs
+    it as a divisor: alpha is the integral of the unscaled bump, 2 pi int_0^1 exp(-4t^2/(1-t^2)) t dt
+    = 0.548576742...  Its vorticity is compactly supported (0 <= r <= 2R, |z| <= R) and smooth, also at
+    the axis."""
+
+    R: float = 1.0
+    gamma: float = 1.0
+    alpha: float = 0.54857674
+
+    def omega_theta(self, r, z):
+        s2 = z * z + (r - self.R) ** 2
+        inside = s2 < self.R * self.R
+        d = np.where(inside, self.R * self.R - s2, 1.0)
+        return np.where(inside, self.gamma / (self.alpha * self.R ** 2) * np.exp(-4.0 * s2 / d), 0.0)
+
+    def omega(self, x, y, z):
+        rho = np.sqrt(x * x + y * y)
+        th = np.arctan2(y, x)
+        wt = self.omega_theta(rho, z)
+        return -wt * np.sin(th), wt * np.cos(th), np.zeros_like(wt)
+
+    def extent(self, cutoff: float = 9.0):
+        """(rmax, zmax): the vorticity vanishes beyond rho = rmax or |z| = zmax."""
+        return 2.0 * self.R, self.R
+
 
 def _gauss_legendre(q: int):
     x, w = np.polynomial.legendre.leggauss(q)
     return 0.5 * x, 0.5 * w  # nodes on [-1/2, 1/2], weights summing to 1
 
 
-def ring_edge_vorticity(n: int, dx: float, ring: Ring, quad: int = 4, cutoff: float = 9.0) -> np.ndarray:
+def ring_edge_vorticity(n: int, dx: float, ring, quad: int = 4, cutoff: float = 9.0,
+                        origin: float | None = None) -> np.ndarray:
     """Discrete vorticity w on the edges: w(q) = (flux of omega_q through the dual face of the
     edge) / dx^2, each flux by quad x quad Gauss-Legendre.  Returns float64 [3, n, n, n].
 
-    Cells further than `cutoff` core radii from the nominal ring centreline are skipped
-    (the Gaussian there is below exp(-81))."""
+    Vertex (0, 0, 0) sits at (origin, origin, origin); the default origin -(n - 1) dx / 2 centres the
+    box on the ring.  Cells outside the ring's extent (for the Gaussian core, further than `cutoff`
+    core radii from the nominal centreline, where it is below exp(-81)) are skipped."""
     w = np.zeros((3, n, n, n))
-    c = (n - 1) / 2.0
+    o = -(n - 1) / 2.0 * dx if origin is None else float(origin)
     gx, gw = _gauss_legendre(quad)
-    rmax = ring.R * (1.0 + 10.0 * abs(ring.eps)) + cutoff * ring.sigma
-    zmax = cutoff * ring.sigma + abs(ring.zc)
+    rmax, zmax = ring.extent(cutoff)
     idx = np.arange(n)
     for q in range(3):
         # edge (q) position offsets in index units: -1/2 along axis q
         off = [0.0, 0.0, 0.0]
         off[q] = -0.5
-        xs = (idx + off[0] - c) * dx
-        ys = (idx + off[1] - c) * dx
-        zs = (idx + off[2] - c) * dx
+        xs = o + (idx + off[0]) * dx
+        ys = o + (idx + off[1]) * dx
+        zs = o + (idx + off[2]) * dx
         ix = np.nonzero(np.abs(xs) <= rmax + dx)[0]
         iy = np.nonzero(np.abs(ys) <= rmax + dx)[0]
         iz = np.nonzero(np.abs(zs) <= zmax + dx)[0]
