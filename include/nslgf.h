@@ -372,6 +372,30 @@ int nslgf_plan_info(nslgf_t h, int nx, int ny, int nz, int dtype, void *stream, 
 int nslgf_copy(nslgf_t h, const void *src, void *dst, size_t n, int dtype, void *stream);
 int nslgf_profile_read(nslgf_t h, int index, char *name, int name_cap, long long *calls, double *total_ms);
 
+/*
+ * Launch tuner.  Per box and dtype the library chooses the column-plan variants of the convolution
+ * (see nslgf_set_fft_plan), the rows per workgroup of the fused x-y integrating-factor pass (64, 128,
+ * 256), the outputs per thread of the strided z pass (16, 32) and the workgroup shape of the point
+ * kernels (0: 64x4, 1: 128x2, 2: 32x8, 3: 256x1 threads).  None of the launch shapes changes the
+ * arithmetic (results are bit-identical); the column variants change the order of rounding only.
+ *   NSLGF_TUNE_DEFAULT  the measured defaults (128 rows, 32 outputs, 64x4, the default column plans);
+ *   NSLGF_TUNE_AUTO     the first use of a box and dtype times every choice on the device on zero fields
+ *                       of that box (one synchronisation) and keeps the fastest.
+ * Choices recorded for a box (tuned, or read by nslgf_tuning_load) are used in either mode, unless an
+ * explicit column plan is set with nslgf_set_fft_plan.  nslgf_tuning_info returns, building or tuning
+ * as needed, out[0..4] = y variant, z variant, IF rows, IF z outputs per thread, point-kernel shape.
+ * nslgf_tuning_save writes every recorded choice as JSON (format "nslgf-tuning-1": one object per box
+ * with nx, ny, nz, dtype "f64"/"f32", the padded lengths Px, Py, Pz, vy, vz, launch (1 if the launch
+ * shapes were tuned), if_rows, if_seg, cell_shape); nslgf_tuning_load reads such a file (NSLGF_EINVAL for
+ * a malformed file or an entry whose padded lengths or choices do not fit this library) and drops the
+ * plans and batch graph that the loaded choices replace.
+ */
+enum nslgf_tune { NSLGF_TUNE_DEFAULT = 0, NSLGF_TUNE_AUTO = 1 };
+int nslgf_set_tuning(nslgf_t h, int mode);
+int nslgf_tuning_info(nslgf_t h, int nx, int ny, int nz, int dtype, void *stream, int *out);
+int nslgf_tuning_save(nslgf_t h, const char *path);
+int nslgf_tuning_load(nslgf_t h, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

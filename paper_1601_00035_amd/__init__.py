@@ -87,6 +87,10 @@ def lib():
                     "herk_run_adaptive": [vp, ctypes.POINTER(_State), i, i, d, d, i, ctypes.POINTER(i),
                                           ctypes.POINTER(i), vp],
                     "classify_blocks": [vp, vp, i, i, i, d, d, i, vp, vp, vp, vp],
+                    "nslgf_set_tuning": [vp, i],
+                    "nslgf_tuning_info": [vp, i, i, i, i, vp, ctypes.POINTER(i)],
+                    "nslgf_tuning_save": [vp, ctypes.c_char_p],
+                    "nslgf_tuning_load": [vp, ctypes.c_char_p],
                 }
                 for name, args in sig.items():
                     f = getattr(L, name)
@@ -337,6 +341,37 @@ def set_fft_plan(choice: int, device: int | None = None):
     default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread (FP64), -2 autotune
     (time every variant when a plan is built and keep the fastest)."""
     _check("nslgf_set_fft_plan", lib().nslgf_set_fft_plan(handle(device), int(choice)))
+
+
+TUNE_DEFAULT, TUNE_AUTO = 0, 1
+CELL_SHAPES = ((64, 4), (128, 2), (32, 8), (256, 1))
+
+
+def set_tuning(mode: int, device: int | None = None):
+    """TUNE_DEFAULT: the measured default launch shapes; TUNE_AUTO: time every choice on the first use of
+    a box and dtype and keep the fastest (launch shapes never change results; column plans change the
+    order of rounding only)."""
+    _check("nslgf_set_tuning", lib().nslgf_set_tuning(handle(device), int(mode)))
+
+
+def tuning_info(nx: int, ny: int, nz: int, dtype=torch.float64, device: int | None = None) -> dict:
+    """The choices used for a box and dtype (tuned first if the handle tunes and none is recorded)."""
+    out = (ctypes.c_int * 5)()
+    code = F64 if dtype == torch.float64 else F32
+    dev = torch.cuda.current_device() if device is None else device
+    s = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check("nslgf_tuning_info", lib().nslgf_tuning_info(handle(dev), nx, ny, nz, code, s, out))
+    return {"vy": out[0], "vz": out[1], "if_rows": out[2], "if_seg": out[3], "cell_shape": out[4]}
+
+
+def tuning_save(path: str, device: int | None = None):
+    """Write every recorded choice (JSON, format nslgf-tuning-1)."""
+    _check("nslgf_tuning_save", lib().nslgf_tuning_save(handle(device), os.fsencode(path)))
+
+
+def tuning_load(path: str, device: int | None = None):
+    """Read recorded choices written by tuning_save (they replace the defaults for their boxes)."""
+    _check("nslgf_tuning_load", lib().nslgf_tuning_load(handle(device), os.fsencode(path)))
 
 
 def plan_info(nx: int, ny: int, nz: int, dtype=torch.float64, device: int | None = None) -> tuple:

@@ -2,6 +2,8 @@
 // workspaces), the integrating factor, the IF-HERK stage driver and Vor2Vel.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <iterator>
 #include <map>
@@ -102,6 +104,14 @@ struct Profiler {
 }  // namespace nslgf
 
 namespace nslgf {
+// The launch tuner's record of one box and dtype: the launch shapes (once tuned or loaded) and the
+// column-plan variants (-1 until a tuned or loaded plan sets them).
+struct TuneEntry {
+    Tuning t;
+    bool launch_set = false;
+    int vy = -1, vz = -1;
+};
+
 // One captured batch step, reused while the batch (boxes, pointers, step parameters) is unchanged.
 struct BatchGraph {
     std::vector<unsigned long long> key;
@@ -128,6 +138,9 @@ struct nslgf_ctx {
     bool no_alloc = false;   // inside lgf_convolve_noalloc: lookups that would allocate fail instead
     void* scratch = nullptr; // this device's address of the library's fixed scratch array
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
+    int tune_mode = NSLGF_TUNE_DEFAULT;
+    // launch shapes per (nx, ny, nz, dtype): tuned on first use in NSLGF_TUNE_AUTO, or loaded from a file
+    std::map<std::tuple<int, int, int, int>, nslgf::TuneEntry> tunings;
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, tmp3b, partial, blockmask;
@@ -364,6 +377,13 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
     p.XP = ((p.Px / 2 + 1 + 7) / 8) * 8;
     p.vy = col_variant_choice(p.Py, dtype, h->fft_plan);
     p.vz = col_variant_choice(p.Pz, dtype, h->fft_plan);
+    auto te = h->tunings.find(std::make_tuple(nx, ny, nz, dtype));
+    const bool loaded = h->fft_plan == -1 && te != h->tunings.end() && te->second.vy >= 0 && te->second.vz >= 0 &&
+                        col_variant_valid(p.Py, dtype, te->second.vy) && col_variant_valid(p.Pz, dtype, te->second.vz);
+    if (loaded) {  // a tuned choice recorded for this box (by the tuner or from a tuning file)
+        p.vy = te->second.vy;
+        p.vz = te->second.vz;
+    }
     p.tb = col_tile_width(p.Pz, dtype);
     p.tiles = ceil_div(p.Px / 2 + 1, p.tb);
     // FP64 kernel on the padded lattice and its spectrum
@@ -409,7 +429,14 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
     NSLGF_TRY(p.khat.ensure(kbytes));
     NSLGF_TRY(extract_spectrum(spec.p, p.Px, p.Py, p.Pz, p.XP, 1.0 / (double)ktot, p.tb, p.tiles, dtype, p.khat.p, s));
     NSLGF_HIP_CHECK(hipStreamSynchronize(s));
-    if (h->fft_plan == NSLGF_FFT_PLAN_AUTOTUNE) NSLGF_TRY(autotune_plan(h, p, s));
+    if (h->fft_plan == NSLGF_FFT_PLAN_AUTOTUNE || (h->tune_mode == NSLGF_TUNE_AUTO && !loaded && h->fft_plan == -1)) {
+        NSLGF_TRY(autotune_plan(h, p, s));
+        if (h->fft_plan == -1) {
+            TuneEntry& e = h->tunings[std::make_tuple(nx, ny, nz, dtype)];
+            e.vy = p.vy;
+            e.vz = p.vz;
+        }
+    }
     *out = plan.get();
     h->plans.emplace(key, std::move(plan));
     return NSLGF_OK;
@@ -421,6 +448,89 @@ static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** t
     NSLGF_TRY(get_twiddles(h, p.Px, dt, twf));
     NSLGF_TRY(get_twiddles(h, p.Py, dt, twy));
     NSLGF_TRY(get_twiddles(h, p.Pz, dt, twz));
+    return NSLGF_OK;
+}
+
+// Launch tuner: times, on zero fields of the box, the fused x-y integrating-factor pass for 64, 128 and
+// 256 rows per workgroup, the strided z pass for 16 and 32 outputs per thread, and the stage kernel
+// (the largest point kernel) for every point-kernel shape, and keeps the fastest of each.  None of
+// these choices changes the arithmetic.  Runs once per box and dtype, outside any capture.
+static int autotune_launch(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, Tuning* out) {
+    const size_t f3 = (size_t)3 * nx * ny * nz * dtype_size(dtype);
+    DevBuf a, b, c, d;
+    NSLGF_TRY(a.ensure(f3));
+    NSLGF_TRY(b.ensure(f3));
+    NSLGF_TRY(c.ensure(f3));
+    NSLGF_TRY(d.ensure(f3));
+    for (DevBuf* x : {&a, &b, &c, &d}) NSLGF_HIP_CHECK(hipMemsetAsync(x->p, 0, x->bytes, s));
+    double w[kIfMaxRadius + 1];
+    const int rad = if_weights(0.02, dtype, w, kIfMaxRadius);  // the step's typical factor (beta / 2)
+    const bool prof = h->prof.on;
+    h->prof.on = false;
+    Tuning t;
+    float best = 3.4e38f;
+    int rc = NSLGF_OK;
+    for (int rows : {64, 128, 256}) {
+        if (rc != NSLGF_OK || (rows > 64 && ny <= rows / 2)) break;  // one tile already covers the plane
+        const IfCombine cb{{a.p, nullptr, nullptr}, {1.0, 0.0, 0.0}};
+        float ms = 0.f;
+        rc = time_min_ms(s, 3, [&] { return launch_if_xy(dtype, cb, b.p, 3, nx, ny, nz, w, rad, s, rows); }, &ms);
+        if (rc == NSLGF_OK && ms < best) {
+            best = ms;
+            t.if_rows = rows;
+        }
+    }
+    best = 3.4e38f;
+    for (int seg : {32, 16}) {
+        if (rc != NSLGF_OK) break;
+        float ms = 0.f;
+        rc = time_min_ms(s, 3, [&] { return launch_if_axis(2, dtype, b.p, a.p, 3, nx, ny, nz, w, rad, s, seg); }, &ms);
+        if (rc == NSLGF_OK && ms < best) {
+            best = ms;
+            t.if_seg = seg;
+        }
+    }
+    best = 3.4e38f;
+    for (int shape = 0; shape < kCellShapeCount && rc == NSLGF_OK; ++shape) {
+        StageCoef cf{};
+        cf.c_q = 1.0;
+        cf.c_w1 = 0.5;
+        cf.c_g = -0.5;
+        float ms = 0.f;
+        rc = time_min_ms(s, 3, [&] {
+            return launch_stage_rhs(dtype, a.p, b.p, c.p, nullptr, d.p, cf, nx, ny, nz, 1.0, s, shape);
+        }, &ms);
+        if (rc == NSLGF_OK && ms < best) {
+            best = ms;
+            t.cell_shape = shape;
+        }
+    }
+    h->prof.on = prof;
+    NSLGF_TRY(rc);
+    NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+    *out = t;
+    return NSLGF_OK;
+}
+
+// Launch shapes for a box and dtype: a tuned or loaded entry, else (in NSLGF_TUNE_AUTO, outside a
+// capture) tuned now, else the defaults.
+static int get_tuning(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, Tuning* out) {
+    auto key = std::make_tuple(nx, ny, nz, dtype);
+    auto it = h->tunings.find(key);
+    if (it != h->tunings.end() && it->second.launch_set) {
+        *out = it->second.t;
+        return NSLGF_OK;
+    }
+    if (h->tune_mode == NSLGF_TUNE_AUTO && !h->capturing && !h->no_alloc) {
+        Tuning t;
+        NSLGF_TRY(autotune_launch(h, nx, ny, nz, dtype, s, &t));
+        TuneEntry& e = h->tunings[key];
+        e.t = t;
+        e.launch_set = true;
+        *out = t;
+        return NSLGF_OK;
+    }
+    *out = Tuning{};
     return NSLGF_OK;
 }
 
@@ -534,7 +644,7 @@ static int run_conv_shared(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst
 
 // IF application through two temporaries (x: src -> t1, y: t1 -> t2, z: t2 -> dst); src == dst allowed.
 static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha, int dtype,
-                  hipStream_t s, void* t1, void* t2) {
+                  hipStream_t s, void* t1, void* t2, const Tuning& tn) {
     const long long n = (long long)nx * ny * nz;
     if (alpha == 0.0) {
         // identity: an elementwise kernel copy (no memory-copy nodes when the caller captures a graph)
@@ -547,8 +657,8 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
     if (r < 0) return NSLGF_EINVAL;
     if (r >= 1 && r <= kIfFixedMaxRadius) {
         const IfCombine cb{{src, nullptr, nullptr}, {1.0, 0.0, 0.0}};
-        NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
-        NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s));
+        NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s, tn.if_rows));
+        NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s, tn.if_seg));
         return NSLGF_OK;
     }
     NSLGF_PROF(h, "if_x", s, launch_if_axis(0, dtype, src, t1, ncomp, nx, ny, nz, w, r, s));
@@ -561,28 +671,28 @@ static int run_if(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, i
 // combination is formed while the fused x-y pass loads its input, so it never makes a round trip
 // through memory; identity and runtime-radius cases combine first into dst.
 static int run_if_combined(nslgf_ctx* h, const IfCombine& cb, void* dst, int ncomp, int nx, int ny, int nz,
-                           double alpha, int dtype, hipStream_t s, void* t1, void* t2) {
+                           double alpha, int dtype, hipStream_t s, void* t1, void* t2, const Tuning& tn) {
     const long long n = (long long)nx * ny * nz;
     if (alpha != 0.0) {
         double w[kIfMaxRadius + 1];
         const int r = if_weights(alpha, dtype, w, kIfMaxRadius);
         if (r < 0) return NSLGF_EINVAL;
         if (r >= 1 && r <= kIfFixedMaxRadius) {
-            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s));
-            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s));
+            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, ncomp, nx, ny, nz, w, r, s, tn.if_rows));
+            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, ncomp, nx, ny, nz, w, r, s, tn.if_seg));
             return NSLGF_OK;
         }
     }
     NSLGF_PROF(h, "axpby", s,
                launch_axpby(dtype, dst, cb.p[0], cb.c[0], cb.p[1], cb.c[1], cb.p[2], cb.c[2], ncomp * n, s));
-    return run_if(h, dst, dst, ncomp, nx, ny, nz, alpha, dtype, s, t1, t2);
+    return run_if(h, dst, dst, ncomp, nx, ny, nz, alpha, dtype, s, t1, t2, tn);
 }
 
 // u = M E(alpha) M (r - G dhat) with the stage's w update, the projection formed while the fused x-y
 // pass loads (r - G dhat never makes a round trip through memory); alpha = 0 or runtime radii project
 // first into r.
 static int run_if_projected(nslgf_ctx* h, void* r, const IfProject& pj, void* dst, int nx, int ny, int nz,
-                            double alpha, int dtype, double dx, hipStream_t s, void* t1, void* t2) {
+                            double alpha, int dtype, double dx, hipStream_t s, void* t1, void* t2, const Tuning& tn) {
     if (alpha != 0.0) {
         double w[kIfMaxRadius + 1];
         const int rad = if_weights(alpha, dtype, w, kIfMaxRadius);
@@ -590,25 +700,25 @@ static int run_if_projected(nslgf_ctx* h, void* r, const IfProject& pj, void* ds
         if (rad >= 1 && rad <= kIfFixedMaxRadius && nx <= 256) {
             IfCombine cb{{r, nullptr, nullptr}, {1.0, 0.0, 0.0}};
             cb.proj = &pj;
-            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, 3, nx, ny, nz, w, rad, s));
-            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, 3, nx, ny, nz, w, rad, s));
+            NSLGF_PROF(h, "if_xy", s, launch_if_xy(dtype, cb, t1, 3, nx, ny, nz, w, rad, s, tn.if_rows));
+            NSLGF_PROF(h, "if_z", s, launch_if_axis(2, dtype, t1, dst, 3, nx, ny, nz, w, rad, s, tn.if_seg));
             return NSLGF_OK;
         }
     }
     void* proj_out = alpha == 0.0 ? dst : r;
     NSLGF_PROF(h, "stage_project", s,
                launch_stage_project(dtype, r, proj_out, pj.dhat, pj.q, pj.w1, nullptr, pj.c_q, pj.c_w1, 0.0, pj.wnew,
-                                    pj.inv, nx, ny, nz, dx, s));
-    if (alpha != 0.0) NSLGF_TRY(run_if(h, r, dst, 3, nx, ny, nz, alpha, dtype, s, t1, t2));
+                                    pj.inv, nx, ny, nz, dx, s, tn.cell_shape));
+    if (alpha != 0.0) NSLGF_TRY(run_if(h, r, dst, 3, nx, ny, nz, alpha, dtype, s, t1, t2, tn));
     return NSLGF_OK;
 }
 
 static int run_if_shared(nslgf_ctx* h, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double alpha,
-                         int dtype, hipStream_t s) {
+                         int dtype, hipStream_t s, const Tuning& tn) {
     const size_t bytes = (size_t)ncomp * nx * ny * nz * dtype_size(dtype);
     NSLGF_TRY(h->if_tmp1.ensure(bytes));
     NSLGF_TRY(h->if_tmp2.ensure(bytes));
-    return run_if(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, s, h->if_tmp1.p, h->if_tmp2.p);
+    return run_if(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, s, h->if_tmp1.p, h->if_tmp2.p, tn);
 }
 
 // Layout of an IF-HERK state's workspace, in elements of its dtype.
@@ -817,7 +927,9 @@ int if_apply(nslgf_t h, const void* src, void* dst, int ncomp, int nx, int ny, i
     NSLGF_CHECK_ARG(src && dst, "if_apply: null pointer");
     NSLGF_CHECK_ARG(ncomp >= 1 && ncomp <= 6, "if_apply: ncomp must be 1..6");
     NSLGF_CHECK_ARG(std::isfinite(alpha) && alpha >= 0.0, "if_apply: alpha must be >= 0");
-    return run_if_shared(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, (hipStream_t)stream);
+    Tuning tn;
+    NSLGF_TRY(get_tuning(h, nx, ny, nz, dtype, (hipStream_t)stream, &tn));
+    return run_if_shared(h, src, dst, ncomp, nx, ny, nz, alpha, dtype, (hipStream_t)stream, tn);
 }
 
 size_t nslgf_state_bytes(int nx, int ny, int nz, int dtype) {
@@ -864,6 +976,8 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     const double alpha = (ct[stage] - ct[stage - 1]) * beta;
     ConvPlan* plan = nullptr;
     NSLGF_TRY(build_plan(h, nx, ny, nz, dt_, s, &plan));
+    Tuning tn;
+    NSLGF_TRY(get_tuning(h, nx, ny, nz, dt_, s, &tn));
     StageCoef c{};
     c.nbuf = st->n_buf;
     c.soln_blocks = st->soln_blocks;
@@ -873,20 +987,23 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
     if (stage == 1) {
         c.c_q = 1.0;
         c.copy_q = 1;
-        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s,
+                   launch_stage_rhs(dt_, st->u, q, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s, tn.cell_shape));
     } else if (stage == 2) {
         const double a_prev = (ct[1] - ct[0]) * beta;
-        NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s, t1, t2));  // q and w1 are adjacent
+        NSLGF_TRY(run_if(h, q, q, 6, nx, ny, nz, a_prev, dt_, s, t1, t2, tn));  // q and w1 are adjacent
         c.c_q = 1.0;
         c.c_w1 = dt * at[2][1];
-        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s,
+                   launch_stage_rhs(dt_, st->u, q, w1, nullptr, r, c, nx, ny, nz, st->dx, s, tn.cell_shape));
     } else {
         // final-stage form: r^3 = H^2 (q^2 + dt (a~31 w^{2,1} + a~32 w^{2,2})) + g^3
         const double a_prev = (ct[2] - ct[1]) * beta;
         const IfCombine cb{{q, w1, w2}, {1.0, dt * at[3][1], dt * at[3][2]}};
-        NSLGF_TRY(run_if_combined(h, cb, r, 3, nx, ny, nz, a_prev, dt_, s, t1, t2));
+        NSLGF_TRY(run_if_combined(h, cb, r, 3, nx, ny, nz, a_prev, dt_, s, t1, t2, tn));
         c.c_q = 1.0;
-        NSLGF_PROF(h, "stage_rhs", s, launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s));
+        NSLGF_PROF(h, "stage_rhs", s,
+                   launch_stage_rhs(dt_, st->u, r, nullptr, nullptr, r, c, nx, ny, nz, st->dx, s, tn.cell_shape));
     }
     // pressure source M_supp Dbar r, formed while the convolution's first pass loads
     const DivSource dsrc{r, st->n_buf, 1.0 / st->dx, st->supp_blocks, st->block};
@@ -908,7 +1025,7 @@ int herk_stage(nslgf_t h, nslgf_state* st, int stage, void* stream) {
         pj.wnew = w2;
         pj.inv = inv;
     }
-    NSLGF_TRY(run_if_projected(h, r, pj, st->u, nx, ny, nz, alpha, dt_, st->dx, s, t1, t2));
+    NSLGF_TRY(run_if_projected(h, r, pj, st->u, nx, ny, nz, alpha, dt_, st->dx, s, t1, t2, tn));
     if (stage == 3) {
         NSLGF_PROF(h, "axpby", s, launch_axpby(dt_, st->d, dhat, 1.0 / (at[3][3] * dt), nullptr, 0.0, nullptr, 0.0, M, s));
         st->t += dt;
@@ -963,7 +1080,7 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
     NSLGF_CHECK_ARG(sts != nullptr && n >= 1 && n <= 4096, "herk_step_batched: need 1..4096 states");
     hipStream_t s = (hipStream_t)stream;
     std::vector<unsigned long long> key;
-    key.reserve((size_t)n * 19);
+    key.reserve((size_t)n * 22);
     auto bits = [](double v) {
         unsigned long long b;
         std::memcpy(&b, &v, sizeof b);
@@ -983,7 +1100,10 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
         NSLGF_TRY(build_plan(h, st->nx, st->ny, st->nz, st->dtype, s, &p));
         const void *a, *b, *c, *d;
         NSLGF_TRY(plan_twiddles(h, *p, st->dtype, &a, &b, &c, &d));
-        const unsigned long long k[] = {(unsigned long long)st->nx, (unsigned long long)st->ny,
+        Tuning tn;  // (tuned now if the handle tunes, so that the capture only looks it up)
+        NSLGF_TRY(get_tuning(h, st->nx, st->ny, st->nz, st->dtype, s, &tn));
+        const unsigned long long k[] = {(unsigned long long)tn.if_rows, (unsigned long long)tn.if_seg,
+                                        (unsigned long long)tn.cell_shape,(unsigned long long)st->nx, (unsigned long long)st->ny,
                                         (unsigned long long)st->nz, (unsigned long long)st->dtype,
                                         (unsigned long long)st->scheme, (unsigned long long)st->n_buf,
                                         bits(st->dx), bits(st->dt), bits(st->re),
@@ -1080,8 +1200,11 @@ int vor2vel(nslgf_t h, const void* w, void* u, int nx, int ny, int nz, double dx
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
     const long long M = (long long)nx * ny * nz;
     NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * dtype_size(dtype)));
+    Tuning tn;
+    NSLGF_TRY(get_tuning(h, nx, ny, nz, dtype, s, &tn));
     NSLGF_TRY(run_conv_shared(h, *p, w, h->tmp3.p, 3, -dx * dx, s));  // a = -L^{-1} w
-    NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s));
+    NSLGF_PROF(h, "curl_bar", s,
+               launch_stencil(NSLGF_OP_CURL_BAR, dtype, h->tmp3.p, u, 3, nx, ny, nz, dx, s, tn.cell_shape));
     return NSLGF_OK;
 }
 
@@ -1090,9 +1213,12 @@ static int refresh_into(nslgf_t h, void* u, int nx, int ny, int nz, int n_buf, d
                         void* abuf, hipStream_t s, const unsigned char* blocks = nullptr, int nb = 0) {
     ConvPlan* p = nullptr;
     NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
-    NSLGF_PROF(h, "curl_masked", s, launch_masked_curl(dtype, u, wbuf, n_buf, blocks, nb, nx, ny, nz, dx, s));
+    Tuning tn;
+    NSLGF_TRY(get_tuning(h, nx, ny, nz, dtype, s, &tn));
+    NSLGF_PROF(h, "curl_masked", s,
+               launch_masked_curl(dtype, u, wbuf, n_buf, blocks, nb, nx, ny, nz, dx, s, tn.cell_shape));
     NSLGF_TRY(run_conv_shared(h, *p, wbuf, abuf, 3, -dx * dx, s));
-    NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, abuf, u, 3, nx, ny, nz, dx, s));
+    NSLGF_PROF(h, "curl_bar", s, launch_stencil(NSLGF_OP_CURL_BAR, dtype, abuf, u, 3, nx, ny, nz, dx, s, tn.cell_shape));
     return NSLGF_OK;
 }
 
@@ -1423,6 +1549,152 @@ int nslgf_copy(nslgf_t h, const void* src, void* dst, size_t n, int dtype, void*
     NSLGF_CHECK_ARG(src && dst && src != dst, "nslgf_copy: null or aliased pointers");
     hipStream_t s = (hipStream_t)stream;
     NSLGF_PROF(h, "copy", s, launch_copy(src, dst, n * dtype_size(dtype), s));
+    return NSLGF_OK;
+}
+
+int nslgf_set_tuning(nslgf_t h, int mode) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(mode == NSLGF_TUNE_DEFAULT || mode == NSLGF_TUNE_AUTO, "nslgf_set_tuning: unknown mode");
+    h->tune_mode = mode;
+    return NSLGF_OK;
+}
+
+int nslgf_tuning_info(nslgf_t h, int nx, int ny, int nz, int dtype, void* stream, int* out) {
+    NSLGF_ENTER(h);
+    NSLGF_TRY(check_box(nx, ny, nz));
+    NSLGF_TRY(check_dtype(dtype));
+    NSLGF_CHECK_ARG(out != nullptr, "nslgf_tuning_info: null output");
+    hipStream_t s = (hipStream_t)stream;
+    ConvPlan* p = nullptr;
+    NSLGF_TRY(build_plan(h, nx, ny, nz, dtype, s, &p));
+    Tuning tn;
+    NSLGF_TRY(get_tuning(h, nx, ny, nz, dtype, s, &tn));
+    out[0] = p->vy;
+    out[1] = p->vz;
+    out[2] = tn.if_rows;
+    out[3] = tn.if_seg;
+    out[4] = tn.cell_shape;
+    return NSLGF_OK;
+}
+
+int nslgf_tuning_save(nslgf_t h, const char* path) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(path != nullptr, "nslgf_tuning_save: null path");
+    std::string txt = "{\n  \"format\": \"nslgf-tuning-1\",\n  \"entries\": [";
+    bool first = true;
+    for (const auto& kv : h->tunings) {
+        const int nx = std::get<0>(kv.first), ny = std::get<1>(kv.first), nz = std::get<2>(kv.first);
+        const int dt = std::get<3>(kv.first);
+        const TuneEntry& e = kv.second;
+        const Tuning t = e.launch_set ? e.t : Tuning{};
+        char line[512];
+        std::snprintf(line, sizeof line,
+                      "%s\n    {\"nx\": %d, \"ny\": %d, \"nz\": %d, \"dtype\": \"%s\", \"Px\": %d, \"Py\": %d, "
+                      "\"Pz\": %d, \"vy\": %d, \"vz\": %d, \"launch\": %d, \"if_rows\": %d, \"if_seg\": %d, "
+                      "\"cell_shape\": %d}",
+                      first ? "" : ",", nx, ny, nz, dt == NSLGF_F32 ? "f32" : "f64", padded(nx), padded(ny), padded(nz),
+                      e.vy, e.vz, e.launch_set ? 1 : 0, t.if_rows, t.if_seg, t.cell_shape);
+        txt += line;
+        first = false;
+    }
+    txt += "\n  ]\n}\n";
+    FILE* f = std::fopen(path, "w");
+    if (!f) {
+        set_error(std::string("nslgf_tuning_save: cannot open ") + path);
+        return NSLGF_EINVAL;
+    }
+    const bool ok = std::fwrite(txt.data(), 1, txt.size(), f) == txt.size();
+    if (std::fclose(f) != 0 || !ok) {
+        set_error(std::string("nslgf_tuning_save: write failed for ") + path);
+        return NSLGF_EINVAL;
+    }
+    return NSLGF_OK;
+}
+
+// Reads the integer (or "f32"/"f64" string) value of "key" inside one JSON object's text.
+static bool json_field(const std::string& obj, const char* key, int* out) {
+    const std::string k = std::string("\"") + key + "\"";
+    const size_t at = obj.find(k);
+    if (at == std::string::npos) return false;
+    size_t p = obj.find(':', at + k.size());
+    if (p == std::string::npos) return false;
+    ++p;
+    while (p < obj.size() && (obj[p] == ' ' || obj[p] == '\t' || obj[p] == '\n')) ++p;
+    if (p < obj.size() && obj[p] == '"') {
+        const size_t q = obj.find('"', p + 1);
+        if (q == std::string::npos) return false;
+        const std::string v = obj.substr(p + 1, q - p - 1);
+        if (v == "f64") *out = NSLGF_F64;
+        else if (v == "f32") *out = NSLGF_F32;
+        else return false;
+        return true;
+    }
+    char* end = nullptr;
+    const long v = std::strtol(obj.c_str() + p, &end, 10);
+    if (end == obj.c_str() + p) return false;
+    *out = (int)v;
+    return true;
+}
+
+int nslgf_tuning_load(nslgf_t h, const char* path) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(path != nullptr, "nslgf_tuning_load: null path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) {
+        set_error(std::string("nslgf_tuning_load: cannot open ") + path);
+        return NSLGF_EINVAL;
+    }
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    if (txt.find("\"nslgf-tuning-1\"") == std::string::npos) {
+        set_error("nslgf_tuning_load: not an nslgf-tuning-1 file");
+        return NSLGF_EINVAL;
+    }
+    size_t pos = txt.find("\"entries\"");
+    if (pos == std::string::npos) {
+        set_error("nslgf_tuning_load: no entries");
+        return NSLGF_EINVAL;
+    }
+    std::vector<std::pair<std::tuple<int, int, int, int>, TuneEntry>> read;
+    while ((pos = txt.find('{', pos)) != std::string::npos) {
+        const size_t end = txt.find('}', pos);
+        if (end == std::string::npos) break;
+        const std::string obj = txt.substr(pos, end - pos + 1);
+        pos = end + 1;
+        int nx, ny, nz, dt, Px, Py, Pz, vy, vz, launch, rows, seg, shape;
+        if (!(json_field(obj, "nx", &nx) && json_field(obj, "ny", &ny) && json_field(obj, "nz", &nz) &&
+              json_field(obj, "dtype", &dt) && json_field(obj, "Px", &Px) && json_field(obj, "Py", &Py) &&
+              json_field(obj, "Pz", &Pz) && json_field(obj, "vy", &vy) && json_field(obj, "vz", &vz) &&
+              json_field(obj, "launch", &launch) && json_field(obj, "if_rows", &rows) &&
+              json_field(obj, "if_seg", &seg) && json_field(obj, "cell_shape", &shape))) {
+            set_error("nslgf_tuning_load: an entry lacks a field");
+            return NSLGF_EINVAL;
+        }
+        if (check_box(nx, ny, nz) != NSLGF_OK || check_dtype(dt) != NSLGF_OK || Px != padded(nx) ||
+            Py != padded(ny) || Pz != padded(nz) || (rows != 64 && rows != 128 && rows != 256) ||
+            (seg != 16 && seg != 32) || shape < 0 || shape >= kCellShapeCount ||
+            (vy >= 0 && !col_variant_valid(Py, dt, vy)) || (vz >= 0 && !col_variant_valid(Pz, dt, vz))) {
+            set_error("nslgf_tuning_load: an entry does not fit this library (sizes, padded lengths or choices)");
+            return NSLGF_EINVAL;
+        }
+        TuneEntry e;
+        e.t.if_rows = rows;
+        e.t.if_seg = seg;
+        e.t.cell_shape = shape;
+        e.launch_set = launch != 0;
+        e.vy = vy;
+        e.vz = vz;
+        read.emplace_back(std::make_tuple(nx, ny, nz, dt), e);
+    }
+    // plans built before under the default choice are rebuilt with the loaded variants on next use
+    for (const auto& kv : read) {
+        h->tunings[kv.first] = kv.second;
+        h->plans.erase(std::tuple_cat(kv.first, std::make_tuple(-1)));
+    }
+    h->batch.reset();
     return NSLGF_OK;
 }
 

@@ -140,7 +140,7 @@ struct IfTerms {
 };
 
 // Fused x and y passes (fixed radius R): a workgroup owns one (component, z) plane and S consecutive
-// output rows y0 .. y0 + S - 1, one thread per x (nx <= 256).  It walks the rows from y0 - R upwards,
+// output rows y0 .. y0 + S - 1 (S set per box by the launch tuner), one thread per x (nx <= 256).  It walks the rows from y0 - R upwards,
 // RB rows per step: each thread holds the raw values of the next P steps in registers (loads issued
 // P steps ahead), the step's rows go through a double-buffered LDS tile with R zeros at both ends of
 // each row (one barrier per step), each x-filtered value is rounded to the dtype and pushed into a
@@ -153,11 +153,11 @@ struct IfTerms {
 // the workgroup that owns its output row).
 // Workgroups are numbered so that all row blocks of one plane run on one XCD (the hardware hands
 // workgroup b to XCD b mod 8) and share their halo rows through its L2.
-template <typename T, int R, int S, int RB, int P, int MODE>
+template <typename T, int R, int RB, int P, int MODE>
 __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz,
-                                               int ntiles, IfWeights wts, IfTerms terms) {
+                                               int ntiles, int S, IfWeights wts, IfTerms terms) {
     constexpr int W = 256 + 2 * R;  // LDS row length
-    constexpr int NSTEP = (S + 2 * R + RB - 1) / RB;
+    const int NSTEP = (S + 2 * R + RB - 1) / RB;
     constexpr int NW = 2 * R + RB;  // register window (x-filtered rows)
     __shared__ T tile_lds[2][RB][W];
     const int nb = (int)gridDim.x, b = (int)blockIdx.x, xcd = b % 8;
@@ -293,29 +293,34 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
     }
 }
 
-constexpr int kIfSegment = 32;  // outputs per thread of the strided passes
-
-constexpr int kIfRowsPerBlock = 128;  // output rows per workgroup of the fused x-y pass (halo rows re-read: 2R / 128)
+// Outputs per thread of the strided passes: 32 by default, 16 where the launch tuner finds it faster.
 constexpr int kIfRowsPerStep = 4;    // rows per barrier of the fused x-y pass
 constexpr int kIfPrefetch = 2;       // steps loaded ahead by the fused x-y pass
 
 template <typename T, int R>
 static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
-                         hipStream_t s) {
+                         hipStream_t s, int seg) {
     const long long n = (long long)nx * ny * nz;
     const int len = axis == 1 ? ny : nz;
     const long long stride = axis == 1 ? (long long)nx : (long long)nx * ny;
     const int nouter = axis == 1 ? nz : ny;
     const long long outer_stride = axis == 1 ? (long long)nx * ny : (long long)nx;
-    dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, kIfSegment), 4), nouter * ncomp);
-    hipLaunchKernelGGL((k_if_strided<T, R, kIfSegment>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
-                       outer_stride, n, wts);
+    if (seg == 16) {
+        dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, 16), 4), nouter * ncomp);
+        hipLaunchKernelGGL((k_if_strided<T, R, 16>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
+                           outer_stride, n, wts);
+    } else {
+        dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, 32), 4), nouter * ncomp);
+        hipLaunchKernelGGL((k_if_strided<T, R, 32>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
+                           outer_stride, n, wts);
+    }
 }
 
+// (rows: output rows per workgroup; halo rows re-read: 2R / rows)
 template <typename T, int R>
 static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
-                      hipStream_t s) {
-    const int ntiles = ceil_div(ny, kIfRowsPerBlock);
+                      hipStream_t s, int rows) {
+    const int ntiles = ceil_div(ny, rows);
     const dim3 grid((unsigned)((long long)ntiles * nz * ncomp));
     const T* in = (const T*)cb.p[0];
     IfTerms terms{};
@@ -329,25 +334,25 @@ static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, in
         terms.c_q = pj.c_q;
         terms.c_w1 = pj.c_w1;
         terms.inv = pj.inv;
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_PROJ>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, wts, terms);
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_PROJ>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
     } else if (cb.p[1]) {
         terms.in1 = cb.p[1];
         terms.in2 = cb.p[2];
         terms.c0 = cb.c[0];
         terms.c1 = cb.c[1];
         terms.c2 = cb.c[2];
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_COMB>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, wts, terms);
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_COMB>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
     } else {
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerBlock, kIfRowsPerStep, kIfPrefetch, IF_IN_PLAIN>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, wts, terms);
+        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_PLAIN>), grid, dim3(256), 0,
+                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
     }
 }
 
 template <typename T>
 static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int ny, int nz, const double* w,
-                     int radius, hipStream_t s) {
+                     int radius, hipStream_t s, int seg) {
     IfWeights wts;
     for (int k = 0; k <= kIfMaxRadius; ++k) wts.w[k] = k <= radius ? w[k] : 0.0;
     const long long n = (long long)nx * ny * nz;
@@ -355,7 +360,7 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
     T* dst = (T*)out;
     if (axis != 0) {
         switch (radius) {
-#define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(axis, src, dst, ncomp, nx, ny, nz, wts, s); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
+#define NSLGF_IF_R(R_) case R_: launch_fixed<T, R_>(axis, src, dst, ncomp, nx, ny, nz, wts, s, seg); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
             NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
             NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
 #undef NSLGF_IF_R
@@ -389,12 +394,12 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
 
 template <typename T>
 static int if_xy_t(const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w, int radius,
-                   hipStream_t s) {
+                   hipStream_t s, int rows) {
     IfWeights wts;
     for (int k = 0; k <= kIfMaxRadius; ++k) wts.w[k] = k <= radius ? w[k] : 0.0;
     T* dst = (T*)out;
     switch (radius) {
-#define NSLGF_IF_R(R_) case R_: launch_xy<T, R_>(cb, dst, ncomp, nx, ny, nz, wts, s); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
+#define NSLGF_IF_R(R_) case R_: launch_xy<T, R_>(cb, dst, ncomp, nx, ny, nz, wts, s, rows); NSLGF_LAUNCH_CHECK(); return NSLGF_OK;
         NSLGF_IF_R(1) NSLGF_IF_R(2) NSLGF_IF_R(3) NSLGF_IF_R(4) NSLGF_IF_R(5) NSLGF_IF_R(6) NSLGF_IF_R(7)
         NSLGF_IF_R(8) NSLGF_IF_R(9) NSLGF_IF_R(10) NSLGF_IF_R(11) NSLGF_IF_R(12)
 #undef NSLGF_IF_R
@@ -405,7 +410,7 @@ static int if_xy_t(const IfCombine& cb, void* out, int ncomp, int nx, int ny, in
 }
 
 int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
-                 int radius, hipStream_t s) {
+                 int radius, hipStream_t s, int rows) {
     if (!cb.p[0] || (cb.p[2] && !cb.p[1]) || (cb.proj && (cb.p[1] || ncomp != 3 || !cb.proj->dhat ||
                                                           (cb.proj->wnew && !cb.proj->q)))) {
         set_error("if_apply: bad input combination");
@@ -415,14 +420,22 @@ int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, i
         set_error("if_apply: the fused x-y pass needs nx <= 256");
         return NSLGF_EUNSUPPORTED;
     }
-    if (dtype == NSLGF_F32) return if_xy_t<float>(cb, out, ncomp, nx, ny, nz, w, radius, s);
-    return if_xy_t<double>(cb, out, ncomp, nx, ny, nz, w, radius, s);
+    if (rows != 64 && rows != 128 && rows != 256) {
+        set_error("if_apply: the fused x-y pass takes 64, 128 or 256 rows per workgroup");
+        return NSLGF_EINVAL;
+    }
+    if (dtype == NSLGF_F32) return if_xy_t<float>(cb, out, ncomp, nx, ny, nz, w, radius, s, rows);
+    return if_xy_t<double>(cb, out, ncomp, nx, ny, nz, w, radius, s, rows);
 }
 
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz, const double* w,
-                   int radius, hipStream_t s) {
-    if (dtype == NSLGF_F32) return if_axis_t<float>(axis, in, out, ncomp, nx, ny, nz, w, radius, s);
-    return if_axis_t<double>(axis, in, out, ncomp, nx, ny, nz, w, radius, s);
+                   int radius, hipStream_t s, int seg) {
+    if (seg != 16 && seg != 32) {
+        set_error("if_apply: the strided pass takes 16 or 32 outputs per thread");
+        return NSLGF_EINVAL;
+    }
+    if (dtype == NSLGF_F32) return if_axis_t<float>(axis, in, out, ncomp, nx, ny, nz, w, radius, s, seg);
+    return if_axis_t<double>(axis, in, out, ncomp, nx, ny, nz, w, radius, s, seg);
 }
 
 }  // namespace nslgf

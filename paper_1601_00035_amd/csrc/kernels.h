@@ -20,6 +20,15 @@ __device__ __forceinline__ bool in_domain(int i, int j, int k, int nx, int ny, i
     return i >= nbuf && i < nx - nbuf && j >= nbuf && j < ny - nbuf && k >= nbuf && k < nz - nbuf;
 }
 
+// Launch shapes of one box and dtype, chosen by the launch tuner (or the defaults): they change
+// the work split only, never the arithmetic, so every choice gives bit-identical results.
+constexpr int kCellShapeCount = 4;  // point-kernel workgroups 64x4, 128x2, 32x8, 256x1 (x by y threads)
+struct Tuning {
+    int if_rows = 128;   // output rows per workgroup of the fused x-y integrating-factor pass (64, 128, 256)
+    int if_seg = 32;     // outputs per thread of the strided (z) integrating-factor pass (16 or 32)
+    int cell_shape = 0;  // point-kernel workgroup shape index
+};
+
 // ---- FFT passes (lgf_conv.hip) ----------------------------------------------------------------
 // Supported padded lengths P (2,3,5-smooth, even) of the zero-padded convolution.
 bool fft_length_supported(int P);
@@ -98,7 +107,7 @@ int if_weights(double alpha, int dtype, double* w, int wmax);
 constexpr int kIfMaxRadius = 63;
 constexpr int kIfFixedMaxRadius = 12;  // radii with compile-time passes (larger ones run the runtime-radius passes)
 int launch_if_axis(int axis, int dtype, const void* in, void* out, int ncomp, int nx, int ny, int nz,
-                   const double* w, int radius, hipStream_t s);
+                   const double* w, int radius, hipStream_t s, int seg = 32);
 // Projection of an IF-HERK stage applied while the fused x-y pass loads (Sec. 3.2, Eq. ifherk_aux_1
 // and the w^{ii} update): the input is u = r - G dhat (r the 3-component p[0]), and where wnew is
 // given, wnew = (u - (c_q q + c_w1 w1)) inv is written too (w1 may be null).
@@ -121,7 +130,7 @@ struct IfCombine {
 // x and y passes in one launch (no intermediate field in HBM), for radius 1 .. kIfFixedMaxRadius and
 // nx <= 256 (else NSLGF_EUNSUPPORTED, launching nothing).  out must not overlap the inputs.
 int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, int ny, int nz, const double* w,
-                 int radius, hipStream_t s);
+                 int radius, hipStream_t s, int rows = 128);
 
 // ---- velocity refresh cadence (refresh.hip) -----------------------------------------------------
 // d_a(k) = sum_{n >= k} e^{-2a} I_n(2a) (k >= 1, a >= 0)
@@ -137,7 +146,7 @@ void classify_blocks_host(const double* mu, const double* nu, int bx, int by, in
 
 // ---- stencils (stencils.hip) --------------------------------------------------------------------
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
-                   hipStream_t s);
+                   hipStream_t s, int shape = 0);
 
 // Fused IF-HERK stage kernels (herk.hip)
 struct StageCoef {
@@ -151,7 +160,7 @@ struct StageCoef {
 };
 // r = c_q q + c_w1 w1 + c_w2 w2 + c_g M_soln Ntilde(u); (w pointers may be null)
 int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, const void* w2, void* r,
-                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s);
+                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s, int shape = 0);
 // s = M_supp Dbar r
 int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, int ny, int nz, double dx,
                       hipStream_t s);
@@ -159,7 +168,7 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
 // (optional)
 int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat, const void* q, const void* w1,
                          const void* w2, double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny,
-                         int nz, double dx, hipStream_t s);
+                         int nz, double dx, hipStream_t s, int shape = 0);
 // out = a*x + b*y + c*z (elementwise over n elements; y, z may be null)
 int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
                  long long n, hipStream_t s);
@@ -168,7 +177,7 @@ int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s);
 // e = M_supp C f (edges closer than nbuf points to a box face set to 0, or, when blocks is set, edges
 // outside the marked blocks of nb^3 cells)
 int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsigned char* blocks, int nb, int nx, int ny,
-                       int nz, double dx, hipStream_t s);
+                       int nz, double dx, hipStream_t s, int shape = 0);
 // per-workgroup maxima of |u^(q)| over the three components on the box shrunk by nbuf points
 int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
                    hipStream_t s);

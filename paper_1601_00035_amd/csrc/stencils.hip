@@ -86,21 +86,27 @@ __device__ __forceinline__ void nonlinear_at(const V& f, int i, int j, int k, T 
     out[2] = (T)0.25 * (e1_0 * (b000 + b00p) + e1_jm * (b0m0 + b0mp) - e2_0 * (a000 + a00p) - e2_im * (am00 + am0p));
 }
 
-// Point kernels run on (64 x 4)-thread blocks tiling (x, y), one z plane per grid z (no integer
-// division); launch with cell_grid / kCellBlock.  (Renumbering the blocks so that each XCD works
-// through a contiguous range of planes was measured slower for the stage kernels.)
+// Point kernels run on 256-thread blocks tiling (x, y) (64 x 4 by default; the launch tuner may
+// pick another of kCellShape), one z plane per grid z (no integer division); launch with cell_grid /
+// cell_block.  (Renumbering the blocks so that each XCD works through a contiguous range of planes
+// was measured slower for the stage kernels.)
 #define NSLGF_CELL_INDEX                                                                           \
     const long long n = (long long)nx * ny * nz;                                                   \
-    const int i = (int)(blockIdx.x * 64 + threadIdx.x);                                            \
-    const int j = (int)(blockIdx.y * 4 + threadIdx.y);                                             \
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);                                    \
+    const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);                                    \
     const int kz_ = (int)blockIdx.z;                                                               \
     const int k = kz_ % nz;                                                                        \
     if (i >= nx || j >= ny) return;                                                                \
     const long long idx = (long long)((k * ny + j) * nx + i);
 
-static const dim3 kCellBlock(64, 4);
-static dim3 cell_grid(int nx, int ny, int nz, int ncomp = 1) {
-    return dim3(ceil_div(nx, 64), ceil_div(ny, 4), nz * ncomp);
+static const int kCellShape[kCellShapeCount][2] = {{64, 4}, {128, 2}, {32, 8}, {256, 1}};
+static dim3 cell_block(int shape) {
+    const int k = (shape >= 0 && shape < kCellShapeCount) ? shape : 0;
+    return dim3(kCellShape[k][0], kCellShape[k][1]);
+}
+static dim3 cell_grid(int nx, int ny, int nz, int ncomp = 1, int shape = 0) {
+    const dim3 b = cell_block(shape);
+    return dim3(ceil_div(nx, b.x), ceil_div(ny, b.y), nz * ncomp);
 }
 
 template <typename T>
@@ -414,10 +420,11 @@ __global__ void __launch_bounds__(256) k_block_weights(const T* u, const T* nl, 
 
 // ---------------------------------------------------------------------------------------------------
 template <typename T>
-static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s) {
+static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s,
+                     int shape) {
     const long long n = (long long)nx * ny * nz;
     const T idx_ = (T)(1.0 / dx);
-    const dim3 grid = cell_grid(nx, ny, nz), block = kCellBlock;
+    const dim3 grid = cell_grid(nx, ny, nz, 1, shape), block = cell_block(shape);
     switch (op) {
         case NSLGF_OP_GRAD: hipLaunchKernelGGL(k_grad<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_DIV: hipLaunchKernelGGL(k_div<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_, 0); break;
@@ -425,7 +432,7 @@ static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int 
         case NSLGF_OP_CURL_BAR: hipLaunchKernelGGL(k_curl_bar<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_NONLINEAR: hipLaunchKernelGGL(k_nonlinear<T>, grid, block, 0, s, (const T*)src, (T*)dst, nx, ny, nz, idx_); break;
         case NSLGF_OP_LAPLACIAN:
-            hipLaunchKernelGGL(k_laplacian<T>, cell_grid(nx, ny, nz, ncomp), block, 0, s, (const T*)src, (T*)dst, nx,
+            hipLaunchKernelGGL(k_laplacian<T>, cell_grid(nx, ny, nz, ncomp, shape), block, 0, s, (const T*)src, (T*)dst, nx,
                                ny, nz, (T)(1.0 / (dx * dx)));
             break;
         default: set_error("stencil_apply: unknown operator"); return NSLGF_EINVAL;
@@ -435,21 +442,20 @@ static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int 
 }
 
 int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx,
-                   hipStream_t s) {
-    if (dtype == NSLGF_F32) return stencil_t<float>(op, src, dst, ncomp, nx, ny, nz, dx, s);
-    return stencil_t<double>(op, src, dst, ncomp, nx, ny, nz, dx, s);
+                   hipStream_t s, int shape) {
+    if (dtype == NSLGF_F32) return stencil_t<float>(op, src, dst, ncomp, nx, ny, nz, dx, s, shape);
+    return stencil_t<double>(op, src, dst, ncomp, nx, ny, nz, dx, s, shape);
 }
 
 int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, const void* w2, void* r,
-                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s) {
-    const long long n = (long long)nx * ny * nz;
+                     const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s, int shape) {
     const int copy_q = c.copy_q;
     const StageCoef cc = c;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_rhs<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)u, (float*)q,
+        hipLaunchKernelGGL(k_stage_rhs<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)u, (float*)q,
                            (const float*)w1, (const float*)w2, (float*)r, (float)(1.0 / dx), cc, copy_q, nx, ny, nz);
     else
-        hipLaunchKernelGGL(k_stage_rhs<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)u, (double*)q,
+        hipLaunchKernelGGL(k_stage_rhs<double>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const double*)u, (double*)q,
                            (const double*)w1, (const double*)w2, (double*)r, 1.0 / dx, cc, copy_q, nx, ny, nz);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -459,10 +465,10 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
                       hipStream_t s) {
     const long long n = (long long)nx * ny * nz;
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_div<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)r, (float*)sdiv, nx,
+        hipLaunchKernelGGL(k_div<float>, cell_grid(nx, ny, nz), cell_block(0), 0, s, (const float*)r, (float*)sdiv, nx,
                            ny, nz, (float)(1.0 / dx), nbuf);
     else
-        hipLaunchKernelGGL(k_div<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)r, (double*)sdiv, nx,
+        hipLaunchKernelGGL(k_div<double>, cell_grid(nx, ny, nz), cell_block(0), 0, s, (const double*)r, (double*)sdiv, nx,
                            ny, nz, 1.0 / dx, nbuf);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -470,14 +476,13 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
 
 int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat, const void* q, const void* w1,
                          const void* w2, double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny,
-                         int nz, double dx, hipStream_t s) {
-    const long long n = (long long)nx * ny * nz;
+                         int nz, double dx, hipStream_t s, int shape) {
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_project<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)r,
+        hipLaunchKernelGGL(k_stage_project<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)r,
                            (float*)rout, (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
                            (float*)wnew, inv, nx, ny, nz, (float)(1.0 / dx));
     else
-        hipLaunchKernelGGL(k_stage_project<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)r,
+        hipLaunchKernelGGL(k_stage_project<double>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const double*)r,
                            (double*)rout, (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
                            c_w2, (double*)wnew, inv, nx, ny, nz, 1.0 / dx);
     NSLGF_LAUNCH_CHECK();
@@ -497,12 +502,12 @@ int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, d
 }
 
 int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsigned char* blocks, int nb, int nx, int ny,
-                       int nz, double dx, hipStream_t s) {
+                       int nz, double dx, hipStream_t s, int shape) {
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_curl<float>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const float*)f, (float*)e, nx, ny,
+        hipLaunchKernelGGL(k_curl<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)f, (float*)e, nx, ny,
                            nz, (float)(1.0 / dx), nbuf, blocks, nb);
     else
-        hipLaunchKernelGGL(k_curl<double>, cell_grid(nx, ny, nz), kCellBlock, 0, s, (const double*)f, (double*)e, nx,
+        hipLaunchKernelGGL(k_curl<double>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const double*)f, (double*)e, nx,
                            ny, nz, 1.0 / dx, nbuf, blocks, nb);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
