@@ -15,6 +15,8 @@ Followed passages:
   stays within eps (capped at q_cap; 0 when one step already exceeds it).
 * Refresh (Sec. 4.4): after q_max steps the velocity on the box is recomputed from the vorticity on
   the support domain with Vor2Vel: w = M_supp C u, u = Cbar a, a = -L^{-1} w.
+* Active box (Sec. 4.2, 4.3, and the grid update of Sec. 5): steps computed on the bounding box of the
+  expanded solution domain, which follows the flow (run_active).
 """
 from __future__ import annotations
 
@@ -126,3 +128,84 @@ def run_adaptive(u: np.ndarray, nsteps: int, dt: float, dx: float, re: float, sc
         prev = (supp, soln)
         u, d = ifherk.step(u, dt, dx, re, scheme, soln_mask=cn, supp_mask=cs)
     return u, d, reinit, Ws, edge
+
+
+def run_active(u: np.ndarray, nsteps: int, dt: float, dx: float, re: float, scheme: str, n_buf: int, nb: int,
+               eps_supp: float, eps_soln: float, n_xb: int):
+    """nsteps IF-HERK steps computed on an active box that follows the flow (Sec. 4.2, 4.3 and the grid
+    update of Sec. 5).  The grid G of u is tiled by blocks of nb^3 cells (its sizes must be multiples of
+    nb).  At the beginning of every step, on the current box B (a box of whole blocks; at first G):
+      * the block weights of u_B (values closer than n_buf to a face of B left out) give D_supp = {W >
+        eps_supp} and D_soln = {W > eps_soln} united with D_supp (the domains are nested, D_supp in
+        D_soln), in the block coordinates of G;
+      * D_xsoln = every block of G at most n_xb blocks from D_soln (along each axis), and the new box B'
+        is the bounding box of D_xsoln: the blocks of B' outside D_xsoln are computed too;
+      * first step: u is restricted to B' (the classification only sets the domain); later, when D_supp
+        or D_soln changed, u is re-initialised on B' from the vorticity on the new support, copied from
+        B (Sec. 5, grid update and velocity refresh): u_B' = Vor2Vel(transfer(M_supp C u_B));
+      * the step runs on B' with the pressure source on D_supp and the nonlinear term on D_soln.
+    Returns (u on G, d on G, both zero outside the final box, number of re-initialisations, number of
+    box changes after the first step, [box per step as (lo, hi) block corners, z y x order])."""
+    from . import blocks
+
+    G = u.shape[1:]
+    if any(s % nb for s in G):
+        raise ValueError("the grid sizes must be multiples of the block size")
+    gb = tuple(s // nb for s in G)
+    lo, hi = (0, 0, 0), gb
+    ub = u.copy()
+    prev = None
+    reinit = regrid = 0
+    boxes = []
+
+    def transfer(f, lo0, hi0, lo1, hi1):
+        """f on box (lo0, hi0) -> box (lo1, hi1), zero where the new box leaves the old one."""
+        out = np.zeros((f.shape[0],) + tuple((h - l) * nb for l, h in zip(lo1, hi1)))
+        a = [max(l0, l1) for l0, l1 in zip(lo0, lo1)]
+        b = [min(h0, h1) for h0, h1 in zip(hi0, hi1)]
+        if all(x < y for x, y in zip(a, b)):
+            src = tuple(slice((x - l0) * nb, (y - l0) * nb) for x, y, l0 in zip(a, b, lo0))
+            dst = tuple(slice((x - l1) * nb, (y - l1) * nb) for x, y, l1 in zip(a, b, lo1))
+            out[(slice(None),) + dst] = f[(slice(None),) + src]
+        return out
+
+    def box_of(mask):
+        idx = np.argwhere(mask)
+        return tuple(int(v) for v in idx.min(axis=0)), tuple(int(v) + 1 for v in idx.max(axis=0))
+
+    d = None
+    for _ in range(nsteps):
+        mu, nu = blocks.weights(ub, dx, nb, n_buf)
+        _, supp, soln, _ = blocks.classify(mu, nu, eps_supp, eps_soln, 0)
+        soln = np.maximum(soln, supp)
+        gs = np.zeros(gb, dtype=np.uint8)
+        gn = np.zeros(gb, dtype=np.uint8)
+        box = tuple(slice(l, h) for l, h in zip(lo, hi))
+        gs[box] = supp
+        gn[box] = soln
+        gx = np.zeros_like(gn)
+        for k, j, i in zip(*np.nonzero(gn)):
+            gx[max(0, k - n_xb):k + n_xb + 1, max(0, j - n_xb):j + n_xb + 1, max(0, i - n_xb):i + n_xb + 1] = 1
+        nlo, nhi = box_of(gx)
+        if prev is None:
+            ub = transfer(ub, lo, hi, nlo, nhi)
+        elif not (np.array_equal(prev[0], gs) and np.array_equal(prev[1], gn)):
+            w = blocks.cell_mask(gs[box], nb, ub.shape[1:]) * stencils.curl(ub, dx)
+            ub = ifherk.vor2vel(transfer(w, lo, hi, nlo, nhi), dx)
+            reinit += 1
+            regrid += int((nlo, nhi) != (lo, hi))
+        lo, hi = nlo, nhi
+        prev = (gs, gn)
+        boxes.append((lo, hi))
+        box = tuple(slice(l, h) for l, h in zip(lo, hi))
+        shape = ub.shape[1:]
+        ub, db = ifherk.step(ub, dt, dx, re, scheme, soln_mask=blocks.cell_mask(gn[box], nb, shape),
+                             supp_mask=blocks.cell_mask(gs[box], nb, shape))
+        d = db
+    uf = np.zeros_like(u)
+    df = np.zeros(G)
+    cells = tuple(slice(l * nb, h * nb) for l, h in zip(lo, hi))
+    uf[(slice(None),) + cells] = ub
+    if d is not None:
+        df[cells] = d
+    return uf, df, reinit, regrid, boxes

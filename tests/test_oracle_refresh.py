@@ -193,3 +193,46 @@ def test_run_adaptive_reinitialises_from_the_new_support_when_the_domain_changes
     v2, d2 = ifherk.step(new, dt, dx, re, "A", soln_mask=cm[1][1], supp_mask=cm[1][0])
     u2, dd2, nre2, _, _ = refresh.run_adaptive(u0, 2, dt, dx, re, "A", n_buf, nb, es, eo, 0)
     assert nre2 == 1 and np.array_equal(u2, v2) and np.array_equal(dd2, d2)
+
+
+def test_run_active_on_the_whole_grid_is_the_adaptive_run():
+    """With an expansion of as many blocks as the grid holds, D_xsoln's bounding box is the whole grid at
+    every step, and with eps_soln <= eps_supp (so that D_supp lies in D_soln) the active-box run is the
+    adaptive run of the same domains, bit for bit."""
+    u0, dx = _compact_velocity(n=16, lo=6, hi=10)
+    dt, re, nb, n_buf = 0.2, 100.0, 4, 1
+    ua, da, nra, nrg, boxes = refresh.run_active(u0, 3, dt, dx, re, "A", n_buf, nb, 1e-3, 1e-4, 4)
+    ub, db, nrb, _, _ = refresh.run_adaptive(u0, 3, dt, dx, re, "A", n_buf, nb, 1e-3, 1e-4, 4)
+    assert nrg == 0 and all(b == ((0, 0, 0), (4, 4, 4)) for b in boxes)
+    assert nra == nrb and np.array_equal(ua, ub) and np.array_equal(da, db)
+
+
+def _blob_at(n, corner, width, dx, seed):
+    rng = np.random.default_rng(seed)
+    a = np.zeros((3, n, n, n))
+    sl = tuple(slice(c, c + width) for c in corner)
+    a[(slice(None),) + sl] = rng.standard_normal((3, width, width, width))
+    u = stencils.curl_bar(a, dx)
+    return u * (0.5 / np.abs(u).max())
+
+
+def test_run_active_box_follows_the_flow_and_is_translation_covariant():
+    """A compact vortex blob far from the grid faces: the box shrinks to the blob's expanded domain at the
+    first step and grows as the integrating factor spreads the vorticity (re-initialisations with box
+    changes); the same blob one block further along every axis gives the same fields one block further
+    (the LGF solution and the block logic are translation invariant), and the fields vanish outside the
+    final box."""
+    n, nb, dx, dt, re, n_buf = 40, 4, 0.3, 0.2, 100.0, 1
+    args = (3, dt, dx, re, "A", n_buf, nb, 1e-8, 1e-8, 1)
+    ua, da, nra, nga, ba = refresh.run_active(_blob_at(n, (16, 16, 16), 3, dx, 4), *args)
+    ub, db, nrb, ngb, bb = refresh.run_active(_blob_at(n, (20, 20, 20), 3, dx, 4), *args)
+    assert nra == nrb >= 1 and nga == ngb >= 1
+    assert ba[0] != ((0, 0, 0), (10, 10, 10))  # the first step already works on a smaller box
+    vol = [np.prod([h - l for l, h in zip(*b)]) for b in ba]
+    assert vol[-1] > vol[0]  # the box grew with the support
+    assert [tuple(tuple(v + 1 for v in c) for c in b) for b in ba] == bb
+    assert np.array_equal(ub[:, 4:, 4:, 4:], ua[:, :-4, :-4, :-4]) and np.array_equal(db[4:, 4:, 4:], da[:-4, :-4, :-4])
+    lo, hi = ba[-1]
+    inside = np.zeros((n, n, n), dtype=bool)
+    inside[lo[0] * nb:hi[0] * nb, lo[1] * nb:hi[1] * nb, lo[2] * nb:hi[2] * nb] = True
+    assert not ua[:, ~inside].any() and not da[~inside].any() and np.abs(ua[:, inside]).max() > 0
