@@ -315,6 +315,27 @@ int herk_run_adaptive(nslgf_t h, nslgf_state *st, int nsteps, int block, double 
                       int *reinits, int *edge_steps, void *stream);
 
 /*
+ * nsteps IF-HERK steps computed on an active box that follows the flow (Sec. 4.2 and 4.3 with the grid
+ * update of Sec. 5).  st describes the whole grid G: u [3][nz][ny][nx] and d [nz][ny][nx] on G, whose
+ * sizes must be multiples of block (st->work is not used: the box state lives in handle memory).  At the
+ * beginning of every step, on the current box B of whole blocks (at first G):
+ *   D_supp = {W > eps_supp}, D_soln = {W > eps_soln} united with D_supp (the domains are nested), from
+ *   the block weights of u on B (block_weights with blocks of block^3 cells, leaving out the points
+ *   closer than st->n_buf to a face of B); D_xsoln = every block of G at most n_xb blocks away from
+ *   D_soln along each axis; the new box B' = the bounding box of D_xsoln (its blocks outside D_xsoln
+ *   are computed too).  The first classification restricts u to B'; later, when D_supp or D_soln
+ *   changed, u on B' is re-initialised from the vorticity on the new support, taken on B and copied to
+ *   B' (u = Cbar a, a = -L^{-1} M_supp C u, Eq. vel_refresh).  The step runs on B' with the pressure
+ *   source on D_supp and the nonlinear term on D_soln.
+ * On return u and d on G hold the last box's values and zero elsewhere; st->t is advanced;
+ * *reinits = re-initialisations, *regrids = box changes after the first step (both may be null);
+ * box[0..5] (may be null) = the last box's first cell (x, y, z) and sizes (x, y, z).  Synchronises
+ * `stream` every step.  The box state and its plans stay cached in the handle.
+ */
+int herk_run_active(nslgf_t h, nslgf_state *st, int nsteps, int block, double eps_supp, double eps_soln, int n_xb,
+                    int *reinits, int *regrids, int *box, void *stream);
+
+/*
  * Staggered-grid point operators of Appendix A on the box (inputs zero outside, outputs on the box):
  *   op NSLGF_OP_GRAD      G:     cells  -> faces   (src [nz][ny][nx], dst [3][...])
  *   op NSLGF_OP_DIV       Dbar:  faces  -> cells   (src [3][...],     dst [nz][ny][nx])

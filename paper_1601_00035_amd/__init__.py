@@ -87,6 +87,8 @@ def lib():
                     "herk_run_adaptive": [vp, ctypes.POINTER(_State), i, i, d, d, i, ctypes.POINTER(i),
                                           ctypes.POINTER(i), vp],
                     "classify_blocks": [vp, vp, i, i, i, d, d, i, vp, vp, vp, vp],
+                    "herk_run_active": [vp, ctypes.POINTER(_State), i, i, d, d, i, ctypes.POINTER(i),
+                                        ctypes.POINTER(i), ctypes.POINTER(i), vp],
                     "nslgf_set_tuning": [vp, i],
                     "nslgf_tuning_info": [vp, i, i, i, i, vp, ctypes.POINTER(i)],
                     "nslgf_tuning_save": [vp, ctypes.c_char_p],
@@ -490,6 +492,17 @@ class HerkState:
                                                             int(n_xb), ctypes.byref(nre), ctypes.byref(nedge),
                                                             _stream(self.u)))
         return nre.value, nedge.value
+
+    def run_active(self, nsteps: int, block: int, eps_supp: float, eps_soln: float, n_xb: int = 1):
+        """nsteps steps on an active box (the bounding box of the expanded solution domain) that follows
+        the flow; u and d keep the box's values and zero elsewhere.  Returns (re-initialisations, box
+        changes, box first cell (x, y, z) and sizes (x, y, z))."""
+        nre, nrg = ctypes.c_int(), ctypes.c_int()
+        box = (ctypes.c_int * 6)()
+        _check("herk_run_active", lib().herk_run_active(handle(self.u.device.index), ctypes.byref(self.c), int(nsteps),
+                                                        int(block), float(eps_supp), float(eps_soln), int(n_xb),
+                                                        ctypes.byref(nre), ctypes.byref(nrg), box, _stream(self.u)))
+        return nre.value, nrg.value, tuple(box[:3]), tuple(box[3:])
 
     def run(self, nsteps: int, eps: float, q_cap: int = 10000) -> int:
         """nsteps steps with a velocity refresh after every q_max steps (q_max from eps); returns the

@@ -144,6 +144,7 @@ struct nslgf_ctx {
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<nslgf::ConvPlan>> plans;
     std::map<std::pair<int, int>, std::unique_ptr<nslgf::DevBuf>> twiddles;  // (L, dtype)
     nslgf::DevBuf if_tmp1, if_tmp2, tmp3, tmp3b, partial, blockmask;
+    nslgf::DevBuf act_u[2], act_d, act_w, act_work, act_mask;  // the active-box driver's box state
 };
 
 namespace nslgf {
@@ -1481,6 +1482,194 @@ int herk_run_adaptive(nslgf_t h, nslgf_state* st, int nsteps, int block, double 
     }
     if (reinits) *reinits = nre;
     if (edge_steps) *edge_steps = nedge;
+    return NSLGF_OK;
+}
+
+int herk_run_active(nslgf_t h, nslgf_state* st, int nsteps, int block, double eps_supp, double eps_soln, int n_xb,
+                    int* reinits, int* regrids, int* box, void* stream) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(st != nullptr, "herk_run_active: null state");
+    NSLGF_TRY(check_box(st->nx, st->ny, st->nz));
+    NSLGF_TRY(check_dtype(st->dtype));
+    NSLGF_CHECK_ARG(st->u && st->d, "herk_run_active: null u or d");
+    NSLGF_CHECK_ARG(nsteps >= 0, "herk_run_active: nsteps must be >= 0");
+    NSLGF_CHECK_ARG(block >= 1 && block <= 256, "herk_run_active: block must be 1..256");
+    NSLGF_CHECK_ARG(st->nx % block == 0 && st->ny % block == 0 && st->nz % block == 0,
+                    "herk_run_active: the grid sizes must be multiples of the block size");
+    NSLGF_CHECK_ARG(std::isfinite(eps_supp) && std::isfinite(eps_soln) && eps_supp >= 0 && eps_soln >= 0,
+                    "herk_run_active: thresholds must be finite and >= 0");
+    NSLGF_CHECK_ARG(n_xb >= 0, "herk_run_active: n_xb must be >= 0");
+    NSLGF_CHECK_ARG(std::isfinite(st->dt) && st->dt > 0 && std::isfinite(st->dx) && st->dx > 0 &&
+                        std::isfinite(st->re) && st->re > 0 && st->n_buf >= 0,
+                    "herk_run_active: dt, dx and re must be > 0 and n_buf >= 0");
+    NSLGF_CHECK_ARG(st->scheme >= NSLGF_SCHEME_A && st->scheme <= NSLGF_SCHEME_C, "herk_run_active: unknown scheme");
+    hipStream_t s = (hipStream_t)stream;
+    const int dt_ = st->dtype;
+    const size_t es = dtype_size(dt_);
+    // block grid of the whole grid G, (x, y, z) order; the box is [lo, hi) in blocks
+    const int gb[3] = {st->nx / block, st->ny / block, st->nz / block};
+    const long long gnb = (long long)gb[0] * gb[1] * gb[2];
+    int lo[3] = {0, 0, 0}, hi[3] = {gb[0], gb[1], gb[2]};
+    auto cells = [&](const int* l, const int* u, int* n) {
+        for (int a = 0; a < 3; ++a) n[a] = (u[a] - l[a]) * block;
+    };
+    int bn[3];
+    cells(lo, hi, bn);
+    int cur = 0;
+    NSLGF_TRY(h->act_u[cur].ensure((size_t)3 * bn[0] * bn[1] * bn[2] * es));
+    NSLGF_HIP_CHECK(hipMemcpyAsync(h->act_u[cur].p, st->u, (size_t)3 * bn[0] * bn[1] * bn[2] * es,
+                                   hipMemcpyDeviceToDevice, s));
+    std::vector<unsigned char> gs(gnb), gn(gnb), gx(gnb), ps, pn;
+    int nre = 0, nrg = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        const long long M = (long long)bn[0] * bn[1] * bn[2];
+        const int bb[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        const long long nbk = (long long)bb[0] * bb[1] * bb[2];
+        // classification on the current box (block weights of its velocity, Sec. 4.3)
+        NSLGF_TRY(h->tmp3.ensure((size_t)3 * M * es));
+        NSLGF_TRY(h->partial.ensure((size_t)2 * nbk * sizeof(double)));
+        double* dmu = (double*)h->partial.p;
+        void* U = h->act_u[cur].p;
+        NSLGF_PROF(h, "nonlinear", s, launch_stencil(NSLGF_OP_NONLINEAR, dt_, U, h->tmp3.p, 3, bn[0], bn[1], bn[2], st->dx, s));
+        NSLGF_PROF(h, "block_weights", s, launch_block_weights(dt_, U, h->tmp3.p, bn[0], bn[1], bn[2], block, st->n_buf,
+                                                               st->dx, dmu, dmu + nbk, s));
+        std::vector<double> mu(nbk), nu(nbk);
+        NSLGF_HIP_CHECK(hipMemcpyAsync(mu.data(), dmu, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        NSLGF_HIP_CHECK(hipMemcpyAsync(nu.data(), dmu + nbk, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        NSLGF_HIP_CHECK(hipStreamSynchronize(s));
+        std::vector<unsigned char> supp(nbk), soln(nbk), xs(nbk);
+        classify_blocks_host(mu.data(), nu.data(), bb[0], bb[1], bb[2], eps_supp, eps_soln, 0, nullptr, supp.data(),
+                             soln.data(), xs.data());
+        // D_supp, D_soln (united with D_supp) in the block coordinates of G, then D_xsoln and its bounding box
+        std::fill(gs.begin(), gs.end(), 0);
+        std::fill(gn.begin(), gn.end(), 0);
+        std::fill(gx.begin(), gx.end(), 0);
+        auto gidx = [&](int i, int j, int k) { return ((long long)k * gb[1] + j) * gb[0] + i; };
+        for (int k = 0; k < bb[2]; ++k)
+            for (int j = 0; j < bb[1]; ++j)
+                for (int i = 0; i < bb[0]; ++i) {
+                    const long long b = ((long long)k * bb[1] + j) * bb[0] + i;
+                    gs[gidx(lo[0] + i, lo[1] + j, lo[2] + k)] = supp[b];
+                    gn[gidx(lo[0] + i, lo[1] + j, lo[2] + k)] = (soln[b] || supp[b]) ? 1 : 0;
+                }
+        int nlo[3] = {gb[0], gb[1], gb[2]}, nhi[3] = {0, 0, 0};
+        for (int k = 0; k < gb[2]; ++k)
+            for (int j = 0; j < gb[1]; ++j)
+                for (int i = 0; i < gb[0]; ++i) {
+                    if (!gn[gidx(i, j, k)]) continue;
+                    const int c[3] = {i, j, k};
+                    for (int a = 0; a < 3; ++a) {
+                        nlo[a] = std::min(nlo[a], std::max(0, c[a] - n_xb));
+                        nhi[a] = std::max(nhi[a], std::min(gb[a], c[a] + n_xb + 1));
+                    }
+                }
+        if (nhi[0] <= nlo[0]) {  // no solution block at all (a vanishing flow): keep the box
+            for (int a = 0; a < 3; ++a) {
+                nlo[a] = lo[a];
+                nhi[a] = hi[a];
+            }
+        }
+        const bool first = ps.empty();
+        const bool changed = !first && (ps != gs || pn != gn);
+        const bool moved = nlo[0] != lo[0] || nlo[1] != lo[1] || nlo[2] != lo[2] || nhi[0] != hi[0] ||
+                           nhi[1] != hi[1] || nhi[2] != hi[2];
+        int nn[3];
+        cells(nlo, nhi, nn);
+        const long long Mn = (long long)nn[0] * nn[1] * nn[2];
+        // the overlap of the old and the new box, in the cell offsets of each
+        int soff[3], doff[3], ext[3];
+        for (int a = 0; a < 3; ++a) {
+            const int l = std::max(lo[a], nlo[a]), u = std::min(hi[a], nhi[a]);
+            soff[a] = (l - lo[a]) * block;
+            doff[a] = (l - nlo[a]) * block;
+            ext[a] = std::max(0, u - l) * block;
+        }
+        const int nxt = 1 - cur;
+        if (first && moved) {
+            // the first classification only sets the domain: u restricted to the new box
+            NSLGF_TRY(h->act_u[nxt].ensure((size_t)3 * Mn * es));
+            NSLGF_TRY(launch_zero(dt_, h->act_u[nxt].p, 3 * Mn, s));
+            NSLGF_TRY(launch_copy_box(dt_, U, bn, soff, h->act_u[nxt].p, nn, doff, ext, 3, s));
+            cur = nxt;
+        } else if (changed) {
+            // grid update and re-initialisation: the vorticity on the new support, taken on the old box,
+            // moves to the new box, where Vor2Vel gives the velocity (Sec. 5; Eq. vel_refresh)
+            std::vector<unsigned char> osupp(nbk);
+            for (int k = 0; k < bb[2]; ++k)
+                for (int j = 0; j < bb[1]; ++j)
+                    for (int i = 0; i < bb[0]; ++i)
+                        osupp[((long long)k * bb[1] + j) * bb[0] + i] = gs[gidx(lo[0] + i, lo[1] + j, lo[2] + k)];
+            NSLGF_TRY(h->act_mask.ensure((size_t)nbk));
+            NSLGF_HIP_CHECK(hipMemcpyAsync(h->act_mask.p, osupp.data(), nbk, hipMemcpyHostToDevice, s));
+            NSLGF_TRY(h->tmp3b.ensure((size_t)3 * M * es));
+            NSLGF_PROF(h, "curl_masked", s, launch_masked_curl(dt_, U, h->tmp3b.p, 0, (const unsigned char*)h->act_mask.p,
+                                                               block, bn[0], bn[1], bn[2], st->dx, s));
+            NSLGF_TRY(h->act_w.ensure((size_t)3 * Mn * es));
+            NSLGF_TRY(launch_zero(dt_, h->act_w.p, 3 * Mn, s));
+            NSLGF_TRY(launch_copy_box(dt_, h->tmp3b.p, bn, soff, h->act_w.p, nn, doff, ext, 3, s));
+            NSLGF_TRY(h->act_u[nxt].ensure((size_t)3 * Mn * es));
+            NSLGF_TRY(vor2vel(h, h->act_w.p, h->act_u[nxt].p, nn[0], nn[1], nn[2], st->dx, dt_, stream));
+            NSLGF_HIP_CHECK(hipStreamSynchronize(s));  // the host mask above is reused
+            cur = nxt;
+            ++nre;
+            nrg += moved ? 1 : 0;
+        }
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = nlo[a];
+            hi[a] = nhi[a];
+            bn[a] = nn[a];
+        }
+        ps = gs;
+        pn = gn;
+        // the step on the box, with D_supp and D_soln in the box's block coordinates
+        const int b2[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+        const long long nb2 = (long long)b2[0] * b2[1] * b2[2];
+        std::vector<unsigned char> m2(2 * nb2);
+        for (int k = 0; k < b2[2]; ++k)
+            for (int j = 0; j < b2[1]; ++j)
+                for (int i = 0; i < b2[0]; ++i) {
+                    const long long b = ((long long)k * b2[1] + j) * b2[0] + i;
+                    m2[b] = gs[gidx(lo[0] + i, lo[1] + j, lo[2] + k)];
+                    m2[nb2 + b] = gn[gidx(lo[0] + i, lo[1] + j, lo[2] + k)];
+                }
+        NSLGF_TRY(h->blockmask.ensure((size_t)2 * nb2));
+        NSLGF_HIP_CHECK(hipMemcpyAsync(h->blockmask.p, m2.data(), 2 * nb2, hipMemcpyHostToDevice, s));
+        NSLGF_TRY(h->act_d.ensure((size_t)Mn * es));
+        NSLGF_TRY(h->act_work.ensure(nslgf_state_bytes(bn[0], bn[1], bn[2], dt_)));
+        nslgf_state bs = *st;
+        bs.nx = bn[0];
+        bs.ny = bn[1];
+        bs.nz = bn[2];
+        bs.u = h->act_u[cur].p;
+        bs.d = h->act_d.p;
+        bs.work = h->act_work.p;
+        bs.supp_blocks = (const unsigned char*)h->blockmask.p;
+        bs.soln_blocks = (const unsigned char*)h->blockmask.p + nb2;
+        bs.block = block;
+        bs.stage_done = 0;
+        const int rc = herk_step(h, &bs, stream);
+        st->t = bs.t;
+        st->div_max = bs.div_max;
+        NSLGF_HIP_CHECK(hipStreamSynchronize(s));  // the host masks are reused by the next step
+        NSLGF_TRY(rc);
+    }
+    // the fields on G: the box's values, zero elsewhere
+    const long long MG = (long long)st->nx * st->ny * st->nz;
+    const int gd[3] = {st->nx, st->ny, st->nz}, zero[3] = {0, 0, 0};
+    const int off[3] = {lo[0] * block, lo[1] * block, lo[2] * block};
+    if (nsteps > 0) {
+        NSLGF_TRY(launch_zero(dt_, st->u, 3 * MG, s));
+        NSLGF_TRY(launch_copy_box(dt_, h->act_u[cur].p, bn, zero, st->u, gd, off, bn, 3, s));
+        NSLGF_TRY(launch_zero(dt_, st->d, MG, s));
+        NSLGF_TRY(launch_copy_box(dt_, h->act_d.p, bn, zero, st->d, gd, off, bn, 1, s));
+    }
+    if (reinits) *reinits = nre;
+    if (regrids) *regrids = nrg;
+    if (box)
+        for (int a = 0; a < 3; ++a) {
+            box[a] = off[a];
+            box[3 + a] = bn[a];
+        }
     return NSLGF_OK;
 }
 

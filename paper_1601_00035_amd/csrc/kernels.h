@@ -195,6 +195,11 @@ int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int n
 int launch_guard_reset(unsigned long long* acc, hipStream_t s);
 int launch_guard(int dtype, const void* u, const void* d, int nx, int ny, int nz, int margin, double dx,
                  unsigned long long* acc, hipStream_t s);
+// active-box transfers (active.hip): dst = 0 over n elements; and the sub-box copy of ncomp components
+// from the box sdim (x, y, z sizes) at offset soff to the box ddim at offset doff, extent ext (x, y, z)
+int launch_zero(int dtype, void* dst, long long n, hipStream_t s);
+int launch_copy_box(int dtype, const void* src, const int sdim[3], const int soff[3], void* dst, const int ddim[3],
+                    const int doff[3], const int ext[3], int ncomp, hipStream_t s);
 // max over cells of the cell-centred speed
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s);
