@@ -234,7 +234,7 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done (dt = {dt:.4e})")
 
-    nslgf.profile_enable(True)
+    # headline: K steps with no per-kernel events, bracketed by synchronisation
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
@@ -244,11 +244,17 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
-    prof = nslgf.profile_read()
-    nslgf.profile_enable(False)
     ms = ev0.elapsed_time(ev1) / args.steps
     assert torch.isfinite(u).all().item(), "non-finite velocity"
     log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {wall:.2f} s)")
+    # per-kernel durations: the same K steps again with HIP events around every launch, recorded on the
+    # stream each kernel is launched on (the library's profiler)
+    nslgf.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    prof = nslgf.profile_read()
+    nslgf.profile_enable(False)
 
     N, P = n, 512
     lgf_pts = 6 * N ** 3
@@ -326,6 +332,14 @@ def main():
         diff = (s32.u.double() - s64.u)
         step_err = {"rel_l2_vs_fp64": float(diff.norm() / s64.u.norm()),
                     "rel_linf_vs_fp64": float(diff.abs().max() / s64.u.abs().max())}
+        # the projection's divergence check, in FP64 for both forms (guarded steps from the same start)
+        div = {}
+        for name, dtp in (("fp64", torch.float64), ("fp32", torch.float32)):
+            sg = nslgf.HerkState(u0.to(dtp).clone(), dx, dt, re, "A", n_buf=16, guard=True)
+            sg.step()
+            div[name] = sg.div_max * dx / float(u0.abs().max())
+        step_err["fp64_divergence_check"] = {"max_abs_Dbar_u_times_dx_over_umax": div,
+                                             "cells": "at least n_buf + r_i + 1 from every face, every stage"}
 
         def step32():
             nslgf.vor2vel(w32, dx, out=s32.u)
@@ -424,6 +438,66 @@ def main():
                                                          "edge_steps": nedge,
                                                          "plain_step_ms": round(ms_plain, 4)}}
         del ua, sa, sp
+        torch.cuda.empty_cache()
+        # steps on an active box that follows the flow (the bounding box of the expanded solution domain,
+        # Sec. 4.2, 4.3 and the grid update of Sec. 5), 20 steps in one call, against 20 plain steps:
+        # time per step (block weights and their host round trip included) and the difference on the
+        # box less its outer block layer
+        nact = 20
+        uref = u.clone()
+        sref = nslgf.HerkState(uref, dx, dt, re, "A", n_buf=16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nact):
+            sref.step()
+        torch.cuda.synchronize()
+        ms_ref = (time.perf_counter() - t0) / nact * 1e3
+        active = {"block": 16, "n_xb": 1, "steps": nact, "plain_step_ms": round(ms_ref, 4), "by_eps": {}}
+        for es, eo in ((1e-8, 1e-3), (1e-6, 1e-3), (1e-4, 1e-3)):
+            for rep in range(2):  # the first run builds the plans of the boxes it meets
+                ub = u.clone()
+                sb = nslgf.HerkState(ub, dx, dt, re, "A", n_buf=16)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nre, nrg, org, size = sb.run_active(nact, 16, es, eo, 1)
+                torch.cuda.synchronize()
+                ms_b = (time.perf_counter() - t0) / nact * 1e3
+            inner = (slice(None),) + tuple(slice(o + 16, o + n_ - 16) for o, n_ in zip(reversed(org), reversed(size)))
+            err = float((ub - uref)[inner].abs().max() / uref.abs().max())
+            active["by_eps"][f"{es:g}"] = {"eps_soln": eo, "ms_per_step": round(ms_b, 4),
+                                           "speedup_vs_plain": round(ms_ref / ms_b, 3), "reinits": nre,
+                                           "box_changes": nrg, "box_first_cell_xyz": list(org),
+                                           "box_size_xyz": list(size),
+                                           "box_fraction_of_grid": round(size[0] * size[1] * size[2] / N ** 3, 4),
+                                           "rel_diff_vs_plain_on_box_less_one_block": err}
+            del ub, sb
+        secondary["active_box"] = active
+        del uref, sref
+        torch.cuda.empty_cache()
+        # launch tuner: the 256^3 FP64 step with the choices timed on the device against the defaults
+        ut = u.clone()
+        st_t = nslgf.HerkState(ut, dx, dt, re, "A", n_buf=16)
+
+        def time_steps(k=10):
+            st_t.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(k):
+                st_t.step()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / k * 1e3
+
+        ms_default = time_steps()
+        default_cfg = nslgf.tuning_info(N, N, N)
+        nslgf.set_tuning(nslgf.TUNE_AUTO)
+        nslgf.lgf_table(N, N, N, torch.float64)  # rebuilt with the column plans timed
+        tuned_cfg = nslgf.tuning_info(N, N, N)
+        ms_tuned = time_steps()
+        nslgf.set_tuning(nslgf.TUNE_DEFAULT)
+        secondary["tuning"] = {"default": {**default_cfg, "step_ms": round(ms_default, 4)},
+                               "tuned": {**tuned_cfg, "step_ms": round(ms_tuned, 4)},
+                               "cell_shapes": nslgf.CELL_SHAPES}
+        del ut, st_t
         torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
