@@ -8,8 +8,10 @@
 //   A (32 x 16): lane l supplies A[l % 32][8 (l / 32) + j], j < 8
 //   B (16 x 32): lane l supplies B[8 (l / 32) + j][l % 32]
 //   D (32 x 32): lane l holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32] in accumulator i < 16
-// The weight gradient reduces over voxels in fixed chunks followed by a fixed-order sum, so every
-// result is deterministic.
+// The weight gradient, whose reduction index is the voxel, first copies dY and X into a blocked layout
+// ([voxel / 8][channel][8]: a lane's 8 voxels of one channel are one 16-byte load) and gives each wave
+// the three taps of one (dz, dy) pair, which share their row loads.  It reduces over voxels in fixed
+// chunks followed by a fixed-order two-level sum, so every result is deterministic.
 #include <cmath>
 
 #include "../../include/nslgf_surrogate.h"
@@ -65,6 +67,8 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const bf16_t* __restrict__ X,
     f32x16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+    // (loading the operands several steps ahead measured slower: the gathered A rows, not load latency,
+    // limit this kernel)
     for (int tap = 0; tap < 27; ++tap) {
         const int zz = z + SIGN * tap_dz(tap), yy = y + SIGN * tap_dy(tap), xx = x + SIGN * tap_dx(tap);
         const bool valid = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
@@ -131,6 +135,139 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ d
         const int row = cot * 32 + 8 * (i / 4) + 4 * half + (i % 4);
         out[(long long)row * cin + ci] = acc[i];
     }
+}
+
+// Channels-last [nvox][C] -> blocked [nvox / 8][C][8] (BF16): within each group of 8 consecutive voxels the
+// channels become the slow index, so that the weight gradient's MFMA operands (whose reduction index is
+// the voxel) read 8 consecutive voxels of one channel as one 16-byte load, and the 32 channels of a
+// half-wave read 512 contiguous bytes.  One thread transposes 8 voxels x 8 channels in registers.
+__global__ void __launch_bounds__(256) k_to_blocked8(const bf16_t* __restrict__ x, bf16_t* __restrict__ y,
+                                                     long long ngroups, int C) {
+    const int cgs = C / 8;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ngroups * cgs) return;
+    const long long g = e / cgs;
+    const int cg = (int)(e % cgs) * 8;
+    uint4 in[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) in[j] = *(const uint4*)(x + (g * 8 + j) * C + cg);
+    const bf16_t* a = (const bf16_t*)in;  // a[j * 8 + c]: voxel j, channel cg + c
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        bf16_t o[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = a[j * 8 + c];
+        *(uint4*)(y + (g * C + cg + c) * 8) = *(const uint4*)o;
+    }
+}
+
+// Partial weight gradient of one voxel chunk for the three taps of one (dz, dy) pair and one (cout, cin)
+// tile pair:
+//     P[chunk][tap][co][ci] = sum_{v in chunk} dY[v][co] X[v + off(tap)][ci],  tap = 3 (3 (dz + 1) + dy + 1) + dx + 1,
+// from blocked copies (dYb [nvox / 8][cout][8], Xb [nvox / 8][cin][8]).  One wave per (chunk, tile pair,
+// (dz, dy)); per 16-voxel slice it loads its A operand (dY, 8 voxels per lane) and the three groups of X
+// around x0 (x0 - 8, x0, x0 + 8) once, and forms the B operands of dx = -1, 0, +1 from them.  Small
+// register footprint (three accumulators), so that many waves per SIMD hide the load latency.  Requires
+// W % 8 == 0 (8-voxel groups stay inside one x row).
+__global__ void __launch_bounds__(256) k_conv_wgrad_cm(const bf16_t* __restrict__ dYb, const bf16_t* __restrict__ Xb,
+                                                       float* __restrict__ P, int D, int H, int W, int cin, int cout,
+                                                       int chunk_len, int nwaves) {
+    const int wid = blockIdx.x * 4 + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (wid >= nwaves) return;
+    const int cotiles = cout / 32, citiles = (cin + 31) / 32;
+    int r = wid;
+    const int g = r % 9;  // (dz, dy) = (g / 3 - 1, g % 3 - 1)
+    r /= 9;
+    const int cit = r % citiles;
+    r /= citiles;
+    const int cot = r % cotiles;
+    const int chunk = r / cotiles;
+    const int dz = g / 3 - 1, dy = g % 3 - 1;
+    const int m = lane % 32, half = lane / 32;
+    const int co = cot * 32 + m, ci = cit * 32 + m;
+    const bool ci_ok = ci < cin;
+    const bf16_t* acol = dYb + (long long)co * 8;
+    const bf16_t* bcol = Xb + (long long)(ci_ok ? ci : 0) * 8;
+    const long long astride = (long long)cout * 8, bstride = (long long)cin * 8;
+    f32x16 acc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+    // the slice's first voxel as (x, y, z), advanced by 16 voxels per slice without divisions
+    const int vstart = chunk * chunk_len, nslices = chunk_len / 16;
+    int xs = vstart % W, ys = (vstart / W) % H, zs = vstart / (W * H);
+    // operands of one slice: A (dY, 8 voxels of this lane's group) and the X groups at x0 - 8, x0, x0 + 8,
+    // loaded one slice ahead of the matrix operations that use them
+    auto load = [&](int sl, bf16x8& a, uint4& p, uint4& q, uint4& n) {
+        int x0 = xs + 8 * half, y = ys, z = zs;
+        if (x0 >= W) {  // (rows of 8 voxels: the second group starts the next row)
+            x0 -= W;
+            if (++y == H) {
+                y = 0;
+                ++z;
+            }
+        }
+        a = load8(acol + (long long)((vstart >> 3) + 2 * sl + half) * astride);
+        p = make_uint4(0, 0, 0, 0);
+        q = p;
+        n = p;
+        const int zz = z + dz, yy = y + dy;
+        if (ci_ok && zz >= 0 && zz < D && yy >= 0 && yy < H) {
+            const bf16_t* blk = bcol + (long long)(((unsigned)((zz * H + yy) * W + x0)) >> 3) * bstride;
+            q = *(const uint4*)blk;
+            if (x0 >= 8) p = *(const uint4*)(blk - bstride);
+            if (x0 + 8 < W) n = *(const uint4*)(blk + bstride);
+        }
+    };
+    bf16x8 a_nx;
+    uint4 p_nx, q_nx, n_nx;
+    load(0, a_nx, p_nx, q_nx, n_nx);
+    for (int sl = 0; sl < nslices; ++sl) {
+        const bf16x8 a = a_nx;
+        const uint4 p = p_nx, q = q_nx, n = n_nx;
+        xs += 16;
+        while (xs >= W) {
+            xs -= W;
+            if (++ys == H) {
+                ys = 0;
+                ++zs;
+            }
+        }
+        if (sl + 1 < nslices) load(sl + 1, a_nx, p_nx, q_nx, n_nx);
+        uint4 bm, bp;  // voxels x0 - 1 .. x0 + 6 and x0 + 1 .. x0 + 8 (zero beyond the row)
+        bm.x = (q.x << 16) | (p.w >> 16);
+        bm.y = (q.y << 16) | (q.x >> 16);
+        bm.z = (q.z << 16) | (q.y >> 16);
+        bm.w = (q.w << 16) | (q.z >> 16);
+        bp.x = (q.x >> 16) | (q.y << 16);
+        bp.y = (q.y >> 16) | (q.z << 16);
+        bp.z = (q.z >> 16) | (q.w << 16);
+        bp.w = (q.w >> 16) | (n.x << 16);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, bm), acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, q), acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, __builtin_bit_cast(bf16x8, bp), acc[2], 0, 0, 0);
+    }
+    if (!ci_ok) return;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        float* out = P + ((long long)chunk * 27 + 3 * g + t) * cout * cin;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = cot * 32 + 8 * (i / 4) + 4 * half + (i % 4);
+            out[(long long)row * cin + ci] = acc[t][i];
+        }
+    }
+}
+
+// First level of the fixed-order chunk reduction: Q[g][i] = sum of the chunks g G .. g G + G - 1.
+__global__ void k_sum_chunk_groups(const float* __restrict__ P, float* __restrict__ Q, long long n, int G) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int g = blockIdx.y;
+    float s = 0.f;
+    for (int c = g * G; c < (g + 1) * G; ++c) s += P[(long long)c * n + i];
+    Q[(long long)g * n + i] = s;
 }
 
 __global__ void k_sum_chunks(const float* __restrict__ P, float* __restrict__ dW, long long n, int nchunks) {
@@ -292,6 +429,19 @@ __global__ void k_mfma_selftest(const bf16_t* A, const bf16_t* B, float* C) {
 
 static int grid1(long long n) { return ceil_div(n, 256); }
 
+// Voxel chunks of the blocked-layout weight gradient: a power of two with chunks of at least 64 voxels
+// (a multiple of 16), enough waves (chunks x tile pairs x 9) to fill the device, at most 4096 chunks.
+static int wgrad_cm_chunks(long long nvox, int cin, int cout) {
+    const long long pairs = (long long)(cout / 32) * ((cin + 31) / 32);
+    int nch = 1;
+    while (nch < 4096 && nch * pairs * 9 < 16384 && nvox % (nch * 2) == 0 && nvox / (nch * 2) >= 64 &&
+           (nvox / (nch * 2)) % 16 == 0)
+        nch *= 2;
+    return nch;
+}
+static bool wgrad_cm_ok(int W, long long nvox) { return W % 8 == 0 && nvox % 16 == 0; }
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 static int wgrad_chunks(long long nvox) {
     // voxel chunks of at least 512 (a multiple of 16), at most 64 chunks
     int nch = 1;
@@ -351,7 +501,14 @@ int sur_conv3d_bwd_data(nslgf_t h, const void* dy, const void* wt, void* dx, int
 
 size_t sur_bwd_weight_work_bytes(int D, int H, int W, int cin, int cout) {
     if (D < 1 || H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
-    return (size_t)wgrad_chunks((long long)D * H * W) * 27 * cin * cout * sizeof(float);
+    const long long nvox = (long long)D * H * W;
+    if (wgrad_cm_ok(W, nvox)) {
+        // chunk partials, the channel-major copies of dY and X, then the group sums of the partials
+        const int nch = wgrad_cm_chunks(nvox, cin, cout);
+        return align256((size_t)nch * 27 * cin * cout * sizeof(float)) + align256((size_t)nvox * cout * 2) +
+               align256((size_t)nvox * cin * 2) + (size_t)(nch / 32 + 1) * 27 * cin * cout * sizeof(float);
+    }
+    return (size_t)wgrad_chunks(nvox) * 27 * cin * cout * sizeof(float);
 }
 
 int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, void* work, int D, int H, int W, int cin,
@@ -360,13 +517,39 @@ int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, vo
     NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
     NSLGF_CHECK_ARG(dy && x && dw && work, "sur_conv3d_bwd_weight: null pointer");
     const long long nvox = (long long)D * H * W;
+    hipStream_t s = (hipStream_t)stream;
+    const long long n = 27LL * cin * cout;
+    if (wgrad_cm_ok(W, nvox)) {
+        const int nch = wgrad_cm_chunks(nvox, cin, cout);
+        const int chunk_len = (int)(nvox / nch);
+        char* base = (char*)work;
+        float* part = (float*)base;
+        bf16_t* dyc = (bf16_t*)(base + align256((size_t)nch * 27 * cin * cout * sizeof(float)));
+        bf16_t* xc = (bf16_t*)((char*)dyc + align256((size_t)nvox * cout * 2));
+        hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (cout / 8), 256)), dim3(256), 0, s,
+                           (const bf16_t*)dy, dyc, nvox / 8, cout);
+        hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (cin / 8), 256)), dim3(256), 0, s,
+                           (const bf16_t*)x, xc, nvox / 8, cin);
+        const long long nwaves = (long long)nch * (cout / 32) * ((cin + 31) / 32) * 9;
+        hipLaunchKernelGGL(k_conv_wgrad_cm, dim3((unsigned)ceil_div(nwaves, 4)), dim3(256), 0, s, (const bf16_t*)dyc,
+                           (const bf16_t*)xc, part, D, H, W, cin, cout, chunk_len, (int)nwaves);
+        if (nch >= 64) {
+            // two levels (groups of 32 chunks, then the groups), each in a fixed order
+            const int G = 32, ng = nch / G;
+            float* q = (float*)((char*)xc + align256((size_t)nvox * cin * 2));
+            hipLaunchKernelGGL(k_sum_chunk_groups, dim3(grid1(n), ng), dim3(256), 0, s, (const float*)part, q, n, G);
+            hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)q, (float*)dw, n, ng);
+        } else {
+            hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)part, (float*)dw, n, nch);
+        }
+        NSLGF_LAUNCH_CHECK();
+        return NSLGF_OK;
+    }
     const int nch = wgrad_chunks(nvox);
     const int chunk_len = (int)(nvox / nch);
     const long long waves = (long long)nch * 27 * (cout / 32) * ((cin + 31) / 32);
-    hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_conv_wgrad, dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)dy, (const bf16_t*)x,
                        (float*)work, D, H, W, cin, cout, chunk_len, nch);
-    const long long n = 27LL * cin * cout;
     hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)work, (float*)dw, n, nch);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;

@@ -35,7 +35,8 @@ def test_mfma_operand_layout():
     assert rel(got, A @ B) < 1e-6
 
 
-@pytest.mark.parametrize("dims,cin,cout", [((8, 8, 8), 32, 64), ((4, 8, 12), 16, 32), ((8, 4, 4), 96, 128)])
+@pytest.mark.parametrize("dims,cin,cout", [((8, 8, 8), 32, 64), ((4, 8, 12), 16, 32), ((8, 4, 4), 96, 128),
+                                           ((4, 6, 16), 16, 32), ((2, 4, 24), 96, 128)])
 def test_conv_layers(dims, cin, cout):
     D, H, W = dims
     x = rand_bf16((D, H, W, cin), 3)
