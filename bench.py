@@ -126,13 +126,14 @@ def cpu_baseline(w, dx, seconds: float):
     }
 
 
-def batched_measure(nslgf, torch, dtype, reps=3):
-    """32 uneven Scheme A steps (n ~ U{48..192}, seeded rings): one captured graph per batch against
-    the same steps issued one state after another on one stream."""
+def batched_measure(nslgf, torch, dtype, reps=3, sizes=None):
+    """32 uneven Scheme A steps (n ~ U{48..192}, seeded rings): the same steps issued one state after
+    another on one stream, against one captured graph per batch in both of its forms (batched passes: one
+    launch per kernel over every group of equal boxes; per problem: each problem on a branch stream)."""
     import workloads
 
     dev = torch.device("cuda:0")
-    specs = workloads.batch_specs(32, seed=0)
+    specs = workloads.batch_specs(32, seed=0, sizes=sizes)
     solo, batch = [], []
     cells = 0
     for (n, dx, ring, re, cfl) in specs:
@@ -149,12 +150,20 @@ def batched_measure(nslgf, torch, dtype, reps=3):
         cells += n ** 3
         del w
     stream = torch.cuda.current_stream()
-    # correctness: one step each way from identical states
-    for st in solo:
-        st.step()
-    nslgf.herk_step_batched(batch)
-    torch.cuda.synchronize()
-    equal = all(torch.equal(a.u, b.u) and torch.equal(a.d, b.d) for a, b in zip(solo, batch))
+    # correctness: one step each way from identical states, per form of the batch graph
+    modes = (("per_problem", nslgf.BATCH_PER_PROBLEM), ("batched_passes", nslgf.BATCH_PASSES))
+    equal, info = {}, {}
+    for name, mode in modes:
+        for a, b in zip(solo, batch):
+            b.u.copy_(a.u)
+            b.c.t = a.c.t
+        nslgf.set_batch_mode(mode)
+        for st in solo:
+            st.step()
+        nslgf.herk_step_batched(batch)
+        torch.cuda.synchronize()
+        equal[name] = all(torch.equal(a.u, b.u) and torch.equal(a.d, b.d) for a, b in zip(solo, batch))
+        info[name] = nslgf.batch_info()
 
     def timed(fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -167,11 +176,21 @@ def batched_measure(nslgf, torch, dtype, reps=3):
         return e0.elapsed_time(e1) / reps
 
     ms_solo = timed(lambda: [st.step() for st in solo])
-    ms_batch = timed(lambda: nslgf.herk_step_batched(batch))
+    ms = {}
+    for name, mode in modes:
+        nslgf.set_batch_mode(mode)
+        nslgf.herk_step_batched(batch)  # (captures the form's graph)
+        ms[name] = timed(lambda: nslgf.herk_step_batched(batch))
+    nslgf.set_batch_mode(nslgf.BATCH_PASSES)
+    best = min(ms, key=ms.get)
     sizes = sorted(set(sp[0] for sp in specs))
     return {"problems": len(specs), "sizes": sizes, "cells": cells, "ms_one_by_one": round(ms_solo, 3),
-            "ms_batched_graph": round(ms_batch, 3), "speedup": round(ms_solo / ms_batch, 3),
-            "Mcells_per_s": round(cells / (ms_batch * 1e-3) / 1e6, 1), "bitwise_equal_to_one_by_one": equal}
+            "ms_graph_per_problem": round(ms["per_problem"], 3),
+            "ms_graph_batched_passes": round(ms["batched_passes"], 3),
+            "batched_passes_groups_launches": list(info["batched_passes"]),
+            "speedup_best_vs_one_by_one": round(ms_solo / ms[best], 3), "best_form": best,
+            "Mcells_per_s": round(cells / (ms[best] * 1e-3) / 1e6, 1),
+            "bitwise_equal_to_one_by_one": equal}
 
 
 def main():
@@ -501,7 +520,8 @@ def main():
         torch.cuda.empty_cache()
         log("batched form: 32 uneven steps, FP64 and FP32 ...")
         secondary["batched"] = {"fp64": batched_measure(nslgf, torch, torch.float64),
-                                "fp32": batched_measure(nslgf, torch, torch.float32)}
+                                "fp32": batched_measure(nslgf, torch, torch.float32),
+                                "ensemble_64cubed_fp64": batched_measure(nslgf, torch, torch.float64, sizes=(64,))}
         torch.cuda.empty_cache()
 
     cpu = None

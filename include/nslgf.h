@@ -198,13 +198,28 @@ int herk_check(nslgf_t h, const nslgf_state *st, int margin, double *div_max, vo
 /*
  * One IF-HERK step of each of n independent states (boxes of any supported sizes and dtypes, each
  * with its own u, d and work; none may share them), as one launch: the first call captures the n
- * steps into a HIP graph with one branch per state (up to 16 concurrent branches) and later calls
- * with the same states and step parameters replay it.  Results equal n herk_step calls bit for bit.
+ * steps into a HIP graph (of batched passes, or of per-problem branches; see nslgf_set_batch_mode) and
+ * later calls with the same states and step parameters replay it.  Results equal n herk_step calls bit
+ * for bit.
  * Advances every st->t by its dt.  Builds missing LGF spectra first (synchronising the stream).
  * Guarded states are checked inside the graph and read back after it (one synchronisation); the call
  * returns NSLGF_ENONFINITE if any of them saw a non-finite value.
  */
 int herk_step_batched(nslgf_t h, nslgf_state *const *sts, int n, void *stream);
+
+/*
+ * Form of the batched graph.  NSLGF_BATCH_PASSES (the default): the states whose steps launch the same
+ * kernels with the same grids (boxes of one size, dtype and scheme whose integrating factors have the
+ * same radii) form a group, and every kernel of the step runs as ONE launch over the whole group, reading
+ * each problem's arguments from a device table; the groups run on concurrent branch streams.  Steps
+ * that use a kernel without a batched form (the step guard, integrating-factor radii above 12) make the
+ * call fall back to NSLGF_BATCH_PER_PROBLEM: each state's kernels on a branch stream of its own.
+ * nslgf_batch_info reports the last captured graph: *groups (0 for the per-problem form) and *launches
+ * (its kernel launches).  Results are identical in both forms.
+ */
+enum nslgf_batch_mode { NSLGF_BATCH_PASSES = 0, NSLGF_BATCH_PER_PROBLEM = 1 };
+int nslgf_set_batch_mode(nslgf_t h, int mode);
+int nslgf_batch_info(nslgf_t h, int *groups, int *launches);
 
 /*
  * Vor2Vel (Sec. 4.1, Eqs. vel_vor and vel_refresh): a = -L^{-1} w per component, u = Cbar a.

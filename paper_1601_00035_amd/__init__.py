@@ -90,6 +90,8 @@ def lib():
                     "herk_run_active": [vp, ctypes.POINTER(_State), i, i, d, d, i, ctypes.POINTER(i),
                                         ctypes.POINTER(i), ctypes.POINTER(i), vp],
                     "nslgf_set_tuning": [vp, i],
+                    "nslgf_set_batch_mode": [vp, i],
+                    "nslgf_batch_info": [vp, ctypes.POINTER(i), ctypes.POINTER(i)],
                     "nslgf_tuning_info": [vp, i, i, i, i, vp, ctypes.POINTER(i)],
                     "nslgf_tuning_save": [vp, ctypes.c_char_p],
                     "nslgf_tuning_load": [vp, ctypes.c_char_p],
@@ -511,6 +513,22 @@ class HerkState:
         _check("herk_run", lib().herk_run(handle(self.u.device.index), ctypes.byref(self.c), int(nsteps), float(eps),
                                           int(q_cap), ctypes.byref(n), _stream(self.u)))
         return n.value
+
+
+BATCH_PASSES, BATCH_PER_PROBLEM = 0, 1
+
+
+def set_batch_mode(mode: int, device: int | None = None):
+    """BATCH_PASSES (default): one launch per kernel of the step over every group of like problems;
+    BATCH_PER_PROBLEM: each problem's kernels on a branch stream of its own.  Same results."""
+    _check("nslgf_set_batch_mode", lib().nslgf_set_batch_mode(handle(device), int(mode)))
+
+
+def batch_info(device: int | None = None) -> tuple:
+    """(groups, kernel launches) of the last captured batch graph (groups 0: the per-problem form)."""
+    g, l = ctypes.c_int(), ctypes.c_int()
+    _check("nslgf_batch_info", lib().nslgf_batch_info(handle(device), ctypes.byref(g), ctypes.byref(l)))
+    return g.value, l.value
 
 
 def herk_step_batched(states: list) -> None:

@@ -28,6 +28,7 @@ __global__ void __launch_bounds__(256) k_zero(T* __restrict__ dst, long long n) 
 }
 
 int launch_zero(int dtype, void* dst, long long n, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (n <= 0) return NSLGF_OK;
     const int blocks = (int)std::min<long long>(4096, (n + 255) / 256);
     if (dtype == NSLGF_F32)
@@ -40,6 +41,7 @@ int launch_zero(int dtype, void* dst, long long n, hipStream_t s) {
 
 int launch_copy_box(int dtype, const void* src, const int sdim[3], const int soff[3], void* dst, const int ddim[3],
                     const int doff[3], const int ext[3], int ncomp, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     for (int a = 0; a < 3; ++a) {
         if (ext[a] <= 0) return NSLGF_OK;
         if (soff[a] < 0 || doff[a] < 0 || soff[a] + ext[a] > sdim[a] || doff[a] + ext[a] > ddim[a]) {

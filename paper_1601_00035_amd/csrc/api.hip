@@ -116,6 +116,9 @@ struct TuneEntry {
 struct BatchGraph {
     std::vector<unsigned long long> key;
     hipGraphExec_t exec = nullptr;
+    DevBuf desc;       // argument tables of the batched passes (read by the graph's kernels)
+    int groups = 0;    // groups of problems run as batched passes (0: one branch of kernels per problem)
+    int launches = 0;  // kernel launches in the graph
     ~BatchGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
     }
@@ -135,6 +138,7 @@ struct nslgf_ctx {
         if (capture) (void)hipStreamDestroy(capture);
     }
     bool capturing = false;  // a batch graph is being captured (no host round trips)
+    int batch_mode = NSLGF_BATCH_PASSES;
     bool no_alloc = false;   // inside lgf_convolve_noalloc: lookups that would allocate fail instead
     void* scratch = nullptr; // this device's address of the library's fixed scratch array
     int fft_plan = -1;  // column-pass plan choice: -1 per-dtype default, -2 autotune, else a variant index
@@ -362,6 +366,12 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
         *out = it->second.get();
         return NSLGF_OK;
     }
+    // (a plan is built, never recorded: its launches run even inside a recording)
+    struct Unrecord {
+        LaunchRecorder* r = launch_recorder();
+        Unrecord() { launch_recorder() = nullptr; }
+        ~Unrecord() { launch_recorder() = r; }
+    } unrecord;
     auto plan = std::make_unique<ConvPlan>();
     ConvPlan& p = *plan;
     p.nx = nx;
@@ -783,6 +793,138 @@ static void tableau(int scheme, double at[4][4], double ct[4]) {
     }
 }
 
+// Records one step of every state (no launch), groups the states whose launch records match position
+// by position (same kernels, grids and blocks: boxes of one size, dtype, scheme and integrating-factor
+// radii), and captures one graph in which every position of every group is one launch over a table of
+// the group's arguments, the groups on their own branch streams.  NSLGF_ESTATE if some step has a
+// launch without a batched form (nothing captured).  Plans, twiddles and launch shapes exist already.
+static int capture_batched_passes(nslgf_ctx* h, nslgf_state* const* sts, int n, hipStream_t s,
+                                  const std::vector<unsigned long long>& key) {
+    std::vector<LaunchRecorder> recs(n);
+    bool ok = true;
+    const bool prof_was = h->prof.on;
+    h->prof.on = false;
+    h->capturing = true;  // (no host round trips while recording)
+    for (int i = 0; i < n && ok; ++i) {
+        const nslgf_state saved = *sts[i];
+        launch_recorder() = &recs[i];
+        const int rc = ::herk_step(h, sts[i], s);
+        launch_recorder() = nullptr;
+        *sts[i] = saved;
+        if (rc != NSLGF_OK) {
+            h->capturing = false;
+            h->prof.on = prof_was;
+            return rc;
+        }
+        ok = recs[i].ok;
+    }
+    h->capturing = false;
+    h->prof.on = prof_was;
+    if (!ok) return NSLGF_ESTATE;
+    auto same = [](const LaunchRecorder& a, const LaunchRecorder& b) {
+        if (a.recs.size() != b.recs.size()) return false;
+        for (size_t k = 0; k < a.recs.size(); ++k) {
+            const LaunchRec &x = a.recs[k], &y = b.recs[k];
+            if (x.fn != y.fn || x.grid.x != y.grid.x || x.grid.y != y.grid.y || x.grid.z != y.grid.z ||
+                x.block.x != y.block.x || x.block.y != y.block.y || x.block.z != y.block.z || x.args.size() != y.args.size())
+                return false;
+        }
+        return true;
+    };
+    std::vector<std::vector<int>> groups;
+    for (int i = 0; i < n; ++i) {
+        size_t g = 0;
+        while (g < groups.size() && !same(recs[groups[g][0]], recs[i])) ++g;
+        if (g == groups.size()) groups.emplace_back();
+        groups[g].push_back(i);
+    }
+    // a batched launch multiplies one grid dimension by the group size (x, whose threads must stay
+    // below 2^32, or y or z, at most 65535): groups larger than every launch allows are split
+    {
+        std::vector<std::vector<int>> split;
+        for (const std::vector<int>& gr : groups) {
+            long long cap = 4096;
+            for (const LaunchRec& r : recs[gr[0]].recs) {
+                cap = std::min(cap, 65535LL / std::max(r.grid.y, r.grid.z));
+                cap = std::min(cap, 0xffffffffLL / ((long long)r.grid.x * r.block.x * r.block.y * r.block.z));
+            }
+            cap = std::max(cap, 1LL);
+            for (size_t a = 0; a < gr.size(); a += (size_t)cap)
+                split.emplace_back(gr.begin() + a, gr.begin() + std::min(gr.size(), a + (size_t)cap));
+        }
+        groups.swap(split);
+    }
+    // argument tables: for every group and position, the members' argument structs back to back
+    std::vector<std::vector<size_t>> off(groups.size());
+    size_t total = 0;
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (const LaunchRec& r : recs[groups[g][0]].recs) {
+            off[g].push_back(total);
+            total += (r.args.size() * groups[g].size() + 255) / 256 * 256;
+        }
+    std::vector<unsigned char> host(std::max<size_t>(total, 256));
+    for (size_t g = 0; g < groups.size(); ++g)
+        for (size_t k = 0; k < off[g].size(); ++k)
+            for (size_t m = 0; m < groups[g].size(); ++m) {
+                const LaunchRec& r = recs[groups[g][m]].recs[k];
+                std::memcpy(host.data() + off[g][k] + m * r.args.size(), r.args.data(), r.args.size());
+            }
+    auto graph_holder = std::make_unique<BatchGraph>();
+    NSLGF_TRY(graph_holder->desc.ensure(host.size()));
+    NSLGF_HIP_CHECK(hipMemcpy(graph_holder->desc.p, host.data(), host.size(), hipMemcpyHostToDevice));
+    const int nb = std::min((int)groups.size(), 16);
+    while ((int)h->branches.size() < nb) {
+        hipStream_t bs;
+        NSLGF_HIP_CHECK(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+        h->branches.push_back(bs);
+    }
+    while ((int)h->batch_events.size() < nb + 1) {
+        hipEvent_t e;
+        NSLGF_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->batch_events.push_back(e);
+    }
+    if (!h->capture) NSLGF_HIP_CHECK(hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    int rc = NSLGF_OK, launches = 0;
+    if (hipStreamBeginCapture(h->capture, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        set_error("herk_step_batched: stream capture could not start");
+        rc = NSLGF_EHIP;
+    }
+    if (rc == NSLGF_OK && hipEventRecord(h->batch_events[0], h->capture) != hipSuccess) rc = NSLGF_EHIP;
+    for (int b = 0; rc == NSLGF_OK && b < nb; ++b)
+        if (hipStreamWaitEvent(h->branches[b], h->batch_events[0], 0) != hipSuccess) rc = NSLGF_EHIP;
+    for (size_t g = 0; rc == NSLGF_OK && g < groups.size(); ++g) {
+        const std::vector<LaunchRec>& rs = recs[groups[g][0]].recs;
+        for (size_t k = 0; rc == NSLGF_OK && k < rs.size(); ++k, ++launches)
+            rc = rs[k].fn((const char*)graph_holder->desc.p + off[g][k], (int)groups[g].size(), rs[k].grid,
+                          rs[k].block, h->branches[g % nb]);
+    }
+    for (int b = 0; rc == NSLGF_OK && b < nb; ++b) {
+        if (hipEventRecord(h->batch_events[b + 1], h->branches[b]) != hipSuccess ||
+            hipStreamWaitEvent(h->capture, h->batch_events[b + 1], 0) != hipSuccess)
+            rc = NSLGF_EHIP;
+    }
+    const hipError_t ec = hipStreamEndCapture(h->capture, &graph);
+    if (rc == NSLGF_OK && ec != hipSuccess) {
+        set_error(std::string("herk_step_batched: capture failed: ") + hipGetErrorString(ec));
+        rc = NSLGF_EHIP;
+    }
+    if (rc == NSLGF_OK && hipGraphInstantiate(&graph_holder->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error("herk_step_batched: graph instantiation failed");
+        rc = NSLGF_EHIP;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != NSLGF_OK) {
+        (void)hipGetLastError();
+        return rc;
+    }
+    graph_holder->key = key;
+    graph_holder->groups = (int)groups.size();
+    graph_holder->launches = launches;
+    h->batch = std::move(graph_holder);
+    return NSLGF_OK;
+}
+
 // Reads a guarded step's accumulators back (synchronising the stream): st->div_max, and
 // NSLGF_ENONFINITE if a non-finite value was seen.
 static int read_guard(nslgf_state* st, const unsigned long long* acc, hipStream_t s) {
@@ -1118,6 +1260,15 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
     }
     if (!h->batch || h->batch->key != key) {
         h->batch.reset();
+        if (h->batch_mode == NSLGF_BATCH_PASSES) {
+            const int rc = capture_batched_passes(h, sts, n, s, key);
+            if (rc != NSLGF_ESTATE) {  // (NSLGF_ESTATE: a step has no batched form; capture it per problem)
+                NSLGF_TRY(rc);
+            }
+        }
+    }
+    if (!h->batch || h->batch->key != key) {
+        h->batch.reset();
         const int nb = std::min(n, 16);
         while ((int)h->branches.size() < nb) {
             hipStream_t bs;
@@ -1168,7 +1319,7 @@ int herk_step_batched(nslgf_t h, nslgf_state* const* sts, int n, void* stream) {
             (void)hipGetLastError();
             return rc;
         }
-        g->key = std::move(key);
+        g->key = key;
         h->batch = std::move(g);
     }
     {
@@ -1738,6 +1889,22 @@ int nslgf_copy(nslgf_t h, const void* src, void* dst, size_t n, int dtype, void*
     NSLGF_CHECK_ARG(src && dst && src != dst, "nslgf_copy: null or aliased pointers");
     hipStream_t s = (hipStream_t)stream;
     NSLGF_PROF(h, "copy", s, launch_copy(src, dst, n * dtype_size(dtype), s));
+    return NSLGF_OK;
+}
+
+int nslgf_set_batch_mode(nslgf_t h, int mode) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(mode == NSLGF_BATCH_PASSES || mode == NSLGF_BATCH_PER_PROBLEM, "nslgf_set_batch_mode: unknown mode");
+    if (mode != h->batch_mode) h->batch.reset();
+    h->batch_mode = mode;
+    return NSLGF_OK;
+}
+
+int nslgf_batch_info(nslgf_t h, int* groups, int* launches) {
+    NSLGF_ENTER(h);
+    NSLGF_CHECK_ARG(groups && launches, "nslgf_batch_info: null output");
+    *groups = h->batch ? h->batch->groups : 0;
+    *launches = h->batch ? h->batch->launches : 0;
     return NSLGF_OK;
 }
 

@@ -46,6 +46,7 @@ __global__ void k_guard_reset(unsigned long long* acc) {
 }
 
 int launch_guard_reset(unsigned long long* acc, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     hipLaunchKernelGGL(k_guard_reset, dim3(1), dim3(64), 0, s, acc);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
@@ -53,6 +54,7 @@ int launch_guard_reset(unsigned long long* acc, hipStream_t s) {
 
 int launch_guard(int dtype, const void* u, const void* d, int nx, int ny, int nz, int margin, double dx,
                  unsigned long long* acc, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     const long long n = (long long)nx * ny * nz;
     const int blocks = (int)std::min<long long>(2048, (n + 255) / 256);
     if (margin < 1) margin = 1;

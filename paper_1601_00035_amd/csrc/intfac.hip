@@ -153,15 +153,38 @@ struct IfTerms {
 // the workgroup that owns its output row).
 // Workgroups are numbered so that all row blocks of one plane run on one XCD (the hardware hands
 // workgroup b to XCD b mod 8) and share their halo rows through its L2.
-template <typename T, int R, int RB, int P, int MODE>
-__global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz,
-                                               int ntiles, int S, IfWeights wts, IfTerms terms) {
+// Arguments of one fused x-y pass (the batched form reads one table entry per problem).
+struct IfXyArgs {
+    const void* in;
+    void* out;
+    int nx, ny, nz, ntiles, S;
+    IfWeights wts;
+    IfTerms terms;
+};
+// BATCH: per consecutive logical workgroups make up one problem, whose arguments are da[problem].
+template <typename T, int R, int RB, int P, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) k_if_xy(IfXyArgs a0, const IfXyArgs* __restrict__ da, int per) {
     constexpr int W = 256 + 2 * R;  // LDS row length
-    const int NSTEP = (S + 2 * R + RB - 1) / RB;
     constexpr int NW = 2 * R + RB;  // register window (x-filtered rows)
     __shared__ T tile_lds[2][RB][W];
     const int nb = (int)gridDim.x, b = (int)blockIdx.x, xcd = b % 8;
-    const int lg = xcd * (nb / 8) + min(xcd, nb % 8) + b / 8;
+    int lg = xcd * (nb / 8) + min(xcd, nb % 8) + b / 8;
+    int pb = 0;
+    if constexpr (BATCH) {
+        pb = lg / per;
+        lg -= pb * per;
+    }
+    const IfXyArgs* A = BATCH ? da + pb : nullptr;
+    const T* __restrict__ in = (const T*)(BATCH ? A->in : a0.in);
+    T* __restrict__ out = (T*)(BATCH ? A->out : a0.out);
+    const int nx = BATCH ? A->nx : a0.nx, ny = BATCH ? A->ny : a0.ny, nz = BATCH ? A->nz : a0.nz;
+    const int ntiles = BATCH ? A->ntiles : a0.ntiles, S = BATCH ? A->S : a0.S;
+    const IfTerms terms = BATCH ? A->terms : a0.terms;
+    auto wd = [&](int d) -> double {
+        if constexpr (BATCH) return A->wts.w[d];
+        else return a0.wts.w[d];
+    };
+    const int NSTEP = (S + 2 * R + RB - 1) / RB;
     const int tile = lg % ntiles, plane = lg / ntiles;  // plane = comp * nz + z
     const int x = threadIdx.x;
     const bool act = x < nx;
@@ -235,9 +258,9 @@ __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __re
             T xf = (T)0;
             if (act) {
                 const T* p = &lt[i][R + x];
-                double acc = wts.w[0] * (double)p[0];
+                double acc = wd(0) * (double)p[0];
 #pragma unroll
-                for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(p[-d] + p[d]);
+                for (int d = 1; d <= R; ++d) acc += wd(d) * (double)(p[-d] + p[d]);
                 xf = (T)acc;
             }
             win[2 * R + i] = xf;
@@ -248,9 +271,9 @@ __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __re
             const int y = ylo + kk - R;
             if (kk >= 2 * R && act && y < ny && y < y0 + S) {
                 const T* v = win + i;
-                double acc = wts.w[0] * (double)v[R];
+                double acc = wd(0) * (double)v[R];
 #pragma unroll
-                for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[R - d] + v[R + d]);
+                for (int d = 1; d <= R; ++d) acc += wd(d) * (double)(v[R - d] + v[R + d]);
                 out[pbase + (long long)y * nx + x] = (T)acc;
             }
         }
@@ -261,14 +284,35 @@ __global__ void __launch_bounds__(256) k_if_xy(const T* __restrict__ in, T* __re
 // and store of a wavefront is one contiguous row segment) and S consecutive outputs of its line; the
 // S + 2R inputs go straight from memory into registers (neighbouring segments re-read their shared
 // halo through the caches, not from HBM).  No LDS and no barriers.
-template <typename T, int R, int S>
-__global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T* __restrict__ out, int nx, int len,
-                                                    long long stride, int nouter, long long outer_stride,
-                                                    long long comp_stride, IfWeights wts) {
+struct IfStrArgs {
+    const void* in;
+    void* out;
+    int nx, len, nouter;
+    long long stride, outer_stride, comp_stride;
+    IfWeights wts;
+};
+// BATCH: per consecutive values of the grid's z index make up one problem, whose arguments are da[problem].
+template <typename T, int R, int S, bool BATCH>
+__global__ void __launch_bounds__(256) k_if_strided(IfStrArgs a0, const IfStrArgs* __restrict__ da, int per) {
+    int bz = blockIdx.z, pb = 0;
+    if constexpr (BATCH) {
+        pb = bz / per;
+        bz -= pb * per;
+    }
+    const IfStrArgs* A = BATCH ? da + pb : nullptr;
+    const T* __restrict__ in = (const T*)(BATCH ? A->in : a0.in);
+    T* __restrict__ out = (T*)(BATCH ? A->out : a0.out);
+    const int nx = BATCH ? A->nx : a0.nx, len = BATCH ? A->len : a0.len, nouter = BATCH ? A->nouter : a0.nouter;
+    const long long stride = BATCH ? A->stride : a0.stride, outer_stride = BATCH ? A->outer_stride : a0.outer_stride;
+    const long long comp_stride = BATCH ? A->comp_stride : a0.comp_stride;
+    auto wd = [&](int d) -> double {
+        if constexpr (BATCH) return A->wts.w[d];
+        else return a0.wts.w[d];
+    };
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int k0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * S;
     if (x >= nx || k0 >= len) return;
-    const int o = blockIdx.z % nouter, comp = blockIdx.z / nouter;
+    const int o = bz % nouter, comp = bz / nouter;
     const long long base = comp * comp_stride + (long long)o * outer_stride + x;
     T v[S + 2 * R];
     if (k0 >= R && k0 + S + R <= len) {  // the whole window inside the line: loads without tests
@@ -285,9 +329,9 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
 #pragma unroll
     for (int m = 0; m < S; ++m) {
         if (full || k0 + m < len) {
-            double acc = wts.w[0] * (double)v[m + R];
+            double acc = wd(0) * (double)v[m + R];
 #pragma unroll
-            for (int d = 1; d <= R; ++d) acc += wts.w[d] * (double)(v[m + R - d] + v[m + R + d]);
+            for (int d = 1; d <= R; ++d) acc += wd(d) * (double)(v[m + R - d] + v[m + R + d]);
             out[base + (long long)(k0 + m) * stride] = (T)acc;
         }
     }
@@ -297,6 +341,29 @@ __global__ void __launch_bounds__(256) k_if_strided(const T* __restrict__ in, T*
 constexpr int kIfRowsPerStep = 4;    // rows per barrier of the fused x-y pass
 constexpr int kIfPrefetch = 2;       // steps loaded ahead by the fused x-y pass
 
+template <typename T, int R, int S>
+static int batched_strided(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_if_strided<T, R, S, true>), dim3(g.x, g.y, g.z * nprob), b, 0, s, IfStrArgs{},
+                       (const IfStrArgs*)args, (int)g.z);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int R, int MODE>
+static int batched_xy(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, MODE, true>), dim3(g.x * nprob), b, 0, s,
+                       IfXyArgs{}, (const IfXyArgs*)args, (int)g.x);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+template <typename T, int R, int S> static void issue_strided(const IfStrArgs& a, dim3 grid, hipStream_t s) {
+    if (launch_recorder()) {
+        record_launch(&batched_strided<T, R, S>, grid, dim3(256), a);
+        return;
+    }
+    hipLaunchKernelGGL((k_if_strided<T, R, S, false>), grid, dim3(256), 0, s, a, nullptr, 0);
+}
+
 template <typename T, int R>
 static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
                          hipStream_t s, int seg) {
@@ -305,15 +372,19 @@ static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int n
     const long long stride = axis == 1 ? (long long)nx : (long long)nx * ny;
     const int nouter = axis == 1 ? nz : ny;
     const long long outer_stride = axis == 1 ? (long long)nx * ny : (long long)nx;
-    if (seg == 16) {
-        dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, 16), 4), nouter * ncomp);
-        hipLaunchKernelGGL((k_if_strided<T, R, 16>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
-                           outer_stride, n, wts);
-    } else {
-        dim3 grid(ceil_div(nx, 64), ceil_div(ceil_div(len, 32), 4), nouter * ncomp);
-        hipLaunchKernelGGL((k_if_strided<T, R, 32>), grid, dim3(256), 0, s, in, out, nx, len, stride, nouter,
-                           outer_stride, n, wts);
+    const IfStrArgs a{in, out, nx, len, nouter, stride, outer_stride, n, wts};
+    if (seg == 16)
+        issue_strided<T, R, 16>(a, dim3(ceil_div(nx, 64), ceil_div(ceil_div(len, 16), 4), nouter * ncomp), s);
+    else
+        issue_strided<T, R, 32>(a, dim3(ceil_div(nx, 64), ceil_div(ceil_div(len, 32), 4), nouter * ncomp), s);
+}
+
+template <typename T, int R, int MODE> static void issue_xy(const IfXyArgs& a, dim3 grid, hipStream_t s) {
+    if (launch_recorder()) {
+        record_launch(&batched_xy<T, R, MODE>, grid, dim3(256), a);
+        return;
     }
+    hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, MODE, false>), grid, dim3(256), 0, s, a, nullptr, 0);
 }
 
 // (rows: output rows per workgroup; halo rows re-read: 2R / rows)
@@ -322,8 +393,8 @@ static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, in
                       hipStream_t s, int rows) {
     const int ntiles = ceil_div(ny, rows);
     const dim3 grid((unsigned)((long long)ntiles * nz * ncomp));
-    const T* in = (const T*)cb.p[0];
-    IfTerms terms{};
+    IfXyArgs a{cb.p[0], out, nx, ny, nz, ntiles, rows, wts, IfTerms{}};
+    IfTerms& terms = a.terms;
     if (cb.proj) {
         const IfProject& pj = *cb.proj;
         terms.dhat = pj.dhat;
@@ -334,19 +405,16 @@ static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, in
         terms.c_q = pj.c_q;
         terms.c_w1 = pj.c_w1;
         terms.inv = pj.inv;
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_PROJ>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
+        issue_xy<T, R, IF_IN_PROJ>(a, grid, s);
     } else if (cb.p[1]) {
         terms.in1 = cb.p[1];
         terms.in2 = cb.p[2];
         terms.c0 = cb.c[0];
         terms.c1 = cb.c[1];
         terms.c2 = cb.c[2];
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_COMB>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
+        issue_xy<T, R, IF_IN_COMB>(a, grid, s);
     } else {
-        hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, IF_IN_PLAIN>), grid, dim3(256), 0,
-                           s, in, out, nx, ny, nz, ntiles, rows, wts, terms);
+        issue_xy<T, R, IF_IN_PLAIN>(a, grid, s);
     }
 }
 
@@ -367,7 +435,8 @@ static int if_axis_t(int axis, const void* in, void* out, int ncomp, int nx, int
             default: break;
         }
     }
-    // runtime-radius passes (every radius on x; radii above the fixed ones on y and z)
+    // runtime-radius passes (every radius on x; radii above the fixed ones on y and z); no batched form
+    if (recording_unsupported()) return NSLGF_OK;
     if (axis == 0) {
         if (nx > kIfRowElems) {
             set_error("if_apply: rows longer than the LDS row buffer");

@@ -2,9 +2,41 @@
 // kernel translation units).  Every launcher enqueues on `stream` and returns an nslgf status.
 #pragma once
 
+#include <cstring>
+#include <vector>
+
 #include "common.h"
 
 namespace nslgf {
+
+// ---- batched launches ----------------------------------------------------------------------------
+// While a LaunchRecorder is installed on the calling thread, the launchers of the IF-HERK stage record
+// their launches (the batched form of the kernel, one problem's grid and block, the arguments) instead
+// of issuing them.  Problems whose records match position by position can then run every position as
+// one launch over a device table of their arguments (the kernels read their arguments from the table
+// entry of the problem their workgroup belongs to).
+using BatchedLaunch = int (*)(const void* args, int nprob, dim3 grid, dim3 block, hipStream_t s);
+struct LaunchRec {
+    BatchedLaunch fn;
+    dim3 grid, block;
+    std::vector<unsigned char> args;
+};
+struct LaunchRecorder {
+    std::vector<LaunchRec> recs;
+    bool ok = true;  // false once a launch without a batched form was requested
+};
+LaunchRecorder*& launch_recorder();  // this thread's recorder (null: launch normally)
+template <class A> inline void record_launch(BatchedLaunch fn, dim3 g, dim3 b, const A& a) {
+    LaunchRec r{fn, g, b, std::vector<unsigned char>(sizeof(A))};
+    std::memcpy(r.args.data(), &a, sizeof(A));
+    launch_recorder()->recs.push_back(std::move(r));
+}
+// For launchers without a batched form: true (and the recording marked unusable) while recording.
+inline bool recording_unsupported() {
+    if (!launch_recorder()) return false;
+    launch_recorder()->ok = false;
+    return true;
+}
 
 // Validates a handle and makes its device current (used by entry points outside api.hip).
 int enter_handle(nslgf_t h);

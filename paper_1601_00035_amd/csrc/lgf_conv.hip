@@ -37,8 +37,11 @@ __device__ __forceinline__ T masked_div_at(const T* f, int x, int y, int z, int 
 // PAIRS: the real rows are read as pairs (x[2n], x[2n+1]) with one vector load each (the host sets it
 // when the base is aligned, rows and components have even lengths, and n_io is even).  DIV: the rows
 // are the masked divergence of RowPass::div_src, formed on load.
+// Batched form (da set): the workgroups of grid z index p take the arguments da[p].
 template <typename T, int LH, bool PAIRS, bool DIV>
-__global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
+__global__ void __launch_bounds__(256) k_row_r2c(RowPass a0, const RowPass* __restrict__ da) {
+    RowPass a = a0;
+    if (da) a = da[blockIdx.z];
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
     using RL = typename P::Fwd;
@@ -115,7 +118,9 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a) {
 
 // PAIRS: the real outputs are written as pairs with one vector store each (conditions as for r2c).
 template <typename T, int LH, bool PAIRS>
-__global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
+__global__ void __launch_bounds__(256) k_row_c2r(RowPass a0, const RowPass* __restrict__ da) {
+    RowPass a = a0;
+    if (da) a = da[blockIdx.z];
     using P = Plan1D<LH>;
     constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
     using RL = Reverse<typename P::Fwd>;
@@ -173,9 +178,11 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a) {
 // PR bit 1: n_in <= L/2, so the forward transform's first butterflies see a zero upper half; bit 2:
 // n_out <= L/2, so the inverse transform's last butterflies produce only the lower half (set by the
 // host; the fused pass always has both).
+// Batched form (da set): one problem spans `per` consecutive values of the grid's z index (FWD, INV:
+// its components) or of the logical workgroup index (CONV) and takes the arguments da[p].
 template <typename T, int L, int MODE, int V = 0, int PR = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PlanV<L, V>::waves)))
-k_col(ColPass a) {
+k_col(ColPass a0, const ColPass* __restrict__ da, int per) {
     using P = PlanV<L, V>;
     constexpr int E = P::E, TP = L / E, TB = col_tb<T>(TP);
     using RF = typename P::Fwd;
@@ -187,13 +194,18 @@ k_col(ColPass a) {
     const int tid = threadIdx.x;
     const int c = tid % TB, t = tid / TB;
     int tile, outer, comp;
+    ColPass a = a0;
     if constexpr (MODE == COL_CONV) {
         // One-dimensional grid, remapped so that the workgroups sharing a spectrum tile (the mirrored
         // outer indices ky and P - ky, every component) run on one XCD one after the other: the
         // hardware hands workgroup b to XCD b mod 8, so XCD x takes the x-th contiguous chunk of the
         // logical order below and the tile stays in that XCD's L2.
         const int n = (int)gridDim.x, b = (int)blockIdx.x, x = b % 8;
-        const int lg = x * (n / 8) + min(x, n % 8) + b / 8;
+        int lg = x * (n / 8) + min(x, n % 8) + b / 8;
+        if (da) {
+            a = da[lg / per];
+            lg %= per;
+        }
         comp = lg % a.ncomp;
         const int rest = lg / a.ncomp;
         const int sq = rest % a.nouter;
@@ -203,6 +215,10 @@ k_col(ColPass a) {
         tile = blockIdx.x;
         outer = blockIdx.y;
         comp = blockIdx.z;
+        if (da) {
+            a = da[blockIdx.z / per];
+            comp = blockIdx.z % per;
+        }
     }
     const int col = tile * TB + c;
     const bool valid = col < a.ncols;
@@ -343,6 +359,57 @@ int make_twiddles(int L, int dtype, void** dev_out) {
     return NSLGF_OK;
 }
 
+LaunchRecorder*& launch_recorder() {
+    static thread_local LaunchRecorder* r = nullptr;
+    return r;
+}
+
+// Batched launches of the row and column passes: nprob problems' argument tables, one problem's grid.
+template <typename T, int LH, bool PAIRS, bool DIV>
+static int batched_r2c(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_r2c<T, LH, PAIRS, DIV>), dim3(g.x, g.y, nprob), b, 0, s, RowPass{}, (const RowPass*)args);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int LH, bool PAIRS>
+static int batched_c2r(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_row_c2r<T, LH, PAIRS>), dim3(g.x, g.y, nprob), b, 0, s, RowPass{}, (const RowPass*)args);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int L, int MODE, int V, int PR>
+static int batched_col(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    if (MODE == COL_CONV)
+        hipLaunchKernelGGL((k_col<T, L, MODE, V, PR>), dim3(g.x * nprob), b, 0, s, ColPass{}, (const ColPass*)args,
+                           (int)g.x);
+    else
+        hipLaunchKernelGGL((k_col<T, L, MODE, V, PR>), dim3(g.x, g.y, g.z * nprob), b, 0, s, ColPass{},
+                           (const ColPass*)args, (int)g.z);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+template <typename T, int LH, bool PAIRS, bool DIV> static int issue_r2c(const RowPass& a, dim3 grid, dim3 block,
+                                                                          hipStream_t s) {
+    if (launch_recorder()) {
+        record_launch(&batched_r2c<T, LH, PAIRS, DIV>, grid, block, a);
+        return NSLGF_OK;
+    }
+    hipLaunchKernelGGL((k_row_r2c<T, LH, PAIRS, DIV>), grid, block, 0, s, a, nullptr);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T, int L, int MODE, int V, int PR> static int issue_col(const ColPass& a, dim3 grid, dim3 block,
+                                                                           hipStream_t s) {
+    if (launch_recorder()) {
+        record_launch(&batched_col<T, L, MODE, V, PR>, grid, block, a);
+        return NSLGF_OK;
+    }
+    hipLaunchKernelGGL((k_col<T, L, MODE, V, PR>), grid, block, 0, s, a, nullptr, 0);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
 template <typename T> static bool real_pairs(const void* p, long long row, long long comp, int n_io) {
     return ((uintptr_t)p % (2 * sizeof(T))) == 0 && row % 2 == 0 && comp % 2 == 0 && n_io % 2 == 0;
 }
@@ -354,22 +421,23 @@ template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s)
             set_error("row pass: the divergence input needs one component over ny * nz rows");
             return NSLGF_EINVAL;
         }
-        hipLaunchKernelGGL((k_row_r2c<T, LH, false, true>), grid, dim3(RPW * TP), 0, s, a);
-    } else if (real_pairs<T>(a.in, a.in_row, a.in_comp, a.n_io)) {
-        hipLaunchKernelGGL((k_row_r2c<T, LH, true, false>), grid, dim3(RPW * TP), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_row_r2c<T, LH, false, false>), grid, dim3(RPW * TP), 0, s, a);
+        return issue_r2c<T, LH, false, true>(a, grid, dim3(RPW * TP), s);
     }
-    NSLGF_LAUNCH_CHECK();
-    return NSLGF_OK;
+    if (real_pairs<T>(a.in, a.in_row, a.in_comp, a.n_io)) return issue_r2c<T, LH, true, false>(a, grid, dim3(RPW * TP), s);
+    return issue_r2c<T, LH, false, false>(a, grid, dim3(RPW * TP), s);
 }
 template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s) {
     constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
-    if (real_pairs<T>(a.out, a.out_row, a.out_comp, a.n_io))
-        hipLaunchKernelGGL((k_row_c2r<T, LH, true>), grid, dim3(RPW * TP), 0, s, a);
+    const bool pairs = real_pairs<T>(a.out, a.out_row, a.out_comp, a.n_io);
+    if (launch_recorder()) {
+        record_launch(pairs ? &batched_c2r<T, LH, true> : &batched_c2r<T, LH, false>, grid, dim3(RPW * TP), a);
+        return NSLGF_OK;
+    }
+    if (pairs)
+        hipLaunchKernelGGL((k_row_c2r<T, LH, true>), grid, dim3(RPW * TP), 0, s, a, nullptr);
     else
-        hipLaunchKernelGGL((k_row_c2r<T, LH, false>), grid, dim3(RPW * TP), 0, s, a);
+        hipLaunchKernelGGL((k_row_c2r<T, LH, false>), grid, dim3(RPW * TP), 0, s, a, nullptr);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
@@ -388,14 +456,11 @@ template <typename T, int L, int MODE, int V = 0> static int do_col(const ColPas
             set_error("column pass: the fused pass needs n_in, n_out <= L/2");
             return NSLGF_EINVAL;
         }
-        hipLaunchKernelGGL((k_col<T, L, MODE, V, 3>), grid, dim3(TB * TP), 0, s, a);
-    } else if ((MODE == COL_FWD && half_in) || (MODE == COL_INV && half_out)) {
-        hipLaunchKernelGGL((k_col<T, L, MODE, V, MODE == COL_FWD ? 1 : 2>), grid, dim3(TB * TP), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_col<T, L, MODE, V, 0>), grid, dim3(TB * TP), 0, s, a);
+        return issue_col<T, L, MODE, V, 3>(a, grid, dim3(TB * TP), s);
     }
-    NSLGF_LAUNCH_CHECK();
-    return NSLGF_OK;
+    if ((MODE == COL_FWD && half_in) || (MODE == COL_INV && half_out))
+        return issue_col<T, L, MODE, V, MODE == COL_FWD ? 1 : 2>(a, grid, dim3(TB * TP), s);
+    return issue_col<T, L, MODE, V, 0>(a, grid, dim3(TB * TP), s);
 }
 
 #define NSLGF_ROW_SWITCH(FN, T)                                                                    \

@@ -90,6 +90,14 @@ __device__ __forceinline__ void nonlinear_at(const V& f, int i, int j, int k, T 
 // pick another of kCellShape), one z plane per grid z (no integer division); launch with cell_grid /
 // cell_block.  (Renumbering the blocks so that each XCD works through a contiguous range of planes
 // was measured slower for the stage kernels.)
+#define NSLGF_CELL_INDEX_Z(KZ)                                                                     \
+    const long long n = (long long)nx * ny * nz;                                                   \
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);                                    \
+    const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);                                    \
+    const int kz_ = (KZ);                                                                          \
+    const int k = kz_ % nz;                                                                        \
+    if (i >= nx || j >= ny) return;                                                                \
+    const long long idx = (long long)((k * ny + j) * nx + i);
 #define NSLGF_CELL_INDEX                                                                           \
     const long long n = (long long)nx * ny * nz;                                                   \
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);                                    \
@@ -169,12 +177,60 @@ __global__ void __launch_bounds__(256) k_laplacian(const T* a, T* out, int nx, i
                            A(i, j, k + 1) + A(i, j, k - 1)) * idx2;
 }
 
+// Arguments of the stage kernels (the batched forms read one table entry per problem: per consecutive
+// values of the grid's z index make up one problem).
+struct StageRhsArgs {
+    const void* u;
+    void* q;
+    const void* w1;
+    const void* w2;
+    void* r;
+    double idx;
+    StageCoef c;
+    int nx, ny, nz;
+};
+struct StageProjArgs {
+    const void* r;
+    void* rout;
+    const void* dhat;
+    const void* q;
+    const void* w1;
+    const void* w2;
+    double c_q, c_w1, c_w2;
+    void* wnew;
+    double inv, idx;
+    int nx, ny, nz;
+};
+struct AxpbyArgs {
+    void* out;
+    const void* x;
+    double a;
+    const void* y;
+    double b;
+    const void* z;
+    double c;
+    long long n;
+};
+
 // r = c_q q + c_w1 w1 + c_w2 w2 + c_g M_soln Ntilde(u); optionally also copies u into q first
 // (stage 1 starts the step with q^1 = u_k).
-template <typename T>
-__global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1, const T* w2, T* r, T idx_,
-                                                   StageCoef c, int copy_q, int nx, int ny, int nz) {
-    NSLGF_CELL_INDEX
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(256) k_stage_rhs(StageRhsArgs a0, const StageRhsArgs* __restrict__ da, int per) {
+    int bz = blockIdx.z, pb = 0;
+    if constexpr (BATCH) {
+        pb = bz / per;
+        bz -= pb * per;
+    }
+    const StageRhsArgs& A = BATCH ? da[pb] : a0;
+    const T* u = (const T*)A.u;
+    T* q = (T*)A.q;
+    const T* w1 = (const T*)A.w1;
+    const T* w2 = (const T*)A.w2;
+    T* r = (T*)A.r;
+    const T idx_ = (T)A.idx;
+    const StageCoef c = A.c;
+    const int copy_q = c.copy_q, nx = A.nx, ny = A.ny, nz = A.nz;
+    NSLGF_CELL_INDEX_Z(bz)
     Vec3<T> U = vec3(u, nx, ny, nz);
     const bool in_soln = in_domain(i, j, k, nx, ny, nz, c.nbuf, c.soln_blocks, c.nb);
     T nl[3] = {0, 0, 0};
@@ -202,11 +258,26 @@ __global__ void __launch_bounds__(256) k_stage_rhs(const T* u, T* q, const T* w1
 }
 
 // y = r - G dhat (into r); if wnew: wnew = (y - (c_q q + c_w1 w1 + c_w2 w2)) * inv
-template <typename T>
-__global__ void __launch_bounds__(256) k_stage_project(const T* r, T* rout, const T* dhat, const T* q, const T* w1,
-                                                       const T* w2, double c_q, double c_w1, double c_w2, T* wnew,
-                                                       double inv, int nx, int ny, int nz, T idx_) {
-    NSLGF_CELL_INDEX
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(256) k_stage_project(StageProjArgs a0, const StageProjArgs* __restrict__ da,
+                                                       int per) {
+    int bz = blockIdx.z, pb = 0;
+    if constexpr (BATCH) {
+        pb = bz / per;
+        bz -= pb * per;
+    }
+    const StageProjArgs& A = BATCH ? da[pb] : a0;
+    const T* r = (const T*)A.r;
+    T* rout = (T*)A.rout;
+    const T* dhat = (const T*)A.dhat;
+    const T* q = (const T*)A.q;
+    const T* w1 = (const T*)A.w1;
+    const T* w2 = (const T*)A.w2;
+    const double c_q = A.c_q, c_w1 = A.c_w1, c_w2 = A.c_w2, inv = A.inv;
+    T* wnew = (T*)A.wnew;
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
+    const T idx_ = (T)A.idx;
+    NSLGF_CELL_INDEX_Z(bz)
     Fld<T> D{dhat, nx, ny, nz};
     const T d0 = D(i, j, k);
     const T g[3] = {(D(i + 1, j, k) - d0) * idx_, (D(i, j + 1, k) - d0) * idx_, (D(i, j, k + 1) - d0) * idx_};
@@ -224,9 +295,16 @@ __global__ void __launch_bounds__(256) k_stage_project(const T* r, T* rout, cons
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_axpby(T* out, const T* x, double a, const T* y, double b, const T* z, double c,
-                                               long long n) {
+// BATCH: the grid's y index is the problem.
+template <typename T, bool BATCH>
+__global__ void __launch_bounds__(256) k_axpby(AxpbyArgs a0, const AxpbyArgs* __restrict__ da) {
+    const AxpbyArgs& A = BATCH ? da[blockIdx.y] : a0;
+    T* out = (T*)A.out;
+    const T* x = (const T*)A.x;
+    const T* y = (const T*)A.y;
+    const T* z = (const T*)A.z;
+    const double a = A.a, b = A.b, c = A.c;
+    const long long n = A.n;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     double v = a * (double)x[idx];
@@ -242,6 +320,7 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ in, uint
 }
 
 int launch_copy(const void* in, void* out, size_t bytes, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (bytes % 16 != 0 || ((uintptr_t)in % 16) != 0 || ((uintptr_t)out % 16) != 0) {
         set_error("copy: size and pointers must be multiples of 16 bytes");
         return NSLGF_EINVAL;
@@ -422,6 +501,7 @@ __global__ void __launch_bounds__(256) k_block_weights(const T* u, const T* nl, 
 template <typename T>
 static int stencil_t(int op, const void* src, void* dst, int ncomp, int nx, int ny, int nz, double dx, hipStream_t s,
                      int shape) {
+    if (recording_unsupported()) return NSLGF_OK;
     const long long n = (long long)nx * ny * nz;
     const T idx_ = (T)(1.0 / dx);
     const dim3 grid = cell_grid(nx, ny, nz, 1, shape), block = cell_block(shape);
@@ -447,22 +527,44 @@ int launch_stencil(int op, int dtype, const void* src, void* dst, int ncomp, int
     return stencil_t<double>(op, src, dst, ncomp, nx, ny, nz, dx, s, shape);
 }
 
+// Batched launches: nprob problems' argument tables, one problem's grid (z extended by nprob).
+template <typename T> static int batched_rhs(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_rhs<T, true>), dim3(g.x, g.y, g.z * nprob), b, 0, s, StageRhsArgs{},
+                       (const StageRhsArgs*)args, (int)g.z);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T> static int batched_proj(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_project<T, true>), dim3(g.x, g.y, g.z * nprob), b, 0, s, StageProjArgs{},
+                       (const StageProjArgs*)args, (int)g.z);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+template <typename T> static int batched_axpby(const void* args, int nprob, dim3 g, dim3 b, hipStream_t s) {
+    hipLaunchKernelGGL((k_axpby<T, true>), dim3(g.x, nprob), b, 0, s, AxpbyArgs{}, (const AxpbyArgs*)args);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
 int launch_stage_rhs(int dtype, const void* u, const void* q, const void* w1, const void* w2, void* r,
                      const StageCoef& c, int nx, int ny, int nz, double dx, hipStream_t s, int shape) {
-    const int copy_q = c.copy_q;
-    const StageCoef cc = c;
+    const StageRhsArgs a{u, (void*)q, w1, w2, r, 1.0 / dx, c, nx, ny, nz};
+    const dim3 grid = cell_grid(nx, ny, nz, 1, shape), block = cell_block(shape);
+    if (launch_recorder()) {
+        record_launch(dtype == NSLGF_F32 ? &batched_rhs<float> : &batched_rhs<double>, grid, block, a);
+        return NSLGF_OK;
+    }
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_rhs<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)u, (float*)q,
-                           (const float*)w1, (const float*)w2, (float*)r, (float)(1.0 / dx), cc, copy_q, nx, ny, nz);
+        hipLaunchKernelGGL((k_stage_rhs<float, false>), grid, block, 0, s, a, nullptr, 0);
     else
-        hipLaunchKernelGGL(k_stage_rhs<double>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const double*)u, (double*)q,
-                           (const double*)w1, (const double*)w2, (double*)r, 1.0 / dx, cc, copy_q, nx, ny, nz);
+        hipLaunchKernelGGL((k_stage_rhs<double, false>), grid, block, 0, s, a, nullptr, 0);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
 
 int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, int ny, int nz, double dx,
                       hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     const long long n = (long long)nx * ny * nz;
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_div<float>, cell_grid(nx, ny, nz), cell_block(0), 0, s, (const float*)r, (float*)sdiv, nx,
@@ -477,32 +579,39 @@ int launch_masked_div(int dtype, const void* r, void* sdiv, int nbuf, int nx, in
 int launch_stage_project(int dtype, const void* r, void* rout, const void* dhat, const void* q, const void* w1,
                          const void* w2, double c_q, double c_w1, double c_w2, void* wnew, double inv, int nx, int ny,
                          int nz, double dx, hipStream_t s, int shape) {
+    const StageProjArgs a{r, rout, dhat, q, w1, w2, c_q, c_w1, c_w2, wnew, inv, 1.0 / dx, nx, ny, nz};
+    const dim3 grid = cell_grid(nx, ny, nz, 1, shape), block = cell_block(shape);
+    if (launch_recorder()) {
+        record_launch(dtype == NSLGF_F32 ? &batched_proj<float> : &batched_proj<double>, grid, block, a);
+        return NSLGF_OK;
+    }
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_stage_project<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)r,
-                           (float*)rout, (const float*)dhat, (const float*)q, (const float*)w1, (const float*)w2, c_q, c_w1, c_w2,
-                           (float*)wnew, inv, nx, ny, nz, (float)(1.0 / dx));
+        hipLaunchKernelGGL((k_stage_project<float, false>), grid, block, 0, s, a, nullptr, 0);
     else
-        hipLaunchKernelGGL(k_stage_project<double>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const double*)r,
-                           (double*)rout, (const double*)dhat, (const double*)q, (const double*)w1, (const double*)w2, c_q, c_w1,
-                           c_w2, (double*)wnew, inv, nx, ny, nz, 1.0 / dx);
+        hipLaunchKernelGGL((k_stage_project<double, false>), grid, block, 0, s, a, nullptr, 0);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
 
 int launch_axpby(int dtype, void* out, const void* x, double a, const void* y, double b, const void* z, double c,
                  long long n, hipStream_t s) {
+    const AxpbyArgs args{out, x, a, y, b, z, c, n};
+    const dim3 grid(ceil_div(n, 256)), block(256);
+    if (launch_recorder()) {
+        record_launch(dtype == NSLGF_F32 ? &batched_axpby<float> : &batched_axpby<double>, grid, block, args);
+        return NSLGF_OK;
+    }
     if (dtype == NSLGF_F32)
-        hipLaunchKernelGGL(k_axpby<float>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (float*)out, (const float*)x, a,
-                           (const float*)y, b, (const float*)z, c, n);
+        hipLaunchKernelGGL((k_axpby<float, false>), grid, block, 0, s, args, nullptr);
     else
-        hipLaunchKernelGGL(k_axpby<double>, dim3(ceil_div(n, 256)), dim3(256), 0, s, (double*)out, (const double*)x, a,
-                           (const double*)y, b, (const double*)z, c, n);
+        hipLaunchKernelGGL((k_axpby<double, false>), grid, block, 0, s, args, nullptr);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }
 
 int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsigned char* blocks, int nb, int nx, int ny,
                        int nz, double dx, hipStream_t s, int shape) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_curl<float>, cell_grid(nx, ny, nz, 1, shape), cell_block(shape), 0, s, (const float*)f, (float*)e, nx, ny,
                            nz, (float)(1.0 / dx), nbuf, blocks, nb);
@@ -515,6 +624,7 @@ int launch_masked_curl(int dtype, const void* f, void* e, int nbuf, const unsign
 
 int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double* dev_partial, int nblocks,
                    hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_max_abs<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, nbuf,
                            dev_partial);
@@ -527,6 +637,7 @@ int launch_max_abs(int dtype, const void* u, int nbuf, int nx, int ny, int nz, d
 
 int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int nz, double dx, const double origin[3],
                        double* dev_partial, int nblocks, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_diagnostics<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, nbuf,
                            (float)(1.0 / dx), dx, origin[0], origin[1], origin[2], dev_partial);
@@ -539,6 +650,7 @@ int launch_diagnostics(int dtype, const void* u, int nbuf, int nx, int ny, int n
 
 int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int ny, int nz, int nb, int nbuf, double dx,
                          double* dev_mu, double* dev_nu, hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     const long long nblocks = (long long)((nx + nb - 1) / nb) * ((ny + nb - 1) / nb) * ((nz + nb - 1) / nb);
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_block_weights<float>, dim3((unsigned)nblocks), dim3(256), 0, s, (const float*)u,
@@ -552,6 +664,7 @@ int launch_block_weights(int dtype, const void* u, const void* nl, int nx, int n
 
 int launch_max_speed(int dtype, const void* u, int nx, int ny, int nz, double* dev_partial, int nblocks,
                      hipStream_t s) {
+    if (recording_unsupported()) return NSLGF_OK;
     if (dtype == NSLGF_F32)
         hipLaunchKernelGGL(k_max_speed<float>, dim3(nblocks), dim3(256), 0, s, (const float*)u, nx, ny, nz, dev_partial);
     else

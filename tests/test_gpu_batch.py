@@ -21,22 +21,49 @@ def _problem(n, seed, dtype):
     return u0.to(dtype), dx, dt, re
 
 
-def test_batched_equals_unbatched_bitwise():
-    # 128^3 in FP32 and FP64 pads to 256, where the column passes use the wide and the narrow plan
+@pytest.mark.parametrize("mode", [nslgf.BATCH_PASSES, nslgf.BATCH_PER_PROBLEM])
+def test_batched_equals_unbatched_bitwise(mode):
+    """Both forms of the batch graph (batched passes over groups of like problems, or one branch per
+    problem) give the one-by-one results bit for bit over three replays.  The specs hold groups of equal
+    boxes (two 24^3 FP64 problems with the same step parameters share every launch) and singletons; 128^3
+    in FP32 and FP64 pads to 256, where the column passes use the wide and the narrow plan."""
     specs = [(24, 1, torch.float64), (32, 2, torch.float64), (20, 3, torch.float32), (28, 4, torch.float64),
-             (24, 5, torch.float32), (128, 6, torch.float32), (128, 7, torch.float64)]
+             (24, 5, torch.float32), (128, 6, torch.float32), (128, 7, torch.float64), (24, 1, torch.float64),
+             (32, 2, torch.float64)]
     probs = [_problem(*s) for s in specs]
     solo = [nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2) for (u, dx, dt, re) in probs]
     batch = [nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2) for (u, dx, dt, re) in probs]
-    for step in range(3):  # the first call captures, the next ones replay the graph
-        for st in solo:
-            st.step()
-        nslgf.herk_step_batched(batch)
-        torch.cuda.synchronize()
-        for a, b in zip(solo, batch):
-            assert torch.equal(a.u, b.u), step
-            assert torch.equal(a.d, b.d), step
-            assert a.t == b.t
+    nslgf.set_batch_mode(mode)
+    try:
+        for step in range(3):  # the first call captures, the next ones replay the graph
+            for st in solo:
+                st.step()
+            nslgf.herk_step_batched(batch)
+            torch.cuda.synchronize()
+            for a, b in zip(solo, batch):
+                assert torch.equal(a.u, b.u), step
+                assert torch.equal(a.d, b.d), step
+                assert a.t == b.t
+        groups, launches = nslgf.batch_info()
+        if mode == nslgf.BATCH_PASSES:
+            # the repeated specs share their group: 9 problems in 7 groups, and fewer launches than the
+            # per-problem form's 9 x (launches of one step)
+            assert groups == 7, groups
+        else:
+            assert groups == 0
+    finally:
+        nslgf.set_batch_mode(nslgf.BATCH_PASSES)
+
+
+def test_batched_passes_fall_back_for_the_guard():
+    """A guarded step has a kernel without a batched form: the batch is captured per problem and still
+    equals one-by-one steps."""
+    u, dx, dt, re = _problem(24, 11, torch.float64)
+    a = nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2, guard=True)
+    b = nslgf.HerkState(u.clone(), dx, dt, re, "A", n_buf=2, guard=True)
+    a.step()
+    nslgf.herk_step_batched([b])
+    assert torch.equal(a.u, b.u) and nslgf.batch_info()[0] == 0
 
 
 def test_batched_matches_oracle_and_recaptures():

@@ -189,13 +189,13 @@ def small_ring_case(n: int = 32, seed: int = 1):
     return n, dx, Ring(R=R, sigma=sig, gamma=1.0, eps=1e-4, seed=seed), 500.0, 0.5
 
 
-def batch_specs(count: int = 32, seed: int = 0):
-    """Uneven batch: per problem (n, dx, Ring, Re, CFL) with n ~ U{48..192}, R = 1,
+def batch_specs(count: int = 32, seed: int = 0, sizes=None):
+    """Uneven batch: per problem (n, dx, Ring, Re, CFL) with n ~ U{48..192} (or U(sizes)), R = 1,
     sigma/R ~ U[0.1, 0.3], dx = 2 (R + 5 sigma) / (n - 16)."""
     rng = np.random.default_rng(seed)
     out = []
     for b in range(count):
-        n = int(rng.choice(BATCH_SIZES))
+        n = int(rng.choice(BATCH_SIZES if sizes is None else tuple(sizes)))
         sr = float(rng.uniform(0.1, 0.3))
         dx = 2.0 * (1.0 + 5.0 * sr) / (n - 16)
         out.append((n, dx, Ring(R=1.0, sigma=sr, gamma=1.0, eps=1e-4, seed=1000 + b), 500.0, 0.5))
