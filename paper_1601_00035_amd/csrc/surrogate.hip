@@ -90,6 +90,122 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const bf16_t* __restrict__ X,
     }
 }
 
+// The same convolution with the input staged in LDS.  A workgroup (4 waves) owns a block of 2 (z) x 8 (y)
+// rows of 32 voxels along x and one tile of 32 output channels (the grid's x index also walks the tiles).  For every slice of 16 input channels it copies the slice's halo (4 x 10 x 34 voxels,
+// zero outside the volume) into LDS once.  Each wave owns 4 adjacent rows of one z plane: for every
+// (dz, dx) of the stencil it reads the 6 halo rows those 4 rows need into registers and applies them for
+// the three dy taps, so that an A operand read from LDS serves up to three taps, and a B operand (weights,
+// read through the caches) serves the wave's 4 rows.  Needs W % 32 == 0, H % 8 == 0, D % 2 == 0.  The sum
+// runs over slices, then dz, dx, dy in a fixed order: results are deterministic.
+constexpr int kLdsBZ = 2, kLdsBY = 8, kLdsHX = 34, kLdsRows = 4;
+constexpr int kLdsHalo = (kLdsBZ + 2) * (kLdsBY + 2) * kLdsHX;  // voxels of the halo block
+template <bool RELU, int SIGN>
+__global__ void __launch_bounds__(256) k_conv_lds(const bf16_t* __restrict__ X, const bf16_t* __restrict__ Wn,
+                                                  float* __restrict__ Y, int D, int H, int W, int K, int N) {
+    __shared__ uint4 halo[kLdsHalo * 2];  // [voxel][16 channels] as two 16-byte halves
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int m = lane % 32, half = lane / 32;
+    const int xt = W / 32;
+    const int x0 = (blockIdx.x % xt) * 32, nb = (blockIdx.x / xt) * 32;
+    const int y0 = blockIdx.y * kLdsBY, z0 = blockIdx.z * kLdsBZ;
+    // this wave's rows: z = z0 + wave / 2, y = y0 + 4 (wave % 2) + r, r < 4
+    const int tz = wave / 2, ty = kLdsRows * (wave % 2);
+    f32x16 acc[kLdsRows][1];
+#pragma unroll
+    for (int r = 0; r < kLdsRows; ++r)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[r][0][i] = 0.f;
+    // this thread's halo elements (the same in every slice): offsets from the block's first voxel, in
+    // BF16 elements (the host keeps 4 H W K below 2^31), and whether each lies inside the volume
+    constexpr int kPer = (kLdsHalo * 2 + 255) / 256, kFirst = kPer / 2;
+    const bf16_t* xblk = X + (((long long)z0 * H + y0) * W + x0) * K;
+    int hoff[kPer];
+    unsigned hok = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int q = tid + 256 * i;
+        const int hv = q / 2, hh = q % 2;
+        const int hx = hv % kLdsHX, hy = (hv / kLdsHX) % (kLdsBY + 2), hz = hv / (kLdsHX * (kLdsBY + 2));
+        const int xx = x0 + hx - 1, yy = y0 + hy - 1, zz = z0 + hz - 1;
+        hoff[i] = (((hz - 1) * H + (hy - 1)) * W + (hx - 1)) * K + hh * 8;
+        if (q < kLdsHalo * 2 && xx >= 0 && xx < W && yy >= 0 && yy < H && zz >= 0 && zz < D) hok |= 1u << i;
+    }
+    for (int kc = 0; kc < K; kc += 16) {
+        // the slice's halo in two batches of loads, each issued whole before its LDS writes
+        uint4 hr[kFirst];
+#pragma unroll
+        for (int i = 0; i < kFirst; ++i)
+            hr[i] = (hok >> i) & 1 ? *(const uint4*)(xblk + kc + hoff[i]) : make_uint4(0, 0, 0, 0);
+        __syncthreads();  // (the previous slice's reads are done)
+#pragma unroll
+        for (int i = 0; i < kFirst; ++i) halo[tid + 256 * i] = hr[i];
+        uint4 hr2[kPer - kFirst];
+#pragma unroll
+        for (int i = kFirst; i < kPer; ++i)
+            hr2[i - kFirst] = (hok >> i) & 1 ? *(const uint4*)(xblk + kc + hoff[i]) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = kFirst; i < kPer; ++i)
+            if (tid + 256 * i < kLdsHalo * 2) halo[tid + 256 * i] = hr2[i - kFirst];
+        __syncthreads();
+        // the weights of the next (dz, dx) are loaded while the current ones multiply
+        const bf16_t* wbase = Wn + ((long long)nb + m) * K + kc + half * 8;
+        auto load_b = [&](int it, bf16x8* b) {
+            const int tdz = it / 3 - 1, tdx = it % 3 - 1;
+#pragma unroll
+            for (int tdy = -1; tdy <= 1; ++tdy) {
+                const int tap = (tdz + 1) * 9 + (tdy + 1) * 3 + (tdx + 1);
+                b[tdy + 1] = load8(wbase + (long long)tap * N * K);
+            }
+        };
+        bf16x8 bcur[3], bnext[3];
+        load_b(0, bcur);
+#pragma unroll 1
+        for (int it = 0; it < 9; ++it) {
+            if (it + 1 < 9) load_b(it + 1, bnext);
+            const int tdz = it / 3 - 1, tdx = it % 3 - 1;
+            // halo rows ty .. ty + 5 hold the input rows y0 + ty - 1 .. y0 + ty + 4 of plane z + SIGN dz
+            const int hb = ((tz + 1 + SIGN * tdz) * (kLdsBY + 2) + ty) * kLdsHX + (m + 1 + SIGN * tdx);
+            bf16x8 a[kLdsRows + 2];
+#pragma unroll
+            for (int j = 0; j < kLdsRows + 2; ++j) a[j] = __builtin_bit_cast(bf16x8, halo[(hb + j * kLdsHX) * 2 + half]);
+#pragma unroll
+            for (int tdy = -1; tdy <= 1; ++tdy)
+#pragma unroll
+                for (int r = 0; r < kLdsRows; ++r)
+                    acc[r][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[r + SIGN * tdy + 1], bcur[tdy + 1], acc[r][0], 0, 0, 0);
+            if (it + 1 < 9) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) bcur[j] = bnext[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kLdsRows; ++r) {
+        const long long vrow = ((long long)(z0 + tz) * H + (y0 + ty + r)) * W + x0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = 8 * (i / 4) + 4 * half + (i % 4);
+            float val = acc[r][0][i];
+            if (RELU) val = fmaxf(val, 0.f);
+            Y[(vrow + row) * N + nb + m] = val;
+        }
+    }
+}
+
+// Whether the LDS-staged convolution serves a volume and channel count.
+static bool conv_lds_ok(int D, int H, int W, int K, int N) {
+    return W % 32 == 0 && H % kLdsBY == 0 && D % kLdsBZ == 0 && N % 32 == 0 && N <= 1024 &&
+           4LL * H * W * K < (1LL << 31);
+}
+template <bool RELU, int SIGN>
+static void launch_conv_lds(const bf16_t* x, const bf16_t* w, float* y, int D, int H, int W, int K, int N,
+                            hipStream_t s) {
+    // one output tile per workgroup: more workgroups on the small volumes, and more tiles would hold
+    // 64 more accumulator registers per lane and tile
+    const dim3 grid((unsigned)(W / 32 * (N / 32)), H / kLdsBY, D / kLdsBZ);
+    hipLaunchKernelGGL((k_conv_lds<RELU, SIGN>), grid, dim3(256), 0, s, x, w, y, D, H, W, K, N);
+}
+
 // Partial weight gradient of one voxel chunk: P[chunk][tap][co][ci] = sum_{v in chunk} dY[v][co] X[v+off][ci]
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ dY, const bf16_t* __restrict__ X,
                                                     float* __restrict__ P, int D, int H, int W, int cin, int cout,
@@ -475,7 +591,12 @@ int sur_conv3d_fwd(nslgf_t h, const void* x, const void* w, void* y, int D, int 
     NSLGF_CHECK_ARG(x && w && y, "sur_conv3d_fwd: null pointer");
     const long long waves = (long long)D * H * W / 32 * (cout / 32);
     hipStream_t s = (hipStream_t)stream;
-    if (relu)
+    if (conv_lds_ok(D, H, W, cin, cout)) {
+        if (relu)
+            launch_conv_lds<true, 1>((const bf16_t*)x, (const bf16_t*)w, (float*)y, D, H, W, cin, cout, s);
+        else
+            launch_conv_lds<false, 1>((const bf16_t*)x, (const bf16_t*)w, (float*)y, D, H, W, cin, cout, s);
+    } else if (relu)
         hipLaunchKernelGGL((k_conv_mfma<true, 1>), dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)x,
                            (const bf16_t*)w, (float*)y, D, H, W, cin, cout);
     else
@@ -493,8 +614,12 @@ int sur_conv3d_bwd_data(nslgf_t h, const void* dy, const void* wt, void* dx, int
     NSLGF_CHECK_ARG(dy && wt && dx, "sur_conv3d_bwd_data: null pointer");
     // GEMM with K = cout (inner) and N = cin (outputs), gathering dy at v - off
     const long long waves = (long long)D * H * W / 32 * (cin / 32);
-    hipLaunchKernelGGL((k_conv_mfma<false, -1>), dim3(ceil_div(waves, 4)), dim3(256), 0, (hipStream_t)stream,
-                       (const bf16_t*)dy, (const bf16_t*)wt, (float*)dx, D, H, W, cout, cin);
+    if (conv_lds_ok(D, H, W, cout, cin))
+        launch_conv_lds<false, -1>((const bf16_t*)dy, (const bf16_t*)wt, (float*)dx, D, H, W, cout, cin,
+                                   (hipStream_t)stream);
+    else
+        hipLaunchKernelGGL((k_conv_mfma<false, -1>), dim3(ceil_div(waves, 4)), dim3(256), 0, (hipStream_t)stream,
+                           (const bf16_t*)dy, (const bf16_t*)wt, (float*)dx, D, H, W, cout, cin);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

@@ -35,8 +35,12 @@ def test_mfma_operand_layout():
     assert rel(got, A @ B) < 1e-6
 
 
+# W % 32 == 0, H % 8 == 0 and D % 2 == 0 take the LDS-staged kernels (halo blocks of 2 x 8 rows of 32
+# voxels; several blocks per axis, and volume faces on every side); the other shapes the gathering ones
 @pytest.mark.parametrize("dims,cin,cout", [((8, 8, 8), 32, 64), ((4, 8, 12), 16, 32), ((8, 4, 4), 96, 128),
-                                           ((4, 6, 16), 16, 32), ((2, 4, 24), 96, 128)])
+                                           ((4, 6, 16), 16, 32), ((2, 4, 24), 96, 128), ((2, 4, 32), 16, 32),
+                                           ((4, 16, 64), 32, 64), ((2, 8, 32), 16, 32), ((6, 16, 32), 96, 128),
+                                           ((2, 8, 96), 64, 96), ((4, 8, 32), 128, 32)])
 def test_conv_layers(dims, cin, cout):
     D, H, W = dims
     x = rand_bf16((D, H, W, cin), 3)
