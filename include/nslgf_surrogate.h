@@ -59,6 +59,15 @@ int sur_adam(nslgf_t h, void *w, void *w_bf16, const void *g, void *m, void *v, 
  * channels 0..2 = omega * scale, channel 3 = feat, the rest 0. */
 int sur_pack_input(nslgf_t h, const void *omega_f64, void *x_bf16, int D, int H, int W, double scale, double feat,
                    void *stream);
+/* Input of the correction form, whose network refines the linear extrapolation of one plain step:
+ * channels 0..2 = omega * scale, channel 3 = feat, channels 4..6 = delta * dscale (delta: planar FP64
+ * [3][D][H][W], the change of the vorticity over one plain step), the rest 0. */
+int sur_pack_input_pair(nslgf_t h, const void *omega_f64, const void *delta_f64, void *x_bf16, int D, int H, int W,
+                        double scale, double dscale, double feat, void *stream);
+/* out[i] = ca a[i] + cb b[i] + cc c[i] for i < n (FP64; c may be NULL, then the last term is left out).
+ * Forms the extrapolation w_k + h (w_{k+1} - w_k), the one-step change and the correction targets. */
+int sur_combine3(nslgf_t h, const void *a_f64, const void *b_f64, const void *c_f64, void *out_f64, long long n,
+                 double ca, double cb, double cc, void *stream);
 /* Pack a planar FP64 target field [3][D][H][W] times scale into [voxel][3] FP32. */
 int sur_pack_target(nslgf_t h, const void *f_f64, void *t_f32, int D, int H, int W, double scale, void *stream);
 /* Unpack: out[q][v] = base[q][v] + y[v][q] / scale for q < 3 (planar FP64). */

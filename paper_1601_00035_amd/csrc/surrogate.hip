@@ -517,6 +517,32 @@ __global__ void k_pack_input(const double* __restrict__ om, bf16_t* __restrict__
     dst[0] = __builtin_bit_cast(uint4, pack8(out));
     dst[1] = __builtin_bit_cast(uint4, pack8(out + 8));
 }
+// Input of the correction form: channels 0..2 = omega * scale, 3 = feat, 4..6 = delta * dscale.
+__global__ void k_pack_input_pair(const double* __restrict__ om, const double* __restrict__ dl, bf16_t* __restrict__ x,
+                                  long long nvox, double scale, double dscale, double feat) {
+    const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    bf16_t out[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) out[k] = 0;
+    for (int q = 0; q < 3; ++q) {
+        out[q] = f2bf((float)(om[q * nvox + v] * scale));
+        out[4 + q] = f2bf((float)(dl[q * nvox + v] * dscale));
+    }
+    out[3] = f2bf((float)feat);
+    uint4* dst = (uint4*)(x + v * 16);
+    dst[0] = __builtin_bit_cast(uint4, pack8(out));
+    dst[1] = __builtin_bit_cast(uint4, pack8(out + 8));
+}
+// out = ca a + cb b + cc c (c may be null), FP64, n values.
+__global__ void k_combine3(const double* __restrict__ a, const double* __restrict__ b, const double* __restrict__ c,
+                           double* __restrict__ out, long long n, double ca, double cb, double cc) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double r = ca * a[i] + cb * b[i];
+    if (c) r += cc * c[i];
+    out[i] = r;
+}
 __global__ void k_pack_target(const double* __restrict__ f, float* __restrict__ t, long long nvox, double scale) {
     const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvox) return;
@@ -781,6 +807,25 @@ int sur_pack_input(nslgf_t h, const void* om, void* x, int D, int H, int W, doub
     const long long nvox = (long long)D * H * W;
     hipLaunchKernelGGL(k_pack_input, dim3(grid1(nvox)), dim3(256), 0, (hipStream_t)stream, (const double*)om,
                        (bf16_t*)x, nvox, scale, feat);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_pack_input_pair(nslgf_t h, const void* om, const void* delta, void* x, int D, int H, int W, double scale,
+                        double dscale, double feat, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(om && delta && x && D > 0 && H > 0 && W > 0, "sur_pack_input_pair: bad arguments");
+    const long long nvox = (long long)D * H * W;
+    hipLaunchKernelGGL(k_pack_input_pair, dim3(grid1(nvox)), dim3(256), 0, (hipStream_t)stream, (const double*)om,
+                       (const double*)delta, (bf16_t*)x, nvox, scale, dscale, feat);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+int sur_combine3(nslgf_t h, const void* a, const void* b, const void* c, void* out, long long n, double ca, double cb,
+                 double cc, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(a && b && out && n > 0, "sur_combine3: bad arguments");
+    hipLaunchKernelGGL(k_combine3, dim3(grid1(n)), dim3(256), 0, (hipStream_t)stream, (const double*)a,
+                       (const double*)b, (const double*)c, (double*)out, n, ca, cb, cc);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

@@ -53,6 +53,8 @@ def _bind():
         "sur_mse": [vp, vp, vp, vp, vp, ll, i, i, vp],
         "sur_adam": [vp, vp, vp, vp, vp, vp, ll, f, f, f, f, i, vp],
         "sur_pack_input": [vp, vp, vp, i, i, i, d, d, vp],
+        "sur_pack_input_pair": [vp, vp, vp, vp, i, i, i, d, d, d, vp],
+        "sur_combine3": [vp, vp, vp, vp, vp, ll, d, d, d, vp],
         "sur_pack_target": [vp, vp, vp, i, i, i, d, vp],
         "sur_unpack_update": [vp, vp, vp, vp, i, i, i, i, d, vp],
         "sur_mfma_selftest": [vp, vp, vp, vp, vp],
@@ -91,16 +93,16 @@ def mfma_selftest(a_bf16: torch.Tensor, b_bf16: torch.Tensor) -> torch.Tensor:
 class UNet:
     """Weights, optimiser state and activation buffers of the surrogate network."""
 
-    def __init__(self, device="cuda:0", seed: int = 0, out_scale: float = 0.1):
+    def __init__(self, device="cuda:0", seed: int = 0, out_scale: float = 0.1, in_real: int = 4):
         self.device = torch.device(device)
         g = torch.Generator().manual_seed(seed)
         self.w, self.wb, self.wt, self.gw, self.m, self.v = [], [], [], [], [], []
         for li, (ci, co) in enumerate(LAYERS):
-            fan_in = 27 * (4 if li == 0 else ci)
+            fan_in = 27 * (in_real if li == 0 else ci)
             std = math.sqrt(2.0 / fan_in) * (out_scale if li == len(LAYERS) - 1 else 1.0)
             w = torch.randn((27, co, ci), generator=g) * std
             if li == 0:
-                w[:, :, 4:] = 0.0  # only 4 real input channels
+                w[:, :, in_real:] = 0.0  # only the real input channels (4, or 7 in the correction form)
             w = w.to(self.device, torch.float32).contiguous()
             self.w.append(w)
             wb = bf16_empty(w.numel(), self.device)
@@ -290,6 +292,23 @@ def pack_input(omega: torch.Tensor, scale: float, re: float, out: torch.Tensor |
     return out
 
 
+def pack_input_pair(omega: torch.Tensor, delta: torch.Tensor, scale: float, dscale: float, re: float,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """Input of the correction form: omega * scale, the Re feature, delta * dscale (planar FP64 fields)."""
+    R = omega.shape[-1]
+    if out is None:
+        out = bf16_empty(R ** 3 * IN_CH, omega.device)
+    call("sur_pack_input_pair", omega, delta, out, R, R, R, float(scale), float(dscale), float(re_feature(re)))
+    return out
+
+
+def combine3(a: torch.Tensor, b: torch.Tensor, c, ca: float, cb: float, cc: float = 0.0) -> torch.Tensor:
+    """ca a + cb b (+ cc c) of FP64 fields, on the GPU."""
+    out = torch.empty_like(a)
+    call("sur_combine3", a, b, c, out, a.numel(), float(ca), float(cb), float(cc))
+    return out
+
+
 def pack_target(delta: torch.Tensor, scale: float, out: torch.Tensor | None = None) -> torch.Tensor:
     R = delta.shape[-1]
     if out is None:
@@ -333,9 +352,12 @@ def make_trajectory(n: int, dx: float, sigma: float, re: float, seed: int, steps
 
 
 def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float = 1e-3, gain: float = 5.0,
-          seed: int = 0, log_every: int = 0):
-    """Adam on random (w_k, w_{k+horizon}) pairs: input w_k * s, target (w_{k+h} - w_k) * s * gain with
-    s = 1 / max|w_0| of the trajectory.  trajs[i]: snapshots [T][3][n][n][n]; res[i]: Re."""
+          seed: int = 0, log_every: int = 0, mode: str = "persist", dgain: float = 10.0):
+    """Adam on random (w_k, w_{k+horizon}) pairs, s = 1 / max|w_0| of the trajectory.
+    mode "persist": input w_k s, target (w_{k+h} - w_k) s gain.
+    mode "correct": input w_k s and the one-step change (w_{k+1} - w_k) s dgain, target the error of the
+    linear extrapolation, (w_{k+h} - w_k - h (w_{k+1} - w_k)) s gain.
+    trajs[i]: snapshots [T][3][n][n][n]; res[i]: Re."""
     g = torch.Generator().manual_seed(seed)
     R = trajs[0].shape[-1]
     nvox = R ** 3
@@ -348,8 +370,14 @@ def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float
         T = trajs[i].shape[0]
         k = int(torch.randint(T - horizon, (1,), generator=g))
         w_k = trajs[i][k].double()
-        pack_input(w_k, scales[i], res[i], out=xb)
-        pack_target(trajs[i][k + horizon].double() - w_k, scales[i] * gain, out=tg)
+        w_h = trajs[i][k + horizon].double()
+        if mode == "correct":
+            w_1 = trajs[i][k + 1].double()
+            pack_input_pair(w_k, combine3(w_1, w_k, None, 1.0, -1.0), scales[i], scales[i] * dgain, res[i], out=xb)
+            pack_target(combine3(w_h, w_k, w_1, 1.0, horizon - 1.0, -float(horizon)), scales[i] * gain, out=tg)
+        else:
+            pack_input(w_k, scales[i], res[i], out=xb)
+            pack_target(combine3(w_h, w_k, None, 1.0, -1.0), scales[i] * gain, out=tg)
         y = net.forward(xb, R)
         part, grad = net.loss_and_grad(y, tg, nvox)
         net.backward(grad)
@@ -367,11 +395,24 @@ def propose(net: UNet, w_k: torch.Tensor, scale: float, re: float, gain: float =
     return unpack_update(w_k.double(), y, scale * gain)
 
 
+def propose_correct(net: UNet, w_k: torch.Tensor, w_1: torch.Tensor, scale: float, re: float, horizon: int,
+                    gain: float, dgain: float) -> torch.Tensor:
+    """The correction form's proposal: the extrapolation w_k + h (w_1 - w_k) plus net(w_k, w_1 - w_k) /
+    (scale gain), FP64 planar."""
+    R = w_k.shape[-1]
+    w_k, w_1 = w_k.double(), w_1.double()
+    xb = pack_input_pair(w_k, combine3(w_1, w_k, None, 1.0, -1.0), scale, scale * dgain, re)
+    y = net.forward(xb, R)
+    return unpack_update(combine3(w_k, w_1, None, 1.0 - horizon, float(horizon)), y, scale * gain)
+
+
 def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: int, blocks: int, horizon: int = 4,
-                   tol: float = 1e-3, cfl: float = 0.5, n_buf: int = 8, gain: float = 5.0):
+                   tol: float = 1e-3, cfl: float = 0.5, n_buf: int = 8, gain: float = 5.0, mode: str = "persist",
+                   dgain: float = 10.0):
     """Every `horizon` steps the surrogate proposes w_{k+h}; the plain FP64 step judges it from the
     same state (rel. max error of the vorticity) and the roll-out continues from the proposal if the
-    error is within tol (velocity rebuilt by Vor2Vel), else from the plain result.  Returns per-block
+    error is within tol (velocity rebuilt by Vor2Vel), else from the plain result.  In mode "correct"
+    the proposal also takes the first plain step (whose cost it then includes).  Returns per-block
     errors, two baselines (persistence w_{k+h} ~ w_k, and linear extrapolation of the first plain step
     w_{k+h} ~ w_k + h (w_{k+1} - w_k)) and timings."""
     import workloads
@@ -389,14 +430,24 @@ def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: 
         w_k = vorticity(u, dx)
         e0, e1, e2, e3, e4 = (torch.cuda.Event(enable_timing=True) for _ in range(5))
         e0.record()
-        prop = propose(net, w_k, scale, re, gain)
-        u_prop = vor2vel(prop, dx)
-        e1.record()
-        st = HerkState(u.clone(), dx, dt, re, "A", n_buf=n_buf)
-        st.step()
-        e2.record()
-        w_1 = vorticity(st.u, dx)
-        e3.record()
+        if mode == "correct":
+            st = HerkState(u.clone(), dx, dt, re, "A", n_buf=n_buf)
+            st.step()
+            e1.record()
+            w_1 = vorticity(st.u, dx)
+            prop = propose_correct(net, w_k, w_1, scale, re, horizon, gain, dgain)
+            u_prop = vor2vel(prop, dx)
+            e2.record()
+            e3.record()
+        else:
+            prop = propose(net, w_k, scale, re, gain)
+            u_prop = vor2vel(prop, dx)
+            e1.record()
+            st = HerkState(u.clone(), dx, dt, re, "A", n_buf=n_buf)
+            st.step()
+            e2.record()
+            w_1 = vorticity(st.u, dx)
+            e3.record()
         for _ in range(horizon - 1):
             st.step()
         e4.record()
@@ -411,7 +462,11 @@ def judged_rollout(net: UNet, n: int, dx: float, sigma: float, re: float, seed: 
         out["persistence_err"].append(perr)
         out["extrapolation_err"].append(xerr)
         out["accepted"].append(ok)
-        out["ms_surrogate"].append(e0.elapsed_time(e1))
-        out["ms_plain"].append(e1.elapsed_time(e2) + e3.elapsed_time(e4))
+        if mode == "correct":
+            out["ms_surrogate"].append(e0.elapsed_time(e2))
+            out["ms_plain"].append(e0.elapsed_time(e1) + e3.elapsed_time(e4))
+        else:
+            out["ms_surrogate"].append(e0.elapsed_time(e1))
+            out["ms_plain"].append(e1.elapsed_time(e2) + e3.elapsed_time(e4))
         u = u_prop if ok else st.u
     return out

@@ -171,3 +171,60 @@ def test_judged_rollout_small():
     assert np.mean(ro["err"]) < np.mean(ro["persistence_err"]), (ro["err"], ro["persistence_err"])
     ro_all = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, blocks=1, horizon=4, tol=1e9, n_buf=2)
     assert all(ro_all["accepted"])
+
+
+def test_correction_form_packing():
+    """The correction form's input packing and the FP64 combination kernel against their definitions."""
+    R = 8
+    rng = np.random.default_rng(8)
+    om = torch.from_numpy(rng.standard_normal((3, R, R, R))).to(DEV)
+    dl = torch.from_numpy(rng.standard_normal((3, R, R, R)) * 0.1).to(DEV)
+    x = S.pack_input_pair(om, dl, 0.7, 9.0, 250.0)
+    got = x.view(torch.int16).cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    got = got.view(np.float32).reshape(R ** 3, 16).astype(np.float64)
+    o, d = om.cpu().numpy().reshape(3, -1).T, dl.cpu().numpy().reshape(3, -1).T
+    ref = np.zeros((R ** 3, 16))
+    ref[:, 0:3] = C.bf16_round((o * 0.7).astype(np.float32))
+    ref[:, 3] = C.bf16_round(np.float32(S.re_feature(250.0)))
+    ref[:, 4:7] = C.bf16_round((d * 9.0).astype(np.float32))
+    assert np.array_equal(got, ref)
+    # (the kernel may fuse a product into the sum: agreement to FP64 rounding, exact for unit weights)
+    c = torch.from_numpy(rng.standard_normal((3, R, R, R))).to(DEV)
+    out = S.combine3(om, dl, c, 1.0, 3.0, -4.0)
+    ref = 1.0 * om + 3.0 * dl + (-4.0) * c
+    assert float((out - ref).abs().max()) <= 4e-16 * float(ref.abs().max())
+    out = S.combine3(om, dl, None, -3.0, 4.0)
+    ref = -3.0 * om + 4.0 * dl
+    assert float((out - ref).abs().max()) <= 4e-16 * float(ref.abs().max())
+    assert torch.equal(S.combine3(om, dl, None, 1.0, -1.0), om - dl)
+
+
+def test_correction_form_rollout_small():
+    """The correction form end to end at 32^3: it trains, its proposal starts from the extrapolation of
+    one plain step (an untrained network's output scale keeps it near that extrapolation), and the
+    judge's fallback works as in the persistence form."""
+    import workloads
+
+    n = 32
+    specs = workloads.surrogate_specs(4, seed=3)
+    dx_of = lambda s: 2.0 * (1.0 + 5.0 * s) / (n - 16)
+    trajs, res = [], []
+    for (sig, re, seed) in specs[:3]:
+        snaps, _ = S.make_trajectory(n, dx_of(sig), sig, re, seed, 16, n_buf=2)
+        trajs.append(snaps)
+        res.append(re)
+    net = S.UNet(DEV, seed=0, in_real=7)
+    sig, re, seed = specs[3]
+    ro0 = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, blocks=2, horizon=4, tol=0.0, n_buf=2, gain=30.0,
+                           mode="correct")
+    # untrained: the output layer's small initial scale leaves the proposal close to the extrapolation
+    assert all(abs(e - x) < 0.5 * x for e, x in zip(ro0["err"], ro0["extrapolation_err"])), ro0
+    losses = S.train(net, trajs, res, 4, 300, lr=1e-3, log_every=50, mode="correct", gain=30.0)
+    assert losses[-1][1] < losses[0][1]
+    ro = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, blocks=3, horizon=4, tol=0.0, n_buf=2, gain=30.0,
+                          mode="correct")
+    assert not any(ro["accepted"]) and np.isfinite(ro["err"]).all()
+    assert np.mean(ro["err"]) < np.mean(ro["persistence_err"]), (ro["err"], ro["persistence_err"])
+    ro_all = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, blocks=1, horizon=4, tol=1e9, n_buf=2, gain=30.0,
+                              mode="correct")
+    assert all(ro_all["accepted"])

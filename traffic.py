@@ -144,16 +144,110 @@ def trace_summary(run_dir: str, last: int) -> str:
     return "\n".join(out)
 
 
+def surrogate_summary(run_dir: str, n: int, iters: int) -> str:
+    """Markdown per-layer summary of the surrogate's convolutions from a rocprofv3 --kernel-trace of
+    `python -m paper_1601_00035_amd.surrogate_run --time-iters K --n n`: the last `iters` training
+    iterations, each layer's forward, data-gradient and weight-gradient launches (the weight gradient
+    with its layout copies and chunk sums), against the layer's roofline max(FLOP / 2.5 PFLOP/s BF16
+    dense, algorithmic bytes / 8 TB/s)."""
+    from paper_1601_00035_amd.surrogate import LAYERS, LEVEL
+
+    dbs = glob.glob(os.path.join(run_dir, "**", "*_results.db"), recursive=True)
+    if not dbs:
+        raise SystemExit(f"no *_results.db under {run_dir}")
+    rows = []
+    for f in dbs:
+        con = sqlite3.connect(f)
+        rows += con.execute("select name, duration from kernels order by dispatch_id").fetchall()
+        con.close()
+
+    def kind(name):
+        short = name.split("(")[0]
+        if "k_conv_lds<" in short or "k_conv_mfma<" in short:
+            return "dgrad" if short.rstrip(">").endswith("-1") else "fwd"
+        if "k_conv_wgrad" in short:
+            return "wgrad"
+        if "k_to_blocked8" in short:
+            return "pre"
+        if "k_sum_chunk" in short:
+            return "post"
+        return None
+
+    # training iterations: 10 forward convolutions, then the weight gradients 9 .. 0 and data gradients
+    # 9 .. 1 interleaved; walk the dispatches, attributing the layout copies to the next weight gradient
+    # and the chunk sums to the previous one
+    seq, pre = [], 0.0
+    for name, dur in rows:
+        k = kind(name)
+        if k in ("fwd", "dgrad"):
+            seq.append([k, float(dur)])
+        elif k == "pre":
+            pre += float(dur)
+        elif k == "wgrad":
+            seq.append(["wgrad", float(dur) + pre])
+            pre = 0.0
+        elif k == "post" and seq and seq[-1][0] == "wgrad":
+            seq[-1][1] += float(dur)
+    per_iter = 10 + 9 + 10
+    seq = seq[-iters * per_iter:]
+    if len(seq) < iters * per_iter:
+        raise SystemExit("fewer convolution launches than the iterations need")
+    order = [("fwd", li) for li in range(10)]
+    for li in range(9, -1, -1):
+        order.append(("wgrad", li))
+        if li >= 1:
+            order.append(("dgrad", li))
+    times = collections.defaultdict(list)
+    for i in range(iters):
+        chunk = seq[i * per_iter:(i + 1) * per_iter]
+        for (k, li), (k2, d) in zip(order, chunk):
+            if k != k2:
+                raise SystemExit(f"launch order differs from a training iteration: {k} vs {k2}")
+            times[(k, li)].append(d)
+    out = ["| layer | grid | cin -> cout | op | avg us | TFLOP/s | GB/s | roofline us (bound) | frac |",
+           "|---:|---:|---|---|---:|---:|---:|---:|---:|"]
+    total = 0.0
+    for li, (ci, co) in enumerate(LAYERS):
+        r = n >> LEVEL[li]
+        nv = r ** 3
+        flop = 2.0 * nv * 27 * ci * co
+        for k in ("fwd", "dgrad", "wgrad"):
+            if (k, li) not in times:
+                continue
+            t = sum(times[(k, li)]) / len(times[(k, li)]) / 1e3  # us
+            total += t
+            if k == "fwd":
+                byt = nv * ci * 2 + nv * co * 4 + 27 * ci * co * 2
+            elif k == "dgrad":
+                byt = nv * co * 2 + nv * ci * 4 + 27 * ci * co * 2
+            else:
+                byt = nv * (ci + co) * 2 + 27 * ci * co * 4
+            tm, tb = flop / 2.5e15 * 1e6, byt / 8e12 * 1e6
+            roof = max(tm, tb)
+            out.append(f"| {li} | {r}^3 | {ci} -> {co} | {k} | {t:.1f} | {flop / t / 1e6:.0f} | {byt / t / 1e3:.0f} | "
+                       f"{roof:.1f} ({'mfma' if tm >= tb else 'hbm'}) | {roof / t:.2f} |")
+    out.append("")
+    out.append(f"Convolutions: {total / 1e3:.3f} ms of each training iteration (average of the last {iters}).")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--trace", help="rocprofv3 --kernel-trace output folder: print the time summary instead")
+    ap.add_argument("--surrogate-trace", help="rocprofv3 --kernel-trace folder of surrogate_run --time-iters: "
+                                              "print the per-layer summary")
+    ap.add_argument("--n", type=int, default=128, help="grid of the surrogate run")
+    ap.add_argument("--iters", type=int, default=3, help="timed iterations of the surrogate run")
     ap.add_argument("--last", type=int, default=12, help="launches of the dominant kernel in the timed steps")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "traffic.json"))
     a = ap.parse_args()
     if a.trace:
         print(trace_summary(a.trace, a.last))
+        return
+    if a.surrogate_trace:
+        print(surrogate_summary(a.surrogate_trace, a.n, a.iters))
         return
     if not (a.fetch and a.write):
         ap.error("--fetch and --write are required without --trace")
