@@ -44,13 +44,13 @@ NSLGF_FFT_PLAN(32, 8, 4, 8)
 NSLGF_FFT_PLAN(48, 12, 3, 4, 4)
 NSLGF_FFT_PLAN(64, 8, 8, 8)
 NSLGF_FFT_PLAN(80, 20, 5, 4, 4)
-NSLGF_FFT_PLAN(96, 24, 3, 4, 8)
+NSLGF_FFT_PLAN(96, 12, 4, 3, 4, 2)
 NSLGF_FFT_PLAN(128, 8, 2, 8, 8)
 NSLGF_FFT_PLAN(160, 20, 5, 2, 4, 4)
-NSLGF_FFT_PLAN(192, 24, 3, 8, 8)
+NSLGF_FFT_PLAN(192, 12, 4, 3, 4, 4)
 NSLGF_FFT_PLAN(256, 8, 4, 8, 8)
 NSLGF_FFT_PLAN(320, 20, 5, 4, 4, 4)
-NSLGF_FFT_PLAN(384, 24, 3, 2, 8, 8)
+NSLGF_FFT_PLAN(384, 12, 4, 3, 4, 4, 2)
 NSLGF_FFT_PLAN(512, 16, 8, 8, 8)
 #undef NSLGF_FFT_PLAN
 
@@ -93,8 +93,7 @@ __host__ __device__ constexpr int col_tb(int tp) {
     const int base = (int)(128 / (2 * sizeof(T)));
     return (tp * base >= 64) ? base : 64 / tp;
 }
-// Rows per workgroup of the contiguous-row kernels.
-__host__ __device__ constexpr int row_rpw(int tp) { return tp >= 256 ? 1 : 256 / tp; }
+
 
 // ---- length-R DFTs on registers -------------------------------------------------------------
 template <typename T, int R, bool INV> struct DFT;
@@ -385,6 +384,16 @@ struct RowAcc {
 };
 template <typename T, int L> __host__ __device__ constexpr int row_lds_len() {
     return L + 1 + ((L + 1) >> row_pad_shift<T>()) + 1;
+}
+// Rows per workgroup of the contiguous-row kernels of half length LH: up to 256 threads, and at most
+// about 40 KB of LDS (row tiles and the half-length twiddle table), so that at least three workgroups
+// share a CU (plans with many elements per thread, the radix-3 and radix-5 lengths, have few threads
+// per row and would otherwise hold 90-110 KB).  A power of two.
+template <typename T, int LH> __host__ __device__ constexpr int row_rpw() {
+    constexpr int tp = LH / Plan1D<LH>::E;
+    int r = tp >= 256 ? 1 : 256 / tp;
+    while (r > 1 && (r * row_lds_len<T, LH>() + LH) * (int)sizeof(cplx<T>) > 40 * 1024) r /= 2;
+    return r;
 }
 
 }  // namespace nslgf

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) k_row_r2c(RowPass a0, const RowPass* __re
     RowPass a = a0;
     if (da) a = da[blockIdx.z];
     using P = Plan1D<LH>;
-    constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
+    constexpr int E = P::E, TP = LH / E, RPW = row_rpw<T, LH>();
     using RL = typename P::Fwd;
     constexpr int LD = row_lds_len<T, LH>();
     __shared__ cplx<T> lds[RPW * LD];
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_row_c2r(RowPass a0, const RowPass* __re
     RowPass a = a0;
     if (da) a = da[blockIdx.z];
     using P = Plan1D<LH>;
-    constexpr int E = P::E, TP = LH / E, RPW = row_rpw(TP);
+    constexpr int E = P::E, TP = LH / E, RPW = row_rpw<T, LH>();
     using RL = Reverse<typename P::Fwd>;
     constexpr int LD = row_lds_len<T, LH>();
     __shared__ cplx<T> lds[RPW * LD];
@@ -414,7 +414,7 @@ template <typename T> static bool real_pairs(const void* p, long long row, long 
     return ((uintptr_t)p % (2 * sizeof(T))) == 0 && row % 2 == 0 && comp % 2 == 0 && n_io % 2 == 0;
 }
 template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s) {
-    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
+    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw<T, LH>();
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
     if (a.div_src) {
         if (a.ncomp != 1 || a.nrows != (long long)a.div_ny * a.div_nz) {
@@ -427,7 +427,7 @@ template <typename T, int LH> static int do_r2c(const RowPass& a, hipStream_t s)
     return issue_r2c<T, LH, false, false>(a, grid, dim3(RPW * TP), s);
 }
 template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s) {
-    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw(TP);
+    constexpr int TP = LH / Plan1D<LH>::E, RPW = row_rpw<T, LH>();
     dim3 grid(ceil_div(a.nrows, RPW), a.ncomp);
     const bool pairs = real_pairs<T>(a.out, a.out_row, a.out_comp, a.n_io);
     if (launch_recorder()) {
