@@ -359,6 +359,21 @@ def main():
             div[name] = sg.div_max * dx / float(u0.abs().max())
         step_err["fp64_divergence_check"] = {"max_abs_Dbar_u_times_dx_over_umax": div,
                                              "cells": "at least n_buf + r_i + 1 from every face, every stage"}
+        # cost of the guard: FP64 steps (no Vor2Vel) with and without it, from the same state
+        def steps_ms(guard):
+            st = nslgf.HerkState(u0.clone(), dx, dt, re, "A", n_buf=16, guard=guard)
+            st.step()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(5):
+                st.step()
+            b.record(stream)
+            torch.cuda.synchronize()
+            return a.elapsed_time(b) / 5
+
+        step_err["fp64_divergence_check"]["fp64_step_ms"] = {"plain": round(steps_ms(False), 4),
+                                                             "guarded": round(steps_ms(True), 4)}
 
         def step32():
             nslgf.vor2vel(w32, dx, out=s32.u)
