@@ -389,8 +389,10 @@ int nslgf_profile_enable(nslgf_t h, int enable);
  *   0  narrow: 8 (length 256) or 16 (length 512) complex elements per thread, radix-4/8 passes,
  *      an LDS exchange between passes;
  *   1  wide: 16 or 32 elements per thread, radices 16 x 16 or 16 x 32, one exchange per transform;
- *   2  (FP64 only) the narrow radices on 4 or 8 elements per thread;
- *  -1  (the default) wide in FP32; in FP64 narrow at length 256 and 2 at length 512;
+ *   2  the narrow radices on 4 or 8 elements per thread (512-thread workgroups; in FP32 on tiles of
+ *      8 columns, 64-byte row segments);
+ *  -1  (the default) in FP32 narrow for the y passes and wide for the fused z pass; in FP64 narrow
+ *      at length 256 and 2 at length 512;
  *  -2  (NSLGF_FFT_PLAN_AUTOTUNE) the autotuner: when a plan is built, every variant that exists for
  *      its y and z lengths is timed on the device on the plan's own shapes and the fastest is kept
  *      (the choice may differ between runs, so results may differ in the last bits).

@@ -342,7 +342,7 @@ FFT_PLAN_AUTOTUNE = -2
 
 def set_fft_plan(choice: int, device: int | None = None):
     """Column-pass FFT plan of convolution plans built from now on (lengths 256 and 512): -1 the
-    default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread (FP64), -2 autotune
+    default, 0 narrow, 1 wide, 2 narrow radices on fewer elements per thread, -2 autotune
     (time every variant when a plan is built and keep the fastest)."""
     _check("nslgf_set_fft_plan", lib().nslgf_set_fft_plan(handle(device), int(choice)))
 

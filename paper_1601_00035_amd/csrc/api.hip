@@ -316,6 +316,7 @@ static int autotune_plan(nslgf_ctx* h, ConvPlan& p, hipStream_t s) {
     z.tw = twz;
     z.khat = p.khat.p;
     z.khat_tiles = p.tiles;
+    z.khat_tb = p.tb;
     z.outer_period = p.Py;
     z.scale = 1.0;
     float best = 3.4e38f;
@@ -386,8 +387,8 @@ static int build_plan(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
         return NSLGF_EUNSUPPORTED;
     }
     p.XP = ((p.Px / 2 + 1 + 7) / 8) * 8;
-    p.vy = col_variant_choice(p.Py, dtype, h->fft_plan);
-    p.vz = col_variant_choice(p.Pz, dtype, h->fft_plan);
+    p.vy = col_variant_choice(p.Py, dtype, h->fft_plan, false);
+    p.vz = col_variant_choice(p.Pz, dtype, h->fft_plan, true);
     auto te = h->tunings.find(std::make_tuple(nx, ny, nz, dtype));
     const bool loaded = h->fft_plan == -1 && te != h->tunings.end() && te->second.vy >= 0 && te->second.vz >= 0 &&
                         col_variant_valid(p.Py, dtype, te->second.vy) && col_variant_valid(p.Pz, dtype, te->second.vz);
@@ -610,6 +611,7 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     z.tw = twz;
     z.khat = p.khat.p;
     z.khat_tiles = p.tiles;
+    z.khat_tb = p.tb;
     z.outer_period = p.Py;
     z.scale = scale;
     NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s, p.vz));

@@ -87,11 +87,13 @@ template <> struct PlanV<256, 2> {
 };
 
 // Columns per workgroup of the strided (column-tile) kernels: one 128-byte row segment at least,
-// and at least one wavefront per workgroup.
+// and at least one wavefront per workgroup, but at most 512 threads (plans with many threads per
+// column then take 64-byte segments).
 template <typename T>
 __host__ __device__ constexpr int col_tb(int tp) {
     const int base = (int)(128 / (2 * sizeof(T)));
-    return (tp * base >= 64) ? base : 64 / tp;
+    const int tb = (tp * base >= 64) ? base : 64 / tp;
+    return tb * tp > 512 ? 512 / tp : tb;
 }
 
 

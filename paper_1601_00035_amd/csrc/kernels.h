@@ -109,16 +109,17 @@ struct ColPass {
     int ncomp;
     int n_in, n_out;      // nonzero inputs / kept outputs along the transform
     const void* tw;       // root table of length L
-    // COL_CONV only: real spectrum laid out [Py/2+1][tiles][L/2+1][TB]; outer index ky folds to
-    // min(ky, outer_period - ky).
+    // COL_CONV only: real spectrum laid out [Py/2+1][khat_tiles][L/2+1][khat_tb] (column c in tile
+    // c / khat_tb); outer index ky folds to min(ky, outer_period - ky).
     const void* khat;
     int khat_tiles;
+    int khat_tb;
     int outer_period;
     double scale;
 };
 // variant: plan variant of lengths 256 and 512 (0 = default; see PlanV and col_variant_choice)
 int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, int variant = 0);
-int col_variant_choice(int L, int dtype, int choice);
+int col_variant_choice(int L, int dtype, int choice, bool zpass);
 constexpr int kColVariants = 3;  // variants 0 .. kColVariants - 1 (not all exist for every length and dtype)
 bool col_variant_valid(int L, int dtype, int v);
 

@@ -258,14 +258,15 @@ k_col(ColPass a0, const ColPass* __restrict__ da, int per) {
     T kv[MODE == COL_CONV ? E : 1];
     if constexpr (MODE == COL_CONV) {
         const int kyf = min(outer, a.outer_period - outer);
-        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + tile) * (L / 2 + 1) * TB + c;
+        const int ktb = a.khat_tb, kcol = tile * TB + c;  // (the spectrum's own tile width may exceed TB)
+        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + kcol / ktb) * (L / 2 + 1) * ktb + kcol % ktb;
 #pragma unroll
         for (int b = 0; b < E / RLf; ++b) {
             const int j = t + b * TP;
 #pragma unroll
             for (int r = 0; r < RLf; ++r) {
                 const int kz = j + r * (L / RLf);
-                kv[b * RLf + r] = kh[min(kz, L - kz) * TB];
+                kv[b * RLf + r] = kh[min(kz, L - kz) * ktb];
             }
         }
     }
@@ -443,7 +444,6 @@ template <typename T, int LH> static int do_c2r(const RowPass& a, hipStream_t s)
 }
 template <typename T, int L, int MODE, int V = 0> static int do_col(const ColPass& a, hipStream_t s) {
     constexpr int TP = L / PlanV<L, V>::E, TB = col_tb<T>(TP);
-    static_assert(TB == col_tb<T>(L / Plan1D<L>::E), "plan variants must share the column-tile width");
     if (a.nouter > 65535 || a.ncomp > 65535) {
         set_error("column pass grid too large");
         return NSLGF_EINVAL;
@@ -523,9 +523,7 @@ template <typename T, int L, int V> static int col_modes(ColMode mode, const Col
 
 template <typename T, int L> static int col_variant(int variant, ColMode mode, const ColPass& a, hipStream_t s) {
     if (variant == 1) return col_modes<T, L, 1>(mode, a, s);
-    if constexpr (sizeof(T) == 8) {  // 512-thread workgroups: double only (float tiles are twice as wide)
-        if (variant == 2) return col_modes<T, L, 2>(mode, a, s);
-    }
+    if (variant == 2) return col_modes<T, L, 2>(mode, a, s);  // (in FP32 on 8-column tiles)
     return col_modes<T, L, 0>(mode, a, s);
 }
 
@@ -551,18 +549,21 @@ int launch_col(int L, int dtype, ColMode mode, const ColPass& a, hipStream_t s, 
 }
 
 bool col_variant_valid(int L, int dtype, int v) {
+    (void)dtype;
     if (L != 512 && L != 256) return v == 0;
-    return v == 0 || v == 1 || (v == 2 && dtype == NSLGF_F64);
+    return v == 0 || v == 1 || v == 2;
 }
 
-// Column-pass plan per length and dtype: a valid choice >= 0 forces that variant; -1 (or a variant
-// that does not exist for the length and dtype) takes the default measured fastest on gfx950: wide
-// in FP32; in FP64 the wide plan spills its registers at length 512, where the default radices on
-// 8 elements per thread (twice the waves of the default) win, and the default plan wins at 256.
-int col_variant_choice(int L, int dtype, int choice) {
+// Column-pass plan per length, dtype and pass (the y passes or the fused z pass): a valid choice >= 0
+// forces that variant; -1 (or a variant that does not exist for the length) takes the default
+// measured fastest on gfx950.  FP32: the narrow plan for the y passes (13-15 % ahead of the wide one
+// at both lengths), the wide plan for the fused pass (0.21 against 0.33 ms at length 512).  FP64: the
+// wide plan spills its registers at length 512, where the default radices on 8 elements per thread
+// (twice the waves of the default) win in both passes, and the default plan wins at 256.
+int col_variant_choice(int L, int dtype, int choice, bool zpass) {
     if (choice >= 0 && col_variant_valid(L, dtype, choice)) return choice;
     if (L != 512 && L != 256) return 0;
-    if (dtype == NSLGF_F32) return 1;
+    if (dtype == NSLGF_F32) return zpass ? 1 : 0;
     return L == 512 ? 2 : 0;
 }
 
