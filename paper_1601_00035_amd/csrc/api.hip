@@ -316,7 +316,6 @@ static int autotune_plan(nslgf_ctx* h, ConvPlan& p, hipStream_t s) {
     z.tw = twz;
     z.khat = p.khat.p;
     z.khat_tiles = p.tiles;
-    z.khat_tb = p.tb;
     z.outer_period = p.Py;
     z.scale = 1.0;
     float best = 3.4e38f;
@@ -611,7 +610,6 @@ static int run_conv(nslgf_ctx* h, ConvPlan& p, const void* src, void* dst, int n
     z.tw = twz;
     z.khat = p.khat.p;
     z.khat_tiles = p.tiles;
-    z.khat_tb = p.tb;
     z.outer_period = p.Py;
     z.scale = scale;
     NSLGF_PROF(h, "conv_z_fused", s, launch_col(p.Pz, dt, COL_CONV, z, s, p.vz));

@@ -109,11 +109,10 @@ struct ColPass {
     int ncomp;
     int n_in, n_out;      // nonzero inputs / kept outputs along the transform
     const void* tw;       // root table of length L
-    // COL_CONV only: real spectrum laid out [Py/2+1][khat_tiles][L/2+1][khat_tb] (column c in tile
-    // c / khat_tb); outer index ky folds to min(ky, outer_period - ky).
+    // COL_CONV only: real spectrum laid out [Py/2+1][khat_tiles][L/2+1][TBk], TBk = col_tile_width(L,
+    // dtype) (column c in tile c / TBk); outer index ky folds to min(ky, outer_period - ky).
     const void* khat;
     int khat_tiles;
-    int khat_tb;
     int outer_period;
     double scale;
 };

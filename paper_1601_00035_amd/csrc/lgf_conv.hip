@@ -258,15 +258,23 @@ k_col(ColPass a0, const ColPass* __restrict__ da, int per) {
     T kv[MODE == COL_CONV ? E : 1];
     if constexpr (MODE == COL_CONV) {
         const int kyf = min(outer, a.outer_period - outer);
-        const int ktb = a.khat_tb, kcol = tile * TB + c;  // (the spectrum's own tile width may exceed TB)
-        const T* kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + kcol / ktb) * (L / 2 + 1) * ktb + kcol % ktb;
+        // the spectrum is tiled by the default plan's column width KTB, which a variant's TB may divide
+        constexpr int KTB = col_tb<T>(L / Plan1D<L>::E);
+        static_assert(KTB % TB == 0, "column tiles must nest in the spectrum's tiles");
+        const T* kh;
+        if constexpr (KTB == TB) {
+            kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + tile) * (L / 2 + 1) * KTB + c;
+        } else {
+            const unsigned kcol = (unsigned)(tile * TB + c);
+            kh = (const T*)a.khat + ((long long)kyf * a.khat_tiles + kcol / KTB) * (L / 2 + 1) * KTB + kcol % KTB;
+        }
 #pragma unroll
         for (int b = 0; b < E / RLf; ++b) {
             const int j = t + b * TP;
 #pragma unroll
             for (int r = 0; r < RLf; ++r) {
                 const int kz = j + r * (L / RLf);
-                kv[b * RLf + r] = kh[min(kz, L - kz) * ktb];
+                kv[b * RLf + r] = kh[min(kz, L - kz) * KTB];
             }
         }
     }

@@ -231,6 +231,63 @@ def surrogate_summary(run_dir: str, n: int, iters: int) -> str:
     return "\n".join(out)
 
 
+def sq_summary(run_dirs: list) -> str:
+    """Markdown summary of SQ counter runs (rocprofv3 --pmc over the benchmark) for the dominant
+    kernels: per launch (dispatches grouped like the traffic figures) the raw counters and the derived
+    rates of rocprofv3's own definitions (GRBM_GUI_ACTIVE summed over the 8 XCDs, so one XCD's clock
+    is a eighth of it; 256 CUs, 32 wave slots per CU)."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(float))
+    meta = {}
+    for d in run_dirs:
+        for f in glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True):
+            con = sqlite3.connect(f)
+            for did, name, grid, c, v in con.execute(
+                    "select dispatch_id, kernel_name, grid_size, counter_name, value from counters_collection"):
+                vals[(name, grid, f, did)][c] += float(v)
+                meta[(name, grid, f, did)] = (name, int(grid))
+            con.close()
+    out = []
+    for key, sym in KERNELS.items():
+        groups = collections.defaultdict(list)
+        for k, cv in vals.items():
+            if sym in k[0]:
+                # conv_z_fused: by grid (components); others: by instantiation and grid
+                gk = k[1] if key == "conv_z_fused" else (k[0].split("(")[0].replace("void ", ""), k[1])
+                groups[gk].append(cv)
+        if not groups:
+            continue
+        g1 = min(groups) if key == "conv_z_fused" else None
+        out.append(f"### `{key}` (`{sym}`)")
+        out.append("")
+        out.append("| launch | n | waves | VALU instr / wave | LDS instr / wave | occupancy % | VALU busy % | "
+                   "LDS active % | LDS bank-conflict % | XCD clock us |")
+        out.append("|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|")
+        for grid in sorted(groups):
+            runs = groups[grid]
+            avg = collections.defaultdict(float)
+            cnt = collections.Counter()
+            for cv in runs:
+                for c, v in cv.items():
+                    avg[c] += v
+                    cnt[c] += 1
+            a = {c: avg[c] / cnt[c] for c in avg}
+            gclk = a.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+            waves = a.get("SQ_WAVES", float("nan"))
+
+            def pct(c, scale):
+                return f"{100.0 * a[c] / scale:.1f}" if c in a and scale else "-"
+
+            label = f"{grid // g1} component(s)" if key == "conv_z_fused" else f"`{grid[0]}`, grid {grid[1]}"
+            vi = f"{a['SQ_INSTS_VALU'] / waves:.0f}" if "SQ_INSTS_VALU" in a and waves == waves else "-"
+            li = f"{a['SQ_INSTS_LDS'] / waves:.0f}" if "SQ_INSTS_LDS" in a and waves == waves else "-"
+            occ = f"{400.0 * a['SQ_WAVE_CYCLES'] / gclk / 256 / 32:.1f}" if "SQ_WAVE_CYCLES" in a and gclk else "-"
+            out.append(f"| {label} | {len(runs)} | {waves:.0f} | {vi} | {li} | {occ} | "
+                       f"{pct('SQ_ACTIVE_INST_VALU', gclk * 256)} | {pct('SQ_ACTIVE_INST_LDS', gclk * 256)} | "
+                       f"{pct('SQ_LDS_BANK_CONFLICT', gclk * 256)} | {gclk / 2.4e3:.1f} |")
+        out.append("")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--fetch")
@@ -238,6 +295,8 @@ def main():
     ap.add_argument("--trace", help="rocprofv3 --kernel-trace output folder: print the time summary instead")
     ap.add_argument("--surrogate-trace", help="rocprofv3 --kernel-trace folder of surrogate_run --time-iters: "
                                               "print the per-layer summary")
+    ap.add_argument("--sq", nargs="+", help="rocprofv3 --pmc folders of SQ counter runs over the benchmark: print "
+                                            "the counter summary of the dominant kernels")
     ap.add_argument("--n", type=int, default=128, help="grid of the surrogate run")
     ap.add_argument("--iters", type=int, default=3, help="timed iterations of the surrogate run")
     ap.add_argument("--last", type=int, default=12, help="launches of the dominant kernel in the timed steps")
@@ -245,6 +304,9 @@ def main():
     a = ap.parse_args()
     if a.trace:
         print(trace_summary(a.trace, a.last))
+        return
+    if a.sq:
+        print(sq_summary(a.sq))
         return
     if a.surrogate_trace:
         print(surrogate_summary(a.surrogate_trace, a.n, a.iters))
