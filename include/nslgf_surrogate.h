@@ -55,6 +55,23 @@ int sur_mse(nslgf_t h, const void *pred, const void *target, void *grad, void *p
 /* Adam step on FP32 master weights (t = step number from 1) and their BF16 copy. */
 int sur_adam(nslgf_t h, void *w, void *w_bf16, const void *g, void *m, void *v, long long n, float lr, float b1,
              float b2, float eps, int t, void *stream);
+/* Blocked BF16 layout of the weight gradient's operands: [nvox / 8][c][8] (8 consecutive voxels of one
+ * channel contiguous).  sur_to_blocked8 rearranges a channels-last [nvox][c] BF16 tensor into it
+ * (nvox % 8 == 0, c % 8 == 0, xb must not overlap x). */
+int sur_to_blocked8(nslgf_t h, const void *x_bf16, void *xb_bf16, long long nvox, int c, void *stream);
+/* Cast of a channels-last FP32 tensor [nvox][c] to BF16 with an optional ReLU backward (act_f32: the
+ * layer's activation; values where act is not > 0 become +0, as sur_relu_bwd leaves them) and an
+ * optional blocked copy (yb_bf16, may be NULL): y = bf16(val) channels-last, yb the same values in the
+ * blocked layout.  Equal bit for bit to sur_relu_bwd, sur_cast_bf16 and sur_to_blocked8 in turn, without
+ * writing the FP32 tensor back.  nvox % 8 == 0, c % 8 == 0. */
+int sur_cast_bf16_ex(nslgf_t h, const void *src_f32, const void *act_f32, void *y_bf16, void *yb_bf16,
+                     long long nvox, int c, void *stream);
+/* Weight gradient from operands already in the blocked layout (dyb [nvox/8][cout][8], xb [nvox/8][cin][8]):
+ * the result of sur_conv3d_bwd_weight bit for bit, without its two layout copies.  Needs W % 8 == 0 and
+ * D*H*W % 16 == 0 (else NSLGF_EINVAL); work of sur_bwd_weight_blocked_work_bytes bytes. */
+int sur_conv3d_bwd_weight_blocked(nslgf_t h, const void *dyb_bf16, const void *xb_bf16, void *dw_f32, void *work,
+                                  int D, int H, int W, int cin, int cout, void *stream);
+size_t sur_bwd_weight_blocked_work_bytes(int D, int H, int W, int cin, int cout);
 /* Pack planar FP64 vorticity [3][D][H][W] into the network input [voxel][16] BF16:
  * channels 0..2 = omega * scale, channel 3 = feat, the rest 0. */
 int sur_pack_input(nslgf_t h, const void *omega_f64, void *x_bf16, int D, int H, int W, double scale, double feat,

@@ -277,6 +277,45 @@ __global__ void __launch_bounds__(256) k_to_blocked8(const bf16_t* __restrict__ 
     }
 }
 
+// FP32 -> BF16 cast of channels-last [nvox][C] with an optional ReLU backward and an optional blocked
+// copy: val = src (0 where act is given and not > 0, as k_relu_bwd leaves it), y[v][c] = bf16(val) and
+// yb[v / 8][c][v % 8] = bf16(val) (the layout of k_to_blocked8).  One thread: 8 voxels x 8 channels.
+__global__ void __launch_bounds__(256) k_cast_ex(const float* __restrict__ src, const float* __restrict__ act,
+                                                 bf16_t* __restrict__ y, bf16_t* __restrict__ yb, long long ngroups,
+                                                 int C) {
+    const int cgs = C / 8;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ngroups * cgs) return;
+    const long long g = e / cgs;
+    const int cg = (int)(e % cgs) * 8;
+    bf16_t o[64];  // o[j * 8 + c]: voxel j, channel cg + c
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const long long base = (g * 8 + j) * C + cg;
+        const float4 v0 = *(const float4*)(src + base), v1 = *(const float4*)(src + base + 4);
+        float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+        if (act) {
+            const float4 a0 = *(const float4*)(act + base), a1 = *(const float4*)(act + base + 4);
+            const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (!(a[c] > 0.f)) v[c] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o[j * 8 + c] = f2bf(v[c]);
+        *(uint4*)(y + base) = *(const uint4*)(o + j * 8);
+    }
+    if (yb) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            bf16_t t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[j] = o[j * 8 + c];
+            *(uint4*)(yb + (g * C + cg + c) * 8) = *(const uint4*)t;
+        }
+    }
+}
+
 // Partial weight gradient of one voxel chunk for the three taps of one (dz, dy) pair and one (cout, cin)
 // tile pair:
 //     P[chunk][tap][co][ci] = sum_{v in chunk} dY[v][co] X[v + off(tap)][ci],  tap = 3 (3 (dz + 1) + dy + 1) + dx + 1,
@@ -659,12 +698,44 @@ size_t sur_bwd_weight_work_bytes(int D, int H, int W, int cin, int cout) {
     if (D < 1 || H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
     const long long nvox = (long long)D * H * W;
     if (wgrad_cm_ok(W, nvox)) {
-        // chunk partials, the channel-major copies of dY and X, then the group sums of the partials
-        const int nch = wgrad_cm_chunks(nvox, cin, cout);
-        return align256((size_t)nch * 27 * cin * cout * sizeof(float)) + align256((size_t)nvox * cout * 2) +
-               align256((size_t)nvox * cin * 2) + (size_t)(nch / 32 + 1) * 27 * cin * cout * sizeof(float);
+        // the channel-major copies of dY and X, then what the blocked form needs
+        return align256((size_t)nvox * cout * 2) + align256((size_t)nvox * cin * 2) +
+               sur_bwd_weight_blocked_work_bytes(D, H, W, cin, cout);
     }
     return (size_t)wgrad_chunks(nvox) * 27 * cin * cout * sizeof(float);
+}
+
+size_t sur_bwd_weight_blocked_work_bytes(int D, int H, int W, int cin, int cout) {
+    if (D < 1 || H < 1 || W < 1 || cin < 1 || cout < 1) return 0;
+    const long long nvox = (long long)D * H * W;
+    if (!wgrad_cm_ok(W, nvox)) return 0;
+    // chunk partials, then the group sums of the partials
+    const int nch = wgrad_cm_chunks(nvox, cin, cout);
+    return align256((size_t)nch * 27 * cin * cout * sizeof(float)) + (size_t)(nch / 32 + 1) * 27 * cin * cout * sizeof(float);
+}
+
+// Weight gradient from the blocked copies, partials and their fixed-order sums in `work`.
+static int wgrad_from_blocked(const bf16_t* dyc, const bf16_t* xc, float* dw, char* work, int D, int H, int W, int cin,
+                              int cout, hipStream_t s) {
+    const long long nvox = (long long)D * H * W;
+    const long long n = 27LL * cin * cout;
+    const int nch = wgrad_cm_chunks(nvox, cin, cout);
+    const int chunk_len = (int)(nvox / nch);
+    float* part = (float*)work;
+    const long long nwaves = (long long)nch * (cout / 32) * ((cin + 31) / 32) * 9;
+    hipLaunchKernelGGL(k_conv_wgrad_cm, dim3((unsigned)ceil_div(nwaves, 4)), dim3(256), 0, s, dyc, xc, part, D, H, W,
+                       cin, cout, chunk_len, (int)nwaves);
+    if (nch >= 64) {
+        // two levels (groups of 32 chunks, then the groups), each in a fixed order
+        const int G = 32, ng = nch / G;
+        float* q = (float*)(work + align256((size_t)nch * 27 * cin * cout * sizeof(float)));
+        hipLaunchKernelGGL(k_sum_chunk_groups, dim3(grid1(n), ng), dim3(256), 0, s, (const float*)part, q, n, G);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)q, dw, n, ng);
+    } else {
+        hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)part, dw, n, nch);
+    }
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
 }
 
 int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, void* work, int D, int H, int W, int cin,
@@ -676,30 +747,15 @@ int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, vo
     hipStream_t s = (hipStream_t)stream;
     const long long n = 27LL * cin * cout;
     if (wgrad_cm_ok(W, nvox)) {
-        const int nch = wgrad_cm_chunks(nvox, cin, cout);
-        const int chunk_len = (int)(nvox / nch);
         char* base = (char*)work;
-        float* part = (float*)base;
-        bf16_t* dyc = (bf16_t*)(base + align256((size_t)nch * 27 * cin * cout * sizeof(float)));
-        bf16_t* xc = (bf16_t*)((char*)dyc + align256((size_t)nvox * cout * 2));
+        bf16_t* dyc = (bf16_t*)base;
+        bf16_t* xc = (bf16_t*)(base + align256((size_t)nvox * cout * 2));
+        char* rest = (char*)xc + align256((size_t)nvox * cin * 2);
         hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (cout / 8), 256)), dim3(256), 0, s,
                            (const bf16_t*)dy, dyc, nvox / 8, cout);
         hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (cin / 8), 256)), dim3(256), 0, s,
                            (const bf16_t*)x, xc, nvox / 8, cin);
-        const long long nwaves = (long long)nch * (cout / 32) * ((cin + 31) / 32) * 9;
-        hipLaunchKernelGGL(k_conv_wgrad_cm, dim3((unsigned)ceil_div(nwaves, 4)), dim3(256), 0, s, (const bf16_t*)dyc,
-                           (const bf16_t*)xc, part, D, H, W, cin, cout, chunk_len, (int)nwaves);
-        if (nch >= 64) {
-            // two levels (groups of 32 chunks, then the groups), each in a fixed order
-            const int G = 32, ng = nch / G;
-            float* q = (float*)((char*)xc + align256((size_t)nvox * cin * 2));
-            hipLaunchKernelGGL(k_sum_chunk_groups, dim3(grid1(n), ng), dim3(256), 0, s, (const float*)part, q, n, G);
-            hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)q, (float*)dw, n, ng);
-        } else {
-            hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)part, (float*)dw, n, nch);
-        }
-        NSLGF_LAUNCH_CHECK();
-        return NSLGF_OK;
+        return wgrad_from_blocked(dyc, xc, (float*)dw, rest, D, H, W, cin, cout, s);
     }
     const int nch = wgrad_chunks(nvox);
     const int chunk_len = (int)(nvox / nch);
@@ -707,6 +763,38 @@ int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, vo
     hipLaunchKernelGGL(k_conv_wgrad, dim3(ceil_div(waves, 4)), dim3(256), 0, s, (const bf16_t*)dy, (const bf16_t*)x,
                        (float*)work, D, H, W, cin, cout, chunk_len, nch);
     hipLaunchKernelGGL(k_sum_chunks, dim3(grid1(n)), dim3(256), 0, s, (const float*)work, (float*)dw, n, nch);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_conv3d_bwd_weight_blocked(nslgf_t h, const void* dyb, const void* xb, void* dw, void* work, int D, int H, int W,
+                                  int cin, int cout, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
+    NSLGF_CHECK_ARG(dyb && xb && dw && work, "sur_conv3d_bwd_weight_blocked: null pointer");
+    NSLGF_CHECK_ARG(wgrad_cm_ok(W, (long long)D * H * W), "sur_conv3d_bwd_weight_blocked: needs W % 8 == 0 and D*H*W % 16 == 0");
+    return wgrad_from_blocked((const bf16_t*)dyb, (const bf16_t*)xb, (float*)dw, (char*)work, D, H, W, cin, cout,
+                              (hipStream_t)stream);
+}
+
+int sur_cast_bf16_ex(nslgf_t h, const void* src, const void* act, void* y, void* yb, long long nvox, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(src && y && nvox >= 0 && nvox % 8 == 0 && c > 0 && c % 8 == 0,
+                    "sur_cast_bf16_ex: need src, y, nvox % 8 == 0, c % 8 == 0");
+    if (nvox == 0) return NSLGF_OK;
+    hipLaunchKernelGGL(k_cast_ex, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)src, (const float*)act, (bf16_t*)y, (bf16_t*)yb, nvox / 8, c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_to_blocked8(nslgf_t h, const void* x, void* xb, long long nvox, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(x && xb && x != xb && nvox >= 0 && nvox % 8 == 0 && c > 0 && c % 8 == 0,
+                    "sur_to_blocked8: need x != xb, nvox % 8 == 0, c % 8 == 0");
+    if (nvox == 0) return NSLGF_OK;
+    hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const bf16_t*)x, (bf16_t*)xb, nvox / 8, c);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

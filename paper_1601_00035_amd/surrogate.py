@@ -44,6 +44,9 @@ def _bind():
         "sur_conv3d_bwd_weight": [vp, vp, vp, vp, vp, i, i, i, i, i, vp],
         "sur_weight_transpose": [vp, vp, vp, i, i, vp],
         "sur_cast_bf16": [vp, vp, vp, ll, vp],
+        "sur_cast_bf16_ex": [vp, vp, vp, vp, vp, ll, i, vp],
+        "sur_to_blocked8": [vp, vp, vp, ll, i, vp],
+        "sur_conv3d_bwd_weight_blocked": [vp, vp, vp, vp, vp, i, i, i, i, i, vp],
         "sur_relu_bwd": [vp, vp, vp, ll, vp],
         "sur_add": [vp, vp, vp, vp, ll, vp],
         "sur_pool2_fwd": [vp, vp, vp, i, i, i, i, vp],
@@ -65,6 +68,8 @@ def _bind():
         fn.restype = i
     L.sur_bwd_weight_work_bytes.argtypes = [i, i, i, i, i]
     L.sur_bwd_weight_work_bytes.restype = ctypes.c_size_t
+    L.sur_bwd_weight_blocked_work_bytes.argtypes = [i, i, i, i, i]
+    L.sur_bwd_weight_blocked_work_bytes.restype = ctypes.c_size_t
     _bound = True
 
 
@@ -128,15 +133,32 @@ class UNet:
         call("sur_cast_bf16", src, dst, n)
         return dst
 
+    def _cast_ex(self, src, key, nvox, c, act=None, blocked=True):
+        """BF16 copy of an FP32 tensor [nvox][c] (after the ReLU backward of `act` when given) and, when
+        `blocked`, its blocked copy for the weight gradient (key + "_k")."""
+        dst = self._buf(key + "_b", nvox * c, bf16=True)
+        blk = self._buf(key + "_k", nvox * c, bf16=True) if blocked else None
+        call("sur_cast_bf16_ex", src, act, dst, blk, nvox, c)
+        return dst
+
     # ---- forward ------------------------------------------------------------------------------
-    def forward(self, xb: torch.Tensor, R: int) -> torch.Tensor:
-        """xb: BF16 input [R^3][16]; returns the FP32 output [R^3][32] (channels 0..2 meaningful)."""
+    def forward(self, xb: torch.Tensor, R: int, train: bool = False) -> torch.Tensor:
+        """xb: BF16 input [R^3][16]; returns the FP32 output [R^3][32] (channels 0..2 meaningful).  With
+        `train`, the BF16 layer inputs also get the blocked copies the weight gradients read."""
         assert R % 16 == 0 and R >= 32
         r = [R >> l for l in range(4)]
         nv = [x ** 3 for x in r]
         A = {}
         self.R = R
         A["x_b"] = xb
+        if train:
+            A["x_k"] = self._buf("x_k", nv[0] * IN_CH, bf16=True)
+            call("sur_to_blocked8", xb, A["x_k"], nv[0], IN_CH)
+
+        def cast(src, key, lv, c):
+            if train:
+                return self._cast_ex(src, key, nv[lv], c)
+            return self._cast(src, key, nv[lv] * c)
 
         def conv(li, src_b, key):
             ci, co = LAYERS[li]
@@ -146,56 +168,65 @@ class UNet:
             return out
 
         A["a0"] = conv(0, xb, "a0")
-        A["a0_b"] = self._cast(A["a0"], "a0", nv[0] * 32)
+        A["a0_b"] = cast(A["a0"], "a0", 0, 32)
         A["e1"] = conv(1, A["a0_b"], "e1")
         A["p1"] = self._buf("p1", nv[1] * 32)
         call("sur_pool2_fwd", A["e1"], A["p1"], r[0], r[0], r[0], 32)
-        A["p1_b"] = self._cast(A["p1"], "p1", nv[1] * 32)
+        A["p1_b"] = cast(A["p1"], "p1", 1, 32)
         A["e2"] = conv(2, A["p1_b"], "e2")
         A["p2"] = self._buf("p2", nv[2] * 64)
         call("sur_pool2_fwd", A["e2"], A["p2"], r[1], r[1], r[1], 64)
-        A["p2_b"] = self._cast(A["p2"], "p2", nv[2] * 64)
+        A["p2_b"] = cast(A["p2"], "p2", 2, 64)
         A["e3"] = conv(3, A["p2_b"], "e3")
         A["p3"] = self._buf("p3", nv[3] * 96)
         call("sur_pool2_fwd", A["e3"], A["p3"], r[2], r[2], r[2], 96)
-        A["p3_b"] = self._cast(A["p3"], "p3", nv[3] * 96)
+        A["p3_b"] = cast(A["p3"], "p3", 3, 96)
         A["b4"] = conv(4, A["p3_b"], "b4")
-        A["b4_b"] = self._cast(A["b4"], "b4", nv[3] * 128)
+        A["b4_b"] = cast(A["b4"], "b4", 3, 128)
         A["b5"] = conv(5, A["b4_b"], "b5")
         A["u3"] = self._buf("u3", nv[2] * 96)
         call("sur_up2_fwd", A["b5"], A["u3"], r[2], r[2], r[2], 96)
         call("sur_add", A["u3"], A["e3"], A["u3"], nv[2] * 96)
-        A["u3_b"] = self._cast(A["u3"], "u3", nv[2] * 96)
+        A["u3_b"] = cast(A["u3"], "u3", 2, 96)
         A["d3"] = conv(6, A["u3_b"], "d3")
         A["u2"] = self._buf("u2", nv[1] * 64)
         call("sur_up2_fwd", A["d3"], A["u2"], r[1], r[1], r[1], 64)
         call("sur_add", A["u2"], A["e2"], A["u2"], nv[1] * 64)
-        A["u2_b"] = self._cast(A["u2"], "u2", nv[1] * 64)
+        A["u2_b"] = cast(A["u2"], "u2", 1, 64)
         A["d2"] = conv(7, A["u2_b"], "d2")
         A["u1"] = self._buf("u1", nv[0] * 32)
         call("sur_up2_fwd", A["d2"], A["u1"], r[0], r[0], r[0], 32)
         call("sur_add", A["u1"], A["e1"], A["u1"], nv[0] * 32)
-        A["u1_b"] = self._cast(A["u1"], "u1", nv[0] * 32)
+        A["u1_b"] = cast(A["u1"], "u1", 0, 32)
         A["d1"] = conv(8, A["u1_b"], "d1")
-        A["d1_b"] = self._cast(A["d1"], "d1", nv[0] * 32)
+        A["d1_b"] = cast(A["d1"], "d1", 0, 32)
         A["y"] = conv(9, A["d1_b"], "y")
         self.A = A
         return A["y"][: nv[0] * OUT_CH]
 
     # ---- backward -----------------------------------------------------------------------------
     def backward(self, gy: torch.Tensor):
-        """gy: FP32 gradient of the loss w.r.t. the output [R^3][32]; fills self.gw."""
+        """gy: FP32 gradient of the loss w.r.t. the output [R^3][32]; fills self.gw.  After a forward with
+        `train`, the weight gradients read blocked copies written by the casts (the ReLU backward folded
+        into the gradient casts); otherwise they copy their operands themselves.  Same results."""
         A = self.A
         R = self.R
         r = [R >> l for l in range(4)]
         nv = [x ** 3 for x in r]
+        blk = "x_k" in A
 
-        def wgrad(li, g_b, x_b):
+        def wgrad(li, gkey, g_b, xkey):
             ci, co = LAYERS[li]
             lv = LEVEL[li]
-            nbytes = lib().sur_bwd_weight_work_bytes(r[lv], r[lv], r[lv], ci, co)
-            work = self._buf("wgrad_work", nbytes // 4 + 1)
-            call("sur_conv3d_bwd_weight", g_b, x_b, self.gw[li], work, r[lv], r[lv], r[lv], ci, co)
+            nbytes = lib().sur_bwd_weight_blocked_work_bytes(r[lv], r[lv], r[lv], ci, co) if blk else 0
+            if nbytes:  # (0: a volume the blocked form does not take, W % 8 != 0)
+                work = self._buf("wgrad_work", nbytes // 4 + 1)
+                call("sur_conv3d_bwd_weight_blocked", self.bufs[gkey + "_k"], self.bufs[xkey + "_k"], self.gw[li], work,
+                     r[lv], r[lv], r[lv], ci, co)
+            else:
+                nbytes = lib().sur_bwd_weight_work_bytes(r[lv], r[lv], r[lv], ci, co)
+                work = self._buf("wgrad_work", nbytes // 4 + 1)
+                call("sur_conv3d_bwd_weight", g_b, A[xkey + "_b"], self.gw[li], work, r[lv], r[lv], r[lv], ci, co)
 
         def dgrad(li, g_b, key):
             ci, co = LAYERS[li]
@@ -205,62 +236,58 @@ class UNet:
             call("sur_conv3d_bwd_data", g_b, self.wt[li], out, r[lv], r[lv], r[lv], ci, co)
             return out
 
-        def relu_bwd(act, g, n):
-            call("sur_relu_bwd", act, g, n)
+        def castg(g, key, lv, c, act=None):
+            """BF16 copy of a gradient, after the ReLU backward of the activation `act` when given."""
+            if blk:
+                return self._cast_ex(g, key, nv[lv], c, act=act)
+            if act is not None:
+                call("sur_relu_bwd", act, g, nv[lv] * c)
+            return self._cast(g, key, nv[lv] * c)
 
-        gy_b = self._cast(gy, "gy", nv[0] * 32)
-        wgrad(9, gy_b, A["d1_b"])
+        gy_b = castg(gy, "gy", 0, 32)
+        wgrad(9, "gy", gy_b, "d1")
         gd1 = dgrad(9, gy_b, "gd1")
-        relu_bwd(A["d1"], gd1, nv[0] * 32)
-        gd1_b = self._cast(gd1, "gd1", nv[0] * 32)
-        wgrad(8, gd1_b, A["u1_b"])
+        gd1_b = castg(gd1, "gd1", 0, 32, A["d1"])
+        wgrad(8, "gd1", gd1_b, "u1")
         gu1 = dgrad(8, gd1_b, "gu1")                       # also the gradient of e1 through the skip
         gd2 = self._buf("gd2", nv[1] * 32)
         call("sur_up2_bwd", gu1, gd2, r[0], r[0], r[0], 32)
-        relu_bwd(A["d2"], gd2, nv[1] * 32)
-        gd2_b = self._cast(gd2, "gd2", nv[1] * 32)
-        wgrad(7, gd2_b, A["u2_b"])
+        gd2_b = castg(gd2, "gd2", 1, 32, A["d2"])
+        wgrad(7, "gd2", gd2_b, "u2")
         gu2 = dgrad(7, gd2_b, "gu2")
         gd3 = self._buf("gd3", nv[2] * 64)
         call("sur_up2_bwd", gu2, gd3, r[1], r[1], r[1], 64)
-        relu_bwd(A["d3"], gd3, nv[2] * 64)
-        gd3_b = self._cast(gd3, "gd3", nv[2] * 64)
-        wgrad(6, gd3_b, A["u3_b"])
+        gd3_b = castg(gd3, "gd3", 2, 64, A["d3"])
+        wgrad(6, "gd3", gd3_b, "u3")
         gu3 = dgrad(6, gd3_b, "gu3")
         gb5 = self._buf("gb5", nv[3] * 96)
         call("sur_up2_bwd", gu3, gb5, r[2], r[2], r[2], 96)
-        relu_bwd(A["b5"], gb5, nv[3] * 96)
-        gb5_b = self._cast(gb5, "gb5", nv[3] * 96)
-        wgrad(5, gb5_b, A["b4_b"])
+        gb5_b = castg(gb5, "gb5", 3, 96, A["b5"])
+        wgrad(5, "gb5", gb5_b, "b4")
         gb4 = dgrad(5, gb5_b, "gb4")
-        relu_bwd(A["b4"], gb4, nv[3] * 128)
-        gb4_b = self._cast(gb4, "gb4", nv[3] * 128)
-        wgrad(4, gb4_b, A["p3_b"])
+        gb4_b = castg(gb4, "gb4", 3, 128, A["b4"])
+        wgrad(4, "gb4", gb4_b, "p3")
         gp3 = dgrad(4, gb4_b, "gp3")
         ge3 = self._buf("ge3", nv[2] * 96)
         call("sur_pool2_bwd", gp3, ge3, r[2], r[2], r[2], 96)
         call("sur_add", ge3, gu3, ge3, nv[2] * 96)
-        relu_bwd(A["e3"], ge3, nv[2] * 96)
-        ge3_b = self._cast(ge3, "ge3", nv[2] * 96)
-        wgrad(3, ge3_b, A["p2_b"])
+        ge3_b = castg(ge3, "ge3", 2, 96, A["e3"])
+        wgrad(3, "ge3", ge3_b, "p2")
         gp2 = dgrad(3, ge3_b, "gp2")
         ge2 = self._buf("ge2", nv[1] * 64)
         call("sur_pool2_bwd", gp2, ge2, r[1], r[1], r[1], 64)
         call("sur_add", ge2, gu2, ge2, nv[1] * 64)
-        relu_bwd(A["e2"], ge2, nv[1] * 64)
-        ge2_b = self._cast(ge2, "ge2", nv[1] * 64)
-        wgrad(2, ge2_b, A["p1_b"])
+        ge2_b = castg(ge2, "ge2", 1, 64, A["e2"])
+        wgrad(2, "ge2", ge2_b, "p1")
         gp1 = dgrad(2, ge2_b, "gp1")
         ge1 = self._buf("ge1", nv[0] * 32)
         call("sur_pool2_bwd", gp1, ge1, r[0], r[0], r[0], 32)
         call("sur_add", ge1, gu1, ge1, nv[0] * 32)
-        relu_bwd(A["e1"], ge1, nv[0] * 32)
-        ge1_b = self._cast(ge1, "ge1", nv[0] * 32)
-        wgrad(1, ge1_b, A["a0_b"])
+        ge1_b = castg(ge1, "ge1", 0, 32, A["e1"])
+        wgrad(1, "ge1", ge1_b, "a0")
         ga0 = dgrad(1, ge1_b, "ga0")
-        relu_bwd(A["a0"], ga0, nv[0] * 32)
-        ga0_b = self._cast(ga0, "ga0", nv[0] * 32)
-        wgrad(0, ga0_b, A["x_b"])
+        ga0_b = castg(ga0, "ga0", 0, 32, A["a0"])
+        wgrad(0, "ga0", ga0_b, "x")
 
     def adam(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1
@@ -378,7 +405,7 @@ def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float
         else:
             pack_input(w_k, scales[i], res[i], out=xb)
             pack_target(combine3(w_h, w_k, None, 1.0, -1.0), scales[i] * gain, out=tg)
-        y = net.forward(xb, R)
+        y = net.forward(xb, R, train=True)
         part, grad = net.loss_and_grad(y, tg, nvox)
         net.backward(grad)
         net.adam(lr=lr)

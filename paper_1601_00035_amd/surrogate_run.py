@@ -115,7 +115,7 @@ def time_iterations(n: int, iters: int, seed: int):
     tg = (torch.randn(nvox * S.USED, generator=g) * 0.01).to("cuda:0", torch.float32)
 
     def it():
-        y = net.forward(xb, n)
+        y = net.forward(xb, n, train=True)
         _, grad = net.loss_and_grad(y, tg, nvox)
         net.backward(grad)
         net.adam(lr=1e-4)

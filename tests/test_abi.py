@@ -1,4 +1,5 @@
-"""The C ABI library loads and exports every entry point declared in include/nslgf.h, and the host-side
+"""The C ABI library loads and exports every entry point declared in include/nslgf.h and
+include/nslgf_surrogate.h, and the host-side
 LGF evaluation of the table builder (same method as the GPU builder) agrees with the oracle."""
 import ctypes
 import os
@@ -14,7 +15,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "nslgf.h")).read()
+    text = open(os.path.join(ROOT, "include", "nslgf.h")).read() + open(os.path.join(ROOT, "include",
+                                                                                   "nslgf_surrogate.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?(?:int|size_t|char|void)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
     return sorted(set(names))
@@ -24,6 +26,7 @@ def test_library_exports_declared_symbols():
     L = nslgf.lib()
     names = _declared()
     assert "lgf_convolve" in names and "herk_stage" in names and "if_apply" in names and "lgf_table" in names
+    assert "sur_conv3d_fwd" in names and "sur_cast_bf16_ex" in names and "sur_bwd_weight_blocked_work_bytes" in names
     for n in names:
         assert hasattr(L, n), n
     assert nslgf.version().startswith("nslgf")

@@ -125,6 +125,53 @@ def test_unet_forward_backward_vs_oracle():
         l2 = np.linalg.norm(got - gref[li]) / np.linalg.norm(gref[li])
         assert l2 < 6e-2, (li, l2)
         assert rel(got, gref[li]) < 1.5e-1, li
+    # the training path (blocked copies written by the casts, the ReLU backward folded into the gradient
+    # casts, the blocked weight gradient) gives the same output and gradients bit for bit
+    plain = [g.clone() for g in net.gw]
+    y2 = net.forward(to_bf16_bits(x).reshape(-1), R, train=True)
+    assert torch.equal(y2, y)
+    net.backward(torch.from_numpy(gy.astype(np.float32).reshape(-1)).to(DEV))
+    for li in range(10):
+        assert torch.equal(net.gw[li], plain[li]), li
+
+
+def test_fused_cast_and_blocked_weight_gradient():
+    """sur_cast_bf16_ex equals sur_relu_bwd, sur_cast_bf16 and sur_to_blocked8 in turn, bit for bit (with
+    and without the ReLU mask, zeros and negative values included); the blocked weight gradient equals
+    the plain one bit for bit."""
+    rng = np.random.default_rng(12)
+    D, H, W, c = 4, 8, 16, 32
+    nv = D * H * W
+    g = rng.standard_normal((nv, c)).astype(np.float32)
+    g[::7] = 0.0
+    act = rng.standard_normal((nv, c)).astype(np.float32)
+    act[::5] = 0.0
+    gt, at = torch.from_numpy(g).to(DEV).reshape(-1), torch.from_numpy(act).to(DEV).reshape(-1)
+    for use_act in (False, True):
+        ref = gt.clone()
+        if use_act:
+            S.call("sur_relu_bwd", at, ref, nv * c)
+        ref_b = S.bf16_empty(nv * c, DEV)
+        S.call("sur_cast_bf16", ref, ref_b, nv * c)
+        ref_k = S.bf16_empty(nv * c, DEV)
+        S.call("sur_to_blocked8", ref_b, ref_k, nv, c)
+        y, yk = S.bf16_empty(nv * c, DEV), S.bf16_empty(nv * c, DEV)
+        S.call("sur_cast_bf16_ex", gt, at if use_act else None, y, yk, nv, c)
+        assert torch.equal(y, ref_b) and torch.equal(yk, ref_k), use_act
+    cin, cout = 32, 64
+    x = to_bf16_bits(rand_bf16((D, H, W, cin), 13)).reshape(-1)
+    dy = to_bf16_bits(rand_bf16((D, H, W, cout), 14)).reshape(-1)
+    work = torch.empty(S.lib().sur_bwd_weight_work_bytes(D, H, W, cin, cout) // 4 + 1, dtype=torch.float32, device=DEV)
+    gw = torch.empty(27 * cout * cin, dtype=torch.float32, device=DEV)
+    S.call("sur_conv3d_bwd_weight", dy, x, gw, work, D, H, W, cin, cout)
+    xk, dyk = S.bf16_empty(x.numel(), DEV), S.bf16_empty(dy.numel(), DEV)
+    S.call("sur_to_blocked8", x, xk, nv, cin)
+    S.call("sur_to_blocked8", dy, dyk, nv, cout)
+    work2 = torch.empty(S.lib().sur_bwd_weight_blocked_work_bytes(D, H, W, cin, cout) // 4 + 1, dtype=torch.float32,
+                        device=DEV)
+    gw2 = torch.full_like(gw, float("nan"))
+    S.call("sur_conv3d_bwd_weight_blocked", dyk, xk, gw2, work2, D, H, W, cin, cout)
+    assert torch.equal(gw, gw2)
 
 
 def test_training_lowers_loss():
