@@ -379,8 +379,9 @@ def make_trajectory(n: int, dx: float, sigma: float, re: float, seed: int, steps
 
 
 def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float = 1e-3, gain: float = 5.0,
-          seed: int = 0, log_every: int = 0, mode: str = "persist", dgain: float = 10.0):
-    """Adam on random (w_k, w_{k+horizon}) pairs, s = 1 / max|w_0| of the trajectory.
+          seed: int = 0, log_every: int = 0, mode: str = "persist", dgain: float = 10.0, lr_min: float | None = None):
+    """Adam on random (w_k, w_{k+horizon}) pairs, s = 1 / max|w_0| of the trajectory.  With lr_min the
+    step size follows a cosine from lr down to lr_min over the iterations (without it, constant lr).
     mode "persist": input w_k s, target (w_{k+h} - w_k) s gain.
     mode "correct": input w_k s and the one-step change (w_{k+1} - w_k) s dgain, target the error of the
     linear extrapolation, (w_{k+h} - w_k - h (w_{k+1} - w_k)) s gain.
@@ -408,7 +409,8 @@ def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float
         y = net.forward(xb, R, train=True)
         part, grad = net.loss_and_grad(y, tg, nvox)
         net.backward(grad)
-        net.adam(lr=lr)
+        lr_it = lr if lr_min is None else lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(1, iters - 1)))
+        net.adam(lr=lr_it)
         if log_every and (it % log_every == 0 or it == iters - 1):
             losses.append((it, part.sum().item() / (nvox * USED)))
     return losses

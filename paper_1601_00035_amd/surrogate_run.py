@@ -29,7 +29,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--horizon", type=int, default=4)
     ap.add_argument("--iters", type=int, default=2000)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4,
+                    help="peak Adam step size (1e-3 let the loss spike and, in some runs, the ReLUs die)")
+    ap.add_argument("--lr-min", type=float, default=1e-5,
+                    help="cosine decay of the Adam step size from --lr to this over the iterations (negative: constant)")
     ap.add_argument("--eval-blocks", type=int, default=6)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
@@ -72,7 +75,7 @@ def main(argv=None):
     net = S.UNet("cuda:0", seed=a.seed, in_real=7 if a.mode == "correct" else 4)
     t0 = time.perf_counter()
     losses = S.train(net, trajs, res, a.horizon, a.iters, lr=a.lr, seed=a.seed, log_every=max(1, a.iters // 20),
-                     mode=a.mode, gain=gain)
+                     mode=a.mode, gain=gain, lr_min=a.lr_min if a.lr_min >= 0 else None)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     for it, l in losses:
@@ -84,7 +87,7 @@ def main(argv=None):
     ro = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, a.eval_blocks, a.horizon, a.tol, gain=gain, mode=a.mode)
     reduction = [p / e for e, p in zip(ro["err"], ro["persistence_err"])]
     report = {
-        "mode": a.mode, "gain": gain, "grid": n, "trajectories": len(train_specs), "snapshots": snapshots, "steps_per_trajectory": a.steps,
+        "mode": a.mode, "gain": gain, "lr": a.lr, "lr_min": a.lr_min, "grid": n, "trajectories": len(train_specs), "snapshots": snapshots, "steps_per_trajectory": a.steps,
         "horizon": a.horizon, "train_iters": a.iters, "data_gen_s": round(gen_s, 2), "train_s": round(train_s, 2),
         "ms_per_train_iter": round(1e3 * train_s / max(1, a.iters), 3),
         "loss_first": losses[0][1], "loss_last": losses[-1][1],
