@@ -128,6 +128,60 @@ def cpu_baseline(w, dx, seconds: float):
     }
 
 
+def cpu_oracle_sizes(nslgf, torch, cores: int):
+    """The oracle's direct sum against the GPU convolution on the compact random source (radius 12 n / 32
+    cells, seed 0) at 32^3 and 64^3 (full grids) and 128^3 (a seeded sample of 4096 targets, the full
+    time extrapolated and labelled so), on all host threads and, at 32^3, on one thread."""
+    import ctypes
+
+    import numpy as np
+
+    import workloads
+    from oracle import native
+
+    native.load()
+    out = {"cores": cores}
+    for n in (32, 64, 128):
+        s = workloads.compact_random_source(n, 12.0 * n / 32, seed=0)
+        t = torch.from_numpy(s).to("cuda:0")
+        y = nslgf.lgf_convolve(t, 1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            nslgf.lgf_convolve(t, 1.0, y)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu_ms = e0.elapsed_time(e1) / 10
+        rec = {"sources": int(np.count_nonzero(s)), "gpu_ms": round(gpu_ms, 4)}
+        if n <= 64:
+            t0 = time.perf_counter()
+            native.lgf_direct(s, 1.0)
+            el = time.perf_counter() - t0
+            rec.update({"oracle_s": round(el, 3), "oracle_full": True})
+        else:
+            tg = workloads.sample_targets(n, 4096, seed=12)
+            t0 = time.perf_counter()
+            native.lgf_direct_targets(s, 1.0, tg)
+            el = time.perf_counter() - t0
+            rec.update({"oracle_s": round(el * n ** 3 / len(tg), 1), "oracle_full": False,
+                        "oracle_sample": f"{len(tg)} targets in {el:.2f} s, full grid extrapolated"})
+        rec["gpu_speedup"] = round(rec["oracle_s"] * 1e3 / gpu_ms, 1)
+        out[f"{n}^3"] = rec
+    # one thread (the OpenMP runtime the oracle's library uses), 32^3 full
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        s = workloads.compact_random_source(32, 12.0, seed=0)
+        gomp.omp_set_num_threads(1)
+        t0 = time.perf_counter()
+        native.lgf_direct(s, 1.0)
+        out["32^3_one_thread_s"] = round(time.perf_counter() - t0, 3)
+        gomp.omp_set_num_threads(cores)
+    except OSError:
+        out["32^3_one_thread_s"] = None
+    return out
+
+
 def batched_measure(nslgf, torch, dtype, reps=3, sizes=None):
     """32 uneven Scheme A steps (n ~ U{48..192}, seeded rings): the same steps issued one state after
     another on one stream, against one captured graph per batch in both of its forms (batched passes: one
@@ -545,6 +599,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores ...")
         cpu = cpu_baseline(w_np, dx, args.cpu_seconds)
+        if not args.no_secondary:
+            log("oracle against the GPU convolution at 32^3, 64^3, 128^3 ...")
+            secondary["cpu_oracle"] = cpu_oracle_sizes(nslgf, torch, cpu["cores"])
 
     line = {
         "metric": "LGF solve Mpts/s & %HBM peak at 256^3; FP32/batched vs FP64 at stated rel err",
