@@ -55,6 +55,8 @@ int sur_mse(nslgf_t h, const void *pred, const void *target, void *grad, void *p
 /* Adam step on FP32 master weights (t = step number from 1) and their BF16 copy. */
 int sur_adam(nslgf_t h, void *w, void *w_bf16, const void *g, void *m, void *v, long long n, float lr, float b1,
              float b2, float eps, int t, void *stream);
+/* The convolution, layout and fused-cast calls move 16 bytes per access: their tensors must start on
+ * 16-byte boundaries (NSLGF_EINVAL otherwise). */
 /* Blocked BF16 layout of the weight gradient's operands: [nvox / 8][c][8] (8 consecutive voxels of one
  * channel contiguous).  sur_to_blocked8 rearranges a channels-last [nvox][c] BF16 tensor into it
  * (nvox % 8 == 0, c % 8 == 0, xb must not overlap x). */

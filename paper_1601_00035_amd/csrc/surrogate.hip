@@ -645,6 +645,9 @@ using namespace nslgf;
         if (rc_ != NSLGF_OK) return rc_;                                                           \
     } while (0)
 
+// The matrix-core and layout kernels move 16 bytes per access: their tensors must start on 16 bytes.
+static bool a16(const void* p) { return p == nullptr || ((uintptr_t)p % 16) == 0; }
+
 static int conv_shape_ok(int D, int H, int W, int cin, int cout) {
     NSLGF_CHECK_ARG(D >= 1 && H >= 1 && W >= 1 && (long long)D * H * W % 32 == 0, "surrogate: D*H*W must be a multiple of 32");
     NSLGF_CHECK_ARG(cin >= 16 && cin % 16 == 0 && cin <= 1024, "surrogate: cin must be a multiple of 16");
@@ -659,6 +662,7 @@ int sur_conv3d_fwd(nslgf_t h, const void* x, const void* w, void* y, int D, int 
     SUR_ENTER(h);
     NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
     NSLGF_CHECK_ARG(x && w && y, "sur_conv3d_fwd: null pointer");
+    NSLGF_CHECK_ARG(a16(x) && a16(w) && a16(y), "sur_conv3d_fwd: tensors must be 16-byte aligned");
     const long long waves = (long long)D * H * W / 32 * (cout / 32);
     hipStream_t s = (hipStream_t)stream;
     if (conv_lds_ok(D, H, W, cin, cout)) {
@@ -682,6 +686,7 @@ int sur_conv3d_bwd_data(nslgf_t h, const void* dy, const void* wt, void* dx, int
     NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
     NSLGF_CHECK_ARG(cin % 32 == 0, "sur_conv3d_bwd_data: cin must be a multiple of 32");
     NSLGF_CHECK_ARG(dy && wt && dx, "sur_conv3d_bwd_data: null pointer");
+    NSLGF_CHECK_ARG(a16(dy) && a16(wt) && a16(dx), "sur_conv3d_bwd_data: tensors must be 16-byte aligned");
     // GEMM with K = cout (inner) and N = cin (outputs), gathering dy at v - off
     const long long waves = (long long)D * H * W / 32 * (cin / 32);
     if (conv_lds_ok(D, H, W, cout, cin))
@@ -743,6 +748,7 @@ int sur_conv3d_bwd_weight(nslgf_t h, const void* dy, const void* x, void* dw, vo
     SUR_ENTER(h);
     NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
     NSLGF_CHECK_ARG(dy && x && dw && work, "sur_conv3d_bwd_weight: null pointer");
+    NSLGF_CHECK_ARG(a16(dy) && a16(x) && a16(dw) && a16(work), "sur_conv3d_bwd_weight: tensors must be 16-byte aligned");
     const long long nvox = (long long)D * H * W;
     hipStream_t s = (hipStream_t)stream;
     const long long n = 27LL * cin * cout;
@@ -772,6 +778,7 @@ int sur_conv3d_bwd_weight_blocked(nslgf_t h, const void* dyb, const void* xb, vo
     SUR_ENTER(h);
     NSLGF_TRY(conv_shape_ok(D, H, W, cin, cout));
     NSLGF_CHECK_ARG(dyb && xb && dw && work, "sur_conv3d_bwd_weight_blocked: null pointer");
+    NSLGF_CHECK_ARG(a16(dyb) && a16(xb) && a16(dw) && a16(work), "sur_conv3d_bwd_weight_blocked: tensors must be 16-byte aligned");
     NSLGF_CHECK_ARG(wgrad_cm_ok(W, (long long)D * H * W), "sur_conv3d_bwd_weight_blocked: needs W % 8 == 0 and D*H*W % 16 == 0");
     return wgrad_from_blocked((const bf16_t*)dyb, (const bf16_t*)xb, (float*)dw, (char*)work, D, H, W, cin, cout,
                               (hipStream_t)stream);
@@ -781,6 +788,7 @@ int sur_cast_bf16_ex(nslgf_t h, const void* src, const void* act, void* y, void*
     SUR_ENTER(h);
     NSLGF_CHECK_ARG(src && y && nvox >= 0 && nvox % 8 == 0 && c > 0 && c % 8 == 0,
                     "sur_cast_bf16_ex: need src, y, nvox % 8 == 0, c % 8 == 0");
+    NSLGF_CHECK_ARG(a16(src) && a16(act) && a16(y) && a16(yb), "sur_cast_bf16_ex: tensors must be 16-byte aligned");
     if (nvox == 0) return NSLGF_OK;
     hipLaunchKernelGGL(k_cast_ex, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
                        (const float*)src, (const float*)act, (bf16_t*)y, (bf16_t*)yb, nvox / 8, c);
@@ -792,6 +800,7 @@ int sur_to_blocked8(nslgf_t h, const void* x, void* xb, long long nvox, int c, v
     SUR_ENTER(h);
     NSLGF_CHECK_ARG(x && xb && x != xb && nvox >= 0 && nvox % 8 == 0 && c > 0 && c % 8 == 0,
                     "sur_to_blocked8: need x != xb, nvox % 8 == 0, c % 8 == 0");
+    NSLGF_CHECK_ARG(a16(x) && a16(xb), "sur_to_blocked8: tensors must be 16-byte aligned");
     if (nvox == 0) return NSLGF_OK;
     hipLaunchKernelGGL(k_to_blocked8, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
                        (const bf16_t*)x, (bf16_t*)xb, nvox / 8, c);

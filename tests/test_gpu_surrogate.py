@@ -275,3 +275,17 @@ def test_correction_form_rollout_small():
     ro_all = S.judged_rollout(net, n, dx_of(sig), sig, re, seed, blocks=1, horizon=4, tol=1e9, n_buf=2, gain=30.0,
                               mode="correct")
     assert all(ro_all["accepted"])
+
+
+def test_misaligned_tensors_are_refused():
+    """The 16-byte vector kernels refuse tensors that do not start on 16 bytes (a host-side check)."""
+    D, H, W, cin, cout = 2, 8, 32, 16, 32
+    x = S.bf16_empty(D * H * W * cin + 8, DEV)
+    w = S.bf16_empty(27 * cout * cin, DEV)
+    y = torch.empty(D * H * W * cout, dtype=torch.float32, device=DEV)
+    with pytest.raises(Exception):
+        S.call("sur_conv3d_fwd", x[1:], w, y, D, H, W, cin, cout, 0)
+    src = torch.zeros(64 * 8 + 4, dtype=torch.float32, device=DEV)
+    out = S.bf16_empty(64 * 8, DEV)
+    with pytest.raises(Exception):
+        S.call("sur_cast_bf16_ex", src[1:], None, out, None, 64, 8)
