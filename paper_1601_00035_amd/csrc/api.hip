@@ -504,6 +504,18 @@ static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** t
     return NSLGF_OK;
 }
 
+// Default launch shapes of a box: up to 192 cells along y and z, 64 output rows per workgroup of the
+// fused x-y integrating-factor pass and 16 outputs per thread of the strided z pass (more workgroups
+// and shorter serial chains for these latency-bound passes; the choices the tuner makes on such boxes);
+// larger boxes 128 and 32.
+static Tuning default_tuning(int nx, int ny, int nz) {
+    (void)nx;
+    Tuning t;
+    if (ny <= 192) t.if_rows = 64;
+    if (nz <= 192) t.if_seg = 16;
+    return t;
+}
+
 // Launch tuner: times, on zero fields of the box, the fused x-y integrating-factor pass for 64, 128 and
 // 256 rows per workgroup, the strided z pass for 16 and 32 outputs per thread, and the stage kernel
 // (the largest point kernel) for every point-kernel shape, and keeps the fastest of each.  None of
@@ -520,7 +532,7 @@ static int autotune_launch(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipS
     const int rad = if_weights(0.02, dtype, w, kIfMaxRadius);  // the step's typical factor (beta / 2)
     const bool prof = h->prof.on;
     h->prof.on = false;
-    Tuning t;  // (the defaults)
+    Tuning t = default_tuning(nx, ny, nz);
     int rc = NSLGF_OK;
     {
         const IfCombine cb{{a.p, nullptr, nullptr}, {1.0, 0.0, 0.0}};
@@ -582,7 +594,7 @@ static int get_tuning(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream
         *out = t;
         return NSLGF_OK;
     }
-    *out = Tuning{};
+    *out = default_tuning(nx, ny, nz);
     return NSLGF_OK;
 }
 
@@ -1983,7 +1995,7 @@ int nslgf_tuning_save(nslgf_t h, const char* path) {
         const int nx = std::get<0>(kv.first), ny = std::get<1>(kv.first), nz = std::get<2>(kv.first);
         const int dt = std::get<3>(kv.first);
         const TuneEntry& e = kv.second;
-        const Tuning t = e.launch_set ? e.t : Tuning{};
+        const Tuning t = e.launch_set ? e.t : default_tuning(nx, ny, nz);
         char line[512];
         std::snprintf(line, sizeof line,
                       "%s\n    {\"nx\": %d, \"ny\": %d, \"nz\": %d, \"dtype\": \"%s\", \"Px\": %d, \"Py\": %d, "

@@ -140,7 +140,8 @@ struct IfTerms {
 };
 
 // Fused x and y passes (fixed radius R): a workgroup owns one (component, z) plane and S consecutive
-// output rows y0 .. y0 + S - 1 (S set per box by the launch tuner), one thread per x (nx <= 256).  It walks the rows from y0 - R upwards,
+// output rows y0 .. y0 + S - 1 (the tile height, from the rows per workgroup the launch tuner sets per
+// box), one thread per x (nx <= 256).  It walks the rows from y0 - R upwards,
 // RB rows per step: each thread holds the raw values of the next P steps in registers (loads issued
 // P steps ahead), the step's rows go through a double-buffered LDS tile with R zeros at both ends of
 // each row (one barrier per step), each x-filtered value is rounded to the dtype and pushed into a
@@ -379,21 +380,26 @@ static void launch_fixed(int axis, const T* in, T* out, int ncomp, int nx, int n
         issue_strided<T, R, 32>(a, dim3(ceil_div(nx, 64), ceil_div(ceil_div(len, 32), 4), nouter * ncomp), s);
 }
 
-template <typename T, int R, int MODE> static void issue_xy(const IfXyArgs& a, dim3 grid, hipStream_t s) {
+template <typename T, int R, int MODE>
+static void issue_xy(const IfXyArgs& a, dim3 grid, dim3 block, hipStream_t s) {
     if (launch_recorder()) {
-        record_launch(&batched_xy<T, R, MODE>, grid, dim3(256), a);
+        record_launch(&batched_xy<T, R, MODE>, grid, block, a);
         return;
     }
-    hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, MODE, false>), grid, dim3(256), 0, s, a, nullptr, 0);
+    hipLaunchKernelGGL((k_if_xy<T, R, kIfRowsPerStep, kIfPrefetch, MODE, false>), grid, block, 0, s, a, nullptr, 0);
 }
 
-// (rows: output rows per workgroup; halo rows re-read: 2R / rows)
+// rows: at most this many output rows per workgroup; the ny rows of a plane are split into
+// ceil(ny / rows) tiles of equal height (up to one row less in the last), so that no workgroup walks
+// past the plane's end or carries a long tail alone (halo rows re-read: 2R / height).  A workgroup
+// has one thread per x rounded up to whole wavefronts.
 template <typename T, int R>
 static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
                       hipStream_t s, int rows) {
     const int ntiles = ceil_div(ny, rows);
-    const dim3 grid((unsigned)((long long)ntiles * nz * ncomp));
-    IfXyArgs a{cb.p[0], out, nx, ny, nz, ntiles, rows, wts, IfTerms{}};
+    const int height = ceil_div(ny, ntiles);
+    const dim3 grid((unsigned)((long long)ntiles * nz * ncomp)), block((unsigned)(ceil_div(nx, 64) * 64));
+    IfXyArgs a{cb.p[0], out, nx, ny, nz, ntiles, height, wts, IfTerms{}};
     IfTerms& terms = a.terms;
     if (cb.proj) {
         const IfProject& pj = *cb.proj;
@@ -405,16 +411,16 @@ static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, in
         terms.c_q = pj.c_q;
         terms.c_w1 = pj.c_w1;
         terms.inv = pj.inv;
-        issue_xy<T, R, IF_IN_PROJ>(a, grid, s);
+        issue_xy<T, R, IF_IN_PROJ>(a, grid, block, s);
     } else if (cb.p[1]) {
         terms.in1 = cb.p[1];
         terms.in2 = cb.p[2];
         terms.c0 = cb.c[0];
         terms.c1 = cb.c[1];
         terms.c2 = cb.c[2];
-        issue_xy<T, R, IF_IN_COMB>(a, grid, s);
+        issue_xy<T, R, IF_IN_COMB>(a, grid, block, s);
     } else {
-        issue_xy<T, R, IF_IN_PLAIN>(a, grid, s);
+        issue_xy<T, R, IF_IN_PLAIN>(a, grid, block, s);
     }
 }
 

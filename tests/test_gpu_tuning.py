@@ -54,9 +54,9 @@ def test_every_launch_choice_is_bit_identical(tmp_path):
             for a, b in zip(got, ref):
                 assert torch.equal(a, b), (rows, seg, shape)
     finally:
-        # back to the defaults for this box on the process's handle
+        # back to the defaults for this box on the process's handle (an entry without launch choices)
         path = tmp_path / "default.json"
-        path.write_text(json.dumps({"format": "nslgf-tuning-1", "entries": [_entry(128, 32, 0)]}))
+        path.write_text(json.dumps({"format": "nslgf-tuning-1", "entries": [_entry(128, 32, 0, launch=0)]}))
         nslgf.tuning_load(str(path))
 
 
