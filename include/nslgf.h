@@ -412,11 +412,13 @@ int nslgf_profile_read(nslgf_t h, int index, char *name, int name_cap, long long
 
 /*
  * Launch tuner.  Per box and dtype the library chooses the column-plan variants of the convolution
- * (see nslgf_set_fft_plan), the rows per workgroup of the fused x-y integrating-factor pass (64, 128,
- * 256), the outputs per thread of the strided z pass (16, 32) and the workgroup shape of the point
- * kernels (0: 64x4, 1: 128x2, 2: 32x8, 3: 256x1 threads).  None of the launch shapes changes the
- * arithmetic (results are bit-identical); the column variants change the order of rounding only.
- *   NSLGF_TUNE_DEFAULT  the measured defaults (128 rows, 32 outputs, 64x4, the default column plans);
+ * (see nslgf_set_fft_plan), the rows per workgroup of the fused x-y integrating-factor pass (32, 64,
+ * 128, 256; a plane's rows are split into tiles of equal height up to that many), the outputs per thread
+ * of the strided z pass (16, 32) and the workgroup shape of the point kernels (0: 64x4, 1: 128x2,
+ * 2: 32x8, 3: 256x1 threads).  None of the launch shapes changes the arithmetic (results are
+ * bit-identical); the column variants change the order of rounding only.
+ *   NSLGF_TUNE_DEFAULT  the measured defaults: IF rows 32 for ny <= 128, 64 for ny <= 192, else 128;
+ *                       z outputs 16 for nz <= 192, else 32; 64x4; the default column plans;
  *   NSLGF_TUNE_AUTO     the first use of a box and dtype times every choice on the device on zero fields
  *                       of that box (one synchronisation) and keeps the fastest.
  * Choices recorded for a box (tuned, or read by nslgf_tuning_load) are used in either mode, unless an

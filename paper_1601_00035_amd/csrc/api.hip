@@ -504,20 +504,20 @@ static int plan_twiddles(nslgf_ctx* h, const ConvPlan& p, int dt, const void** t
     return NSLGF_OK;
 }
 
-// Default launch shapes of a box: up to 192 cells along y and z, 64 output rows per workgroup of the
-// fused x-y integrating-factor pass and 16 outputs per thread of the strided z pass (more workgroups
-// and shorter serial chains for these latency-bound passes; the choices the tuner makes on such boxes);
-// larger boxes 128 and 32.
+// Default launch shapes of a box, the tuner's choices on cubes of 48 to 256 cells: output rows per
+// workgroup of the fused x-y integrating-factor pass 32 up to 128 cells along y, 64 up to 192, else 128
+// (small planes give few workgroups, each a serial walk over its rows: shorter walks, more of them);
+// outputs per thread of the strided z pass 16 up to 192 cells along z, else 32.
 static Tuning default_tuning(int nx, int ny, int nz) {
     (void)nx;
     Tuning t;
-    if (ny <= 192) t.if_rows = 64;
-    if (nz <= 192) t.if_seg = 16;
+    t.if_rows = ny <= 128 ? 32 : ny <= 192 ? 64 : 128;
+    t.if_seg = nz <= 192 ? 16 : 32;
     return t;
 }
 
-// Launch tuner: times, on zero fields of the box, the fused x-y integrating-factor pass for 64, 128 and
-// 256 rows per workgroup, the strided z pass for 16 and 32 outputs per thread, and the stage kernel
+// Launch tuner: times, on zero fields of the box, the fused x-y integrating-factor pass for 32, 64, 128
+// and 256 rows per workgroup, the strided z pass for 16 and 32 outputs per thread, and the stage kernel
 // (the largest point kernel) for every point-kernel shape, and keeps the fastest of each.  None of
 // these choices changes the arithmetic.  Runs once per box and dtype, outside any capture.
 static int autotune_launch(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipStream_t s, Tuning* out) {
@@ -537,10 +537,10 @@ static int autotune_launch(nslgf_ctx* h, int nx, int ny, int nz, int dtype, hipS
     {
         const IfCombine cb{{a.p, nullptr, nullptr}, {1.0, 0.0, 0.0}};
         // (more rows than half the plane gives one tile: the same launch as fewer rows would)
-        std::initializer_list<int> rows_all = {64, 128, 256};
+        std::initializer_list<int> rows_all = {32, 64, 128, 256};
         std::vector<int> rows_ok;
         for (int r : rows_all)
-            if (r <= 64 || ny > r / 2) rows_ok.push_back(r);
+            if (r <= 32 || ny > r / 2) rows_ok.push_back(r);
         int best = t.if_rows;
         float tdef = 0.f;
         rc = time_min_ms(s, 5, [&] { return launch_if_xy(dtype, cb, b.p, 3, nx, ny, nz, w, rad, s, t.if_rows); }, &tdef);
@@ -2083,7 +2083,7 @@ int nslgf_tuning_load(nslgf_t h, const char* path) {
             return NSLGF_EINVAL;
         }
         if (check_box(nx, ny, nz) != NSLGF_OK || check_dtype(dt) != NSLGF_OK || Px != padded(nx) ||
-            Py != padded(ny) || Pz != padded(nz) || (rows != 64 && rows != 128 && rows != 256) ||
+            Py != padded(ny) || Pz != padded(nz) || (rows != 32 && rows != 64 && rows != 128 && rows != 256) ||
             (seg != 16 && seg != 32) || shape < 0 || shape >= kCellShapeCount ||
             (vy >= 0 && !col_variant_valid(Py, dt, vy)) || (vz >= 0 && !col_variant_valid(Pz, dt, vz))) {
             set_error("nslgf_tuning_load: an entry does not fit this library (sizes, padded lengths or choices)");

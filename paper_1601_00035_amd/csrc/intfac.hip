@@ -495,8 +495,8 @@ int launch_if_xy(int dtype, const IfCombine& cb, void* out, int ncomp, int nx, i
         set_error("if_apply: the fused x-y pass needs nx <= 256");
         return NSLGF_EUNSUPPORTED;
     }
-    if (rows != 64 && rows != 128 && rows != 256) {
-        set_error("if_apply: the fused x-y pass takes 64, 128 or 256 rows per workgroup");
+    if (rows != 32 && rows != 64 && rows != 128 && rows != 256) {
+        set_error("if_apply: the fused x-y pass takes 32, 64, 128 or 256 rows per workgroup");
         return NSLGF_EINVAL;
     }
     if (dtype == NSLGF_F32) return if_xy_t<float>(cb, out, ncomp, nx, ny, nz, w, radius, s, rows);

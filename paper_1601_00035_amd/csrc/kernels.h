@@ -56,7 +56,7 @@ __device__ __forceinline__ bool in_domain(int i, int j, int k, int nx, int ny, i
 // the work split only, never the arithmetic, so every choice gives bit-identical results.
 constexpr int kCellShapeCount = 4;  // point-kernel workgroups 64x4, 128x2, 32x8, 256x1 (x by y threads)
 struct Tuning {
-    int if_rows = 128;   // output rows per workgroup of the fused x-y integrating-factor pass (64, 128, 256)
+    int if_rows = 128;   // output rows per workgroup of the fused x-y integrating-factor pass (32 .. 256)
     int if_seg = 32;     // outputs per thread of the strided (z) integrating-factor pass (16 or 32)
     int cell_shape = 0;  // point-kernel workgroup shape index
 };

@@ -46,7 +46,7 @@ def test_every_launch_choice_is_bit_identical(tmp_path):
     u0, dx, dt, re = _state()
     ref = _run(u0, dx, dt, re)
     try:
-        for rows, seg, shape in itertools.product((64, 128, 256), (16, 32), range(4)):
+        for rows, seg, shape in itertools.product((32, 64, 128, 256), (16, 32), range(4)):
             path = tmp_path / f"t_{rows}_{seg}_{shape}.json"
             path.write_text(json.dumps({"format": "nslgf-tuning-1", "entries": [_entry(rows, seg, shape)]}))
             nslgf.tuning_load(str(path))
@@ -68,7 +68,7 @@ def test_auto_tuning_and_save_load(tmp_path):
         info = nslgf.tuning_info(*box)
     finally:
         nslgf.set_tuning(nslgf.TUNE_DEFAULT)
-    assert info["if_rows"] in (64, 128, 256) and info["if_seg"] in (16, 32) and 0 <= info["cell_shape"] < 4
+    assert info["if_rows"] in (32, 64, 128, 256) and info["if_seg"] in (16, 32) and 0 <= info["cell_shape"] < 4
     path = tmp_path / "tuned.json"
     nslgf.tuning_save(str(path))
     doc = json.loads(path.read_text())
