@@ -93,3 +93,11 @@ def test_auto_tuning_and_save_load(tmp_path):
         assert L.nslgf_tuning_load(h, str(bad).encode()) == -1
     finally:
         L.nslgf_destroy(h)
+
+
+def test_default_launch_shapes_follow_the_box():
+    """Without recorded choices a box gets the defaults for its size: x-y IF rows per workgroup 32 up to
+    128 cells along y, 64 up to 192, else 128; z IF outputs per thread 16 up to 192 cells along z, else 32."""
+    for box, rows, seg in (((24, 120, 40), 32, 16), ((24, 150, 200), 64, 32), ((24, 200, 30), 128, 16)):
+        info = nslgf.tuning_info(*box)
+        assert (info["if_rows"], info["if_seg"], info["cell_shape"]) == (rows, seg, 0), (box, info)
