@@ -11,6 +11,8 @@
 // exchange).  Forward transforms use e^{-2 pi i jk/L}; inverse ones e^{+2 pi i jk/L}; neither scales.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace nslgf {
@@ -331,6 +333,37 @@ __device__ __forceinline__ void pass_load(cplx<T>* v, int t, Acc& acc) {
     }
 }
 
+// Split exchange (accessors that address one real part per element): the real parts go through LDS
+// first, then the imaginary parts, so the tile needs half the LDS (two more barriers per exchange; the
+// same values move, the results are unchanged).
+template <class Acc> struct SplitExchange : std::false_type {};
+
+template <typename T, int L, int E, int TP, int NS, int R, int PART, class Acc>
+__device__ __forceinline__ void pass_store_part(const cplx<T>* v, int t, Acc& acc) {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = t + b * TP;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc(base + r * NS) = PART ? v[b * R + r].y : v[b * R + r].x;
+    }
+}
+
+template <typename T, int L, int E, int TP, int R, int PART, class Acc>
+__device__ __forceinline__ void pass_load_part(cplx<T>* v, int t, Acc& acc) {
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = t + b * TP;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (PART)
+                v[b * R + r].y = acc(j + r * (L / R));
+            else
+                v[b * R + r].x = acc(j + r * (L / R));
+        }
+    }
+}
+
 template <typename T, int L, int E, int TP, bool INV, int NS, int PRUNE, class RL> struct Runner;
 
 template <typename T, int L, int E, int TP, bool INV, int NS, int PRUNE, int R>
@@ -349,9 +382,19 @@ struct Runner<T, L, E, TP, INV, NS, PRUNE, RList<R, R2, Rest...>> {
     __device__ __forceinline__ static void run(cplx<T>* v, int t, const cplx<T>* __restrict__ tw, Acc& acc) {
         pass_compute<T, L, E, TP, INV, NS, R, (NS == 1) ? (PRUNE & 1) : 0>(v, t, tw);
         __syncthreads();
-        pass_store<T, L, E, TP, NS, R>(v, t, acc);
-        __syncthreads();
-        pass_load<T, L, E, TP, R2>(v, t, acc);
+        if constexpr (SplitExchange<Acc>::value) {
+            pass_store_part<T, L, E, TP, NS, R, 0>(v, t, acc);
+            __syncthreads();
+            pass_load_part<T, L, E, TP, R2, 0>(v, t, acc);
+            __syncthreads();
+            pass_store_part<T, L, E, TP, NS, R, 1>(v, t, acc);
+            __syncthreads();
+            pass_load_part<T, L, E, TP, R2, 1>(v, t, acc);
+        } else {
+            pass_store<T, L, E, TP, NS, R>(v, t, acc);
+            __syncthreads();
+            pass_load<T, L, E, TP, R2>(v, t, acc);
+        }
         Runner<T, L, E, TP, INV, NS * R, PRUNE, RList<R2, Rest...>>::run(v, t, tw, acc);
     }
 };
@@ -374,6 +417,22 @@ struct ColAcc {
     __device__ __forceinline__ cplx<T>& operator()(int pos) { return base[(pos + (pos >> 4)) * TB + c]; }
 };
 template <int L> __host__ __device__ constexpr int col_lds_len() { return L + L / 16 + 1; }
+// The same layout holding one part (real or imaginary) per element: the split exchange.
+template <typename T, int TB>
+struct ColAccS {
+    T* base;
+    int c;
+    __device__ __forceinline__ T& operator()(int pos) { return base[(pos + (pos >> 4)) * TB + c]; }
+};
+template <typename T, int TB> struct SplitExchange<ColAccS<T, TB>> : std::true_type {};
+// Column passes that use the split exchange: FP64 at lengths 320 and 384, which hold 20 and 12
+// elements per thread, so a full-complex tile needs 20 KB and 12 KB of LDS per wave and a CU holds 6
+// and 8 waves; halving it lets the register budget, not the LDS, set the occupancy (measured: the
+// 192^3 FP64 step 3% faster; in FP32 the tiles are half as large and the extra barriers cost more
+// than the occupancy gains).
+template <typename T, int L> __host__ __device__ constexpr bool col_split_exchange() {
+    return sizeof(T) == 8 && (L == 320 || L == 384);
+}
 
 // LDS accessor of the row kernels: one contiguous segment per row, one pad element every 2^S
 // elements (S = 4; padding every 8 complex doubles measured no faster and would cost the row kernels

@@ -189,8 +189,10 @@ k_col(ColPass a0, const ColPass* __restrict__ da, int per) {
     using RI = Reverse<RF>;
     static_assert(TB * TP <= 512, "column pass workgroup too large");
     constexpr int LD = col_lds_len<L>();
-    using Acc = ColAcc<T, TB>;
-    __shared__ cplx<T> lds[TB * LD];
+    constexpr bool SPLIT = col_split_exchange<T, L>();
+    using Acc = typename std::conditional<SPLIT, ColAccS<T, TB>, ColAcc<T, TB>>::type;
+    using LdsElem = typename std::conditional<SPLIT, T, cplx<T>>::type;
+    __shared__ LdsElem lds[TB * LD];
     const int tid = threadIdx.x;
     const int c = tid % TB, t = tid / TB;
     int tile, outer, comp;

@@ -30,10 +30,11 @@ def test_compact_sphere_32_fp64_fp32():
 
 
 @pytest.mark.parametrize("shape", [(9, 13, 20), (33, 24, 40), (8, 12, 70), (5, 6, 150), (6, 150, 5), (150, 5, 6),
-                                   (1, 1, 1), (2, 3, 1), (17, 17, 17)])
+                                   (4, 5, 170), (5, 170, 4), (170, 4, 5), (1, 1, 1), (2, 3, 1), (17, 17, 17)])
 def test_ragged_boxes_fp64(shape):
     """Non-cubic boxes whose padded sizes exercise radix 2, 3, 4, 5 and 8, several column tiles and a
-    ragged last tile."""
+    ragged last tile; an axis of 150 (170) pads to 320 (384) on the row, y-column and fused z passes,
+    whose column passes exchange real and imaginary parts through LDS one after the other."""
     rng = np.random.default_rng(sum(shape))
     s = rng.standard_normal(shape)
     dx = 0.37
