@@ -1,12 +1,12 @@
 """HBM traffic of the benchmark's dominant kernel from two rocprofv3 counter runs, and the kernel
 time summary of a rocprofv3 kernel trace.
 
-    cd /tmp && export TMPDIR=/tmp
-    rocprofv3 --pmc FETCH_SIZE -d $R/gpurun_out/pmc_fetch -o f -- \\
+    cd /tmp && export TMPDIR=/tmp   # (R: the repository root, OUT: any output folder)
+    rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc_fetch -o f -- \\
         python3 -u $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-secondary --calibrate
-    rocprofv3 --pmc WRITE_SIZE -d $R/gpurun_out/pmc_write -o w -- \\
+    rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc_write -o w -- \\
         python3 -u $R/bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-secondary --calibrate
-    python3 $R/traffic.py --fetch $R/gpurun_out/pmc_fetch --write $R/gpurun_out/pmc_write
+    python3 $R/traffic.py --fetch $OUT/pmc_fetch --write $OUT/pmc_write
 
 `--calibrate` makes the benchmark first copy 1 GiB with the library's plain copy kernel; the ratio
 of 1 GiB to what each counter reads for that copy scales the counter values of the other kernels
@@ -14,9 +14,9 @@ of 1 GiB to what each counter reads for that copy scales the counter values of t
 together with the hash of the kernel sources it was taken on; bench.py reports it only while that
 hash matches.
 
-    rocprofv3 --kernel-trace --stats -d $R/gpurun_out/prof_step -o step -- \
+    rocprofv3 --kernel-trace --stats -d $OUT/prof_step -o step -- \
         python3 -u $R/bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-secondary
-    python3 $R/traffic.py --trace $R/gpurun_out/prof_step > profiles/step256_fp64_kernel_trace.md
+    python3 $R/traffic.py --trace $OUT/prof_step > profiles/step256_fp64_kernel_trace.md
 
 prints per-kernel launch counts and durations, and for the dominant kernel the average launch
 duration over one step's launch mix (the figure bench.py measures with HIP events).
