@@ -68,6 +68,14 @@ int sur_to_blocked8(nslgf_t h, const void *x_bf16, void *xb_bf16, long long nvox
  * writing the FP32 tensor back.  nvox % 8 == 0, c % 8 == 0. */
 int sur_cast_bf16_ex(nslgf_t h, const void *src_f32, const void *act_f32, void *y_bf16, void *yb_bf16,
                      long long nvox, int c, void *stream);
+/* Resampling, skip sum and cast in one pass: val[v][ch] = scale * coarse[parent(v)][ch] + skip[v][ch] over the
+ * fine grid [D][H][W] (channels-last, c channels), parent(v) = (z/2, y/2, x/2) in the coarse grid
+ * [D/2][H/2][W/2]; then as sur_cast_bf16_ex (ReLU backward of act when act is given, BF16 copy y, blocked
+ * copy yb when yb is given).  scale 1 gives sur_up2_fwd, sur_add and sur_cast_bf16_ex in turn, scale 1/8
+ * sur_pool2_bwd, sur_add and sur_cast_bf16_ex, bit for bit, without writing the two FP32 tensors.  Even
+ * D, H, W with D*H*W % 8 == 0, c % 8 == 0, 16-byte aligned tensors (else NSLGF_EINVAL). */
+int sur_cast_bf16_up(nslgf_t h, const void *coarse_f32, double scale, const void *skip_f32, const void *act_f32,
+                     void *y_bf16, void *yb_bf16, int D, int H, int W, int c, void *stream);
 /* Weight gradient from operands already in the blocked layout (dyb [nvox/8][cout][8], xb [nvox/8][cin][8]):
  * the result of sur_conv3d_bwd_weight bit for bit, without its two layout copies.  Needs W % 8 == 0 and
  * D*H*W % 16 == 0 (else NSLGF_EINVAL); work of sur_bwd_weight_blocked_work_bytes bytes. */

@@ -462,6 +462,54 @@ __device__ __forceinline__ long long coarse_of(long long v, int D, int H, int W)
     return ((long long)(z / 2) * (H / 2) + y / 2) * (W / 2) + x / 2;
 }
 
+// Fused resampling, skip sum and cast: val[v][c] = scale * coarse[parent(v)][c] + skip[v][c], parent(v)
+// the voxel of the half-resolution grid that holds v (scale 1: the nearest-neighbour upsampling; scale
+// 1/8: the adjoint of the 2x2x2 average pooling), then as k_cast_ex: zero where act is given and not
+// > 0, y[v][c] = bf16(val), and yb[v / 8][c][v % 8] = bf16(val) when yb is given.  The product and the
+// sum are rounded one at a time, as the separate passes round them.  One thread: 8 voxels x 8 channels.
+__global__ void __launch_bounds__(256) k_cast_up(const float* __restrict__ coarse, float scale,
+                                                 const float* __restrict__ skip, const float* __restrict__ act,
+                                                 bf16_t* __restrict__ y, bf16_t* __restrict__ yb, long long ngroups,
+                                                 int C, int D, int H, int W) {
+    const int cgs = C / 8;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ngroups * cgs) return;
+    const long long g = e / cgs;
+    const int cg = (int)(e % cgs) * 8;
+    bf16_t o[64];  // o[j * 8 + c]: voxel j, channel cg + c
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const long long v = g * 8 + j;
+        const long long base = v * C + cg, cb = coarse_of(v, D, H, W) * C + cg;
+        const float4 c0 = *(const float4*)(coarse + cb), c1 = *(const float4*)(coarse + cb + 4);
+        const float4 s0 = *(const float4*)(skip + base), s1 = *(const float4*)(skip + base + 4);
+        const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+        const float sv[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        float v8[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v8[c] = __fadd_rn(__fmul_rn(scale, cv[c]), sv[c]);
+        if (act) {
+            const float4 a0 = *(const float4*)(act + base), a1 = *(const float4*)(act + base + 4);
+            const float a[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (!(a[c] > 0.f)) v8[c] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) o[j * 8 + c] = f2bf(v8[c]);
+        *(uint4*)(y + base) = *(const uint4*)(o + j * 8);
+    }
+    if (yb) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            bf16_t t[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) t[j] = o[j * 8 + c];
+            *(uint4*)(yb + (g * C + cg + c) * 8) = *(const uint4*)t;
+        }
+    }
+}
+
 __global__ void k_pool2_fwd(const float* __restrict__ x, float* __restrict__ y, int D, int H, int W, int c) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long nc = (long long)(D / 2) * (H / 2) * (W / 2) * c;
@@ -792,6 +840,22 @@ int sur_cast_bf16_ex(nslgf_t h, const void* src, const void* act, void* y, void*
     if (nvox == 0) return NSLGF_OK;
     hipLaunchKernelGGL(k_cast_ex, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
                        (const float*)src, (const float*)act, (bf16_t*)y, (bf16_t*)yb, nvox / 8, c);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_cast_bf16_up(nslgf_t h, const void* coarse, double scale, const void* skip, const void* act, void* y,
+                     void* yb, int D, int H, int W, int c, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(coarse && skip && y && D > 0 && H > 0 && W > 0 && D % 2 == 0 && H % 2 == 0 && W % 2 == 0 &&
+                        c > 0 && c % 8 == 0 && ((long long)D * H * W) % 8 == 0,
+                    "sur_cast_bf16_up: need coarse, skip, y, even D, H, W with D*H*W % 8 == 0, c % 8 == 0");
+    NSLGF_CHECK_ARG(a16(coarse) && a16(skip) && a16(act) && a16(y) && a16(yb),
+                    "sur_cast_bf16_up: tensors must be 16-byte aligned");
+    const long long nvox = (long long)D * H * W;
+    hipLaunchKernelGGL(k_cast_up, dim3(ceil_div(nvox / 8 * (c / 8), 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const float*)coarse, (float)scale, (const float*)skip, (const float*)act, (bf16_t*)y,
+                       (bf16_t*)yb, nvox / 8, c, D, H, W);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

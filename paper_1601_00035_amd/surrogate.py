@@ -45,6 +45,7 @@ def _bind():
         "sur_weight_transpose": [vp, vp, vp, i, i, vp],
         "sur_cast_bf16": [vp, vp, vp, ll, vp],
         "sur_cast_bf16_ex": [vp, vp, vp, vp, vp, ll, i, vp],
+        "sur_cast_bf16_up": [vp, vp, d, vp, vp, vp, vp, i, i, i, i, vp],
         "sur_to_blocked8": [vp, vp, vp, ll, i, vp],
         "sur_conv3d_bwd_weight_blocked": [vp, vp, vp, vp, vp, i, i, i, i, i, vp],
         "sur_relu_bwd": [vp, vp, vp, ll, vp],
@@ -141,6 +142,16 @@ class UNet:
         call("sur_cast_bf16_ex", src, act, dst, blk, nvox, c)
         return dst
 
+    def _cast_up(self, coarse, scale, skip, key, lv, c, blocked, act=None):
+        """BF16 copy of scale * (coarse resampled to level lv) + skip, after the ReLU backward of `act` when
+        given, and, when `blocked`, its blocked copy (key + "_k"): the upsampling (scale 1) or pooling
+        adjoint (scale 1/8), the skip sum and the cast in one pass."""
+        n = self.R >> lv
+        dst = self._buf(key + "_b", n ** 3 * c, bf16=True)
+        blk = self._buf(key + "_k", n ** 3 * c, bf16=True) if blocked else None
+        call("sur_cast_bf16_up", coarse, float(scale), skip, act, dst, blk, n, n, n, c)
+        return dst
+
     # ---- forward ------------------------------------------------------------------------------
     def forward(self, xb: torch.Tensor, R: int, train: bool = False) -> torch.Tensor:
         """xb: BF16 input [R^3][16]; returns the FP32 output [R^3][32] (channels 0..2 meaningful).  With
@@ -184,20 +195,12 @@ class UNet:
         A["b4"] = conv(4, A["p3_b"], "b4")
         A["b4_b"] = cast(A["b4"], "b4", 3, 128)
         A["b5"] = conv(5, A["b4_b"], "b5")
-        A["u3"] = self._buf("u3", nv[2] * 96)
-        call("sur_up2_fwd", A["b5"], A["u3"], r[2], r[2], r[2], 96)
-        call("sur_add", A["u3"], A["e3"], A["u3"], nv[2] * 96)
-        A["u3_b"] = cast(A["u3"], "u3", 2, 96)
+        # decoder inputs u = up2(coarser output) + skip, cast to BF16 in the same pass
+        A["u3_b"] = self._cast_up(A["b5"], 1.0, A["e3"], "u3", 2, 96, train)
         A["d3"] = conv(6, A["u3_b"], "d3")
-        A["u2"] = self._buf("u2", nv[1] * 64)
-        call("sur_up2_fwd", A["d3"], A["u2"], r[1], r[1], r[1], 64)
-        call("sur_add", A["u2"], A["e2"], A["u2"], nv[1] * 64)
-        A["u2_b"] = cast(A["u2"], "u2", 1, 64)
+        A["u2_b"] = self._cast_up(A["d3"], 1.0, A["e2"], "u2", 1, 64, train)
         A["d2"] = conv(7, A["u2_b"], "d2")
-        A["u1"] = self._buf("u1", nv[0] * 32)
-        call("sur_up2_fwd", A["d2"], A["u1"], r[0], r[0], r[0], 32)
-        call("sur_add", A["u1"], A["e1"], A["u1"], nv[0] * 32)
-        A["u1_b"] = cast(A["u1"], "u1", 0, 32)
+        A["u1_b"] = self._cast_up(A["d2"], 1.0, A["e1"], "u1", 0, 32, train)
         A["d1"] = conv(8, A["u1_b"], "d1")
         A["d1_b"] = cast(A["d1"], "d1", 0, 32)
         A["y"] = conv(9, A["d1_b"], "y")
@@ -268,22 +271,14 @@ class UNet:
         gb4_b = castg(gb4, "gb4", 3, 128, A["b4"])
         wgrad(4, "gb4", gb4_b, "p3")
         gp3 = dgrad(4, gb4_b, "gp3")
-        ge3 = self._buf("ge3", nv[2] * 96)
-        call("sur_pool2_bwd", gp3, ge3, r[2], r[2], r[2], 96)
-        call("sur_add", ge3, gu3, ge3, nv[2] * 96)
-        ge3_b = castg(ge3, "ge3", 2, 96, A["e3"])
+        # encoder gradients ge = pool2 adjoint of gp + the skip gradient gu, ReLU backward and cast in one pass
+        ge3_b = self._cast_up(gp3, 0.125, gu3, "ge3", 2, 96, blk, act=A["e3"])
         wgrad(3, "ge3", ge3_b, "p2")
         gp2 = dgrad(3, ge3_b, "gp2")
-        ge2 = self._buf("ge2", nv[1] * 64)
-        call("sur_pool2_bwd", gp2, ge2, r[1], r[1], r[1], 64)
-        call("sur_add", ge2, gu2, ge2, nv[1] * 64)
-        ge2_b = castg(ge2, "ge2", 1, 64, A["e2"])
+        ge2_b = self._cast_up(gp2, 0.125, gu2, "ge2", 1, 64, blk, act=A["e2"])
         wgrad(2, "ge2", ge2_b, "p1")
         gp1 = dgrad(2, ge2_b, "gp1")
-        ge1 = self._buf("ge1", nv[0] * 32)
-        call("sur_pool2_bwd", gp1, ge1, r[0], r[0], r[0], 32)
-        call("sur_add", ge1, gu1, ge1, nv[0] * 32)
-        ge1_b = castg(ge1, "ge1", 0, 32, A["e1"])
+        ge1_b = self._cast_up(gp1, 0.125, gu1, "ge1", 0, 32, blk, act=A["e1"])
         wgrad(1, "ge1", ge1_b, "a0")
         ga0 = dgrad(1, ge1_b, "ga0")
         ga0_b = castg(ga0, "ga0", 0, 32, A["a0"])

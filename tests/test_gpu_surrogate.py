@@ -289,3 +289,37 @@ def test_misaligned_tensors_are_refused():
     out = S.bf16_empty(64 * 8, DEV)
     with pytest.raises(Exception):
         S.call("sur_cast_bf16_ex", src[1:], None, out, None, 64, 8)
+    coarse = torch.zeros(8 * 8 + 4, dtype=torch.float32, device=DEV)
+    with pytest.raises(Exception):
+        S.call("sur_cast_bf16_up", coarse[1:], 1.0, src[:64 * 8], None, out, None, 4, 4, 4, 8)
+
+
+@pytest.mark.parametrize("c", [32, 96])
+def test_fused_resample_skip_cast(c):
+    """sur_cast_bf16_up equals the separate passes bit for bit: scale 1 = sur_up2_fwd, sur_add and
+    sur_cast_bf16_ex; scale 1/8 with the ReLU mask = sur_pool2_bwd, sur_add and sur_cast_bf16_ex (zeros,
+    negative activations and a ragged grid included), with and without the blocked copy."""
+    rng = np.random.default_rng(21 + c)
+    D, H, W = 4, 6, 10
+    nv, nc = D * H * W, (D // 2) * (H // 2) * (W // 2)
+    coarse = torch.from_numpy(rng.standard_normal(nc * c).astype(np.float32)).to(DEV)
+    skip = torch.from_numpy(rng.standard_normal(nv * c).astype(np.float32)).to(DEV)
+    act_np = rng.standard_normal(nv * c).astype(np.float32)
+    act_np[::6] = 0.0
+    act = torch.from_numpy(act_np).to(DEV)
+    for scale, up, use_act in ((1.0, "sur_up2_fwd", False), (0.125, "sur_pool2_bwd", True), (1.0, "sur_up2_fwd", True)):
+        fine = torch.empty(nv * c, dtype=torch.float32, device=DEV)
+        S.call(up, coarse, fine, D, H, W, c)
+        S.call("sur_add", fine, skip, fine, nv * c)
+        ref_b, ref_k = S.bf16_empty(nv * c, DEV), S.bf16_empty(nv * c, DEV)
+        S.call("sur_cast_bf16_ex", fine, act if use_act else None, ref_b, ref_k, nv, c)
+        for blocked in (True, False):
+            y, yk = S.bf16_empty(nv * c, DEV), S.bf16_empty(nv * c, DEV)
+            yk.fill_(7)
+            S.call("sur_cast_bf16_up", coarse, scale, skip, act if use_act else None, y, yk if blocked else None,
+                   D, H, W, c)
+            assert torch.equal(y, ref_b), (scale, use_act, blocked)
+            if blocked:
+                assert torch.equal(yk, ref_k), (scale, use_act)
+            else:
+                assert bool((yk == 7).all())
