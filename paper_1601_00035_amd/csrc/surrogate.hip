@@ -551,21 +551,45 @@ __global__ void k_up2_bwd(const float* __restrict__ gy, float* __restrict__ gx, 
     gx[i] = s;
 }
 
+// VEC (c = 4 * 2^sh, grad on 16 bytes): one thread per 4 channels of a voxel (grid-stride), one
+// 16-byte store each, so a wave writes contiguous rows; else one thread per voxel, one value at a time.
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ pred, const float* __restrict__ tgt,
                                              float* __restrict__ grad, double* __restrict__ partial, long long nvox,
-                                             int c, int used) {
+                                             int c, int used, int sh) {
     __shared__ double red[256];
-    const long long n = nvox * c;
     const double inv = 2.0 / ((double)nvox * used);
     double s = 0.0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int ch = (int)(i % c);
-        if (ch < used) {
-            const double d = (double)pred[i] - (double)tgt[(i / c) * used + ch];
-            s += d * d;
-            grad[i] = (float)(inv * d);
-        } else {
-            grad[i] = 0.f;
+    if constexpr (VEC) {
+        const long long n4 = nvox << sh;
+        for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += (long long)gridDim.x * blockDim.x) {
+            const long long v = e >> sh;
+            const int c0 = (int)(e & ((1 << sh) - 1)) * 4;
+            float o[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int ch = c0 + k;
+                o[k] = 0.f;
+                if (ch < used) {
+                    const double d = (double)pred[v * c + ch] - (double)tgt[v * used + ch];
+                    s += d * d;
+                    o[k] = (float)(inv * d);
+                }
+            }
+            *(float4*)(grad + v * c + c0) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+    } else {
+        for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
+             v += (long long)gridDim.x * blockDim.x) {
+            for (int ch = 0; ch < c; ++ch) {
+                if (ch < used) {
+                    const double d = (double)pred[v * c + ch] - (double)tgt[v * used + ch];
+                    s += d * d;
+                    grad[v * c + ch] = (float)(inv * d);
+                } else {
+                    grad[v * c + ch] = 0.f;
+                }
+            }
         }
     }
     red[threadIdx.x] = s;
@@ -950,8 +974,14 @@ int sur_mse(nslgf_t h, const void* pred, const void* target, void* grad, void* p
             void* stream) {
     SUR_ENTER(h);
     NSLGF_CHECK_ARG(pred && target && grad && partial && nvox > 0 && used >= 1 && used <= c, "sur_mse: bad arguments");
-    hipLaunchKernelGGL(k_mse, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred, (const float*)target,
-                       (float*)grad, (double*)partial, nvox, c, used);
+    int sh = 0;
+    while (sh < 8 && (4 << sh) < c) ++sh;
+    if ((4 << sh) == c && a16(grad))
+        hipLaunchKernelGGL(k_mse<true>, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred,
+                           (const float*)target, (float*)grad, (double*)partial, nvox, c, used, sh);
+    else
+        hipLaunchKernelGGL(k_mse<false>, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred,
+                           (const float*)target, (float*)grad, (double*)partial, nvox, c, used, 0);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

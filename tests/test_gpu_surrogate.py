@@ -90,18 +90,19 @@ def test_resampling_and_elementwise():
     gg = torch.ones_like(xt)
     S.call("sur_relu_bwd", y, gg, y.numel())
     assert torch.equal(gg, (y > 0).float())
-    # squared error: gradient 2 (p - t) / (nvox used) on the used channels
-    nvox, cc, used = 64, 32, 3
-    p = torch.randn(nvox * cc, device=DEV)
-    t = torch.randn(nvox * used, device=DEV)
-    grad = torch.empty_like(p)
-    part = torch.empty(1024, dtype=torch.float64, device=DEV)
-    S.call("sur_mse", p, t, grad, part, nvox, cc, used)
-    pn, tn = p.double().cpu().numpy().reshape(nvox, cc), t.double().cpu().numpy().reshape(nvox, used)
-    assert abs(part.sum().item() - ((pn[:, :used] - tn) ** 2).sum()) < 1e-9
-    gref = np.zeros_like(pn)
-    gref[:, :used] = 2 * (pn[:, :used] - tn) / (nvox * used)
-    assert rel(grad.double().cpu().numpy().reshape(nvox, cc), gref) < 1e-6
+    # squared error: gradient 2 (p - t) / (nvox used) on the used channels (16-byte stores for 32
+    # channels, one at a time for 6)
+    for nvox, cc, used in ((64, 32, 3), (50, 6, 3)):
+        p = torch.randn(nvox * cc, device=DEV)
+        t = torch.randn(nvox * used, device=DEV)
+        grad = torch.full_like(p, float("nan"))
+        part = torch.empty(1024, dtype=torch.float64, device=DEV)
+        S.call("sur_mse", p, t, grad, part, nvox, cc, used)
+        pn, tn = p.double().cpu().numpy().reshape(nvox, cc), t.double().cpu().numpy().reshape(nvox, used)
+        assert abs(part.sum().item() - ((pn[:, :used] - tn) ** 2).sum()) < 1e-9
+        gref = np.zeros_like(pn)
+        gref[:, :used] = 2 * (pn[:, :used] - tn) / (nvox * used)
+        assert rel(grad.double().cpu().numpy().reshape(nvox, cc), gref) < 1e-6, cc
 
 
 def test_unet_forward_backward_vs_oracle():
