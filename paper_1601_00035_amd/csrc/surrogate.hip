@@ -476,11 +476,23 @@ __global__ void __launch_bounds__(256) k_cast_up(const float* __restrict__ coars
     if (e >= ngroups * cgs) return;
     const long long g = e / cgs;
     const int cg = (int)(e % cgs) * 8;
+    // W % 8 == 0: the 8 voxels lie in one x row, so their parents follow from the first one's
+    long long crow = 0;
+    int x0 = 0;
+    const bool row8 = W % 8 == 0;
+    if (row8) {
+        const long long v0 = g * 8;
+        const long long zy = v0 / W;
+        x0 = (int)(v0 - zy * W);
+        const int y = (int)(zy % H), z = (int)(zy / H);
+        crow = ((long long)(z / 2) * (H / 2) + y / 2) * (W / 2);
+    }
     bf16_t o[64];  // o[j * 8 + c]: voxel j, channel cg + c
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const long long v = g * 8 + j;
-        const long long base = v * C + cg, cb = coarse_of(v, D, H, W) * C + cg;
+        const long long parent = row8 ? crow + (x0 + j) / 2 : coarse_of(v, D, H, W);
+        const long long base = v * C + cg, cb = parent * C + cg;
         const float4 c0 = *(const float4*)(coarse + cb), c1 = *(const float4*)(coarse + cb + 4);
         const float4 s0 = *(const float4*)(skip + base), s1 = *(const float4*)(skip + base + 4);
         const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};

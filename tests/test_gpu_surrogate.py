@@ -295,13 +295,13 @@ def test_misaligned_tensors_are_refused():
         S.call("sur_cast_bf16_up", coarse[1:], 1.0, src[:64 * 8], None, out, None, 4, 4, 4, 8)
 
 
-@pytest.mark.parametrize("c", [32, 96])
-def test_fused_resample_skip_cast(c):
+@pytest.mark.parametrize("c,D,H,W", [(32, 4, 6, 10), (96, 4, 6, 10), (32, 6, 4, 16), (64, 2, 2, 24)])
+def test_fused_resample_skip_cast(c, D, H, W):
     """sur_cast_bf16_up equals the separate passes bit for bit: scale 1 = sur_up2_fwd, sur_add and
     sur_cast_bf16_ex; scale 1/8 with the ReLU mask = sur_pool2_bwd, sur_add and sur_cast_bf16_ex (zeros,
-    negative activations and a ragged grid included), with and without the blocked copy."""
-    rng = np.random.default_rng(21 + c)
-    D, H, W = 4, 6, 10
+    negative activations included), with and without the blocked copy; rows of 8-voxel groups (W % 8 ==
+    0) and groups that straddle rows (W = 10)."""
+    rng = np.random.default_rng(21 + c + W)
     nv, nc = D * H * W, (D // 2) * (H // 2) * (W // 2)
     coarse = torch.from_numpy(rng.standard_normal(nc * c).astype(np.float32)).to(DEV)
     skip = torch.from_numpy(rng.standard_normal(nv * c).astype(np.float32)).to(DEV)
