@@ -390,9 +390,9 @@ static void issue_xy(const IfXyArgs& a, dim3 grid, dim3 block, hipStream_t s) {
 }
 
 // rows: at most this many output rows per workgroup; the ny rows of a plane are split into
-// ceil(ny / rows) tiles of equal height (up to one row less in the last), so that no workgroup walks
-// past the plane's end or carries a long tail alone (halo rows re-read: 2R / height).  A workgroup
-// has one thread per x rounded up to whole wavefronts.
+// ntiles = ceil(ny / rows) tiles of height ceil(ny / ntiles) (the last at most ntiles - 1 rows shorter,
+// never empty), so that no workgroup walks far past the plane's end or carries a long tail alone (halo
+// rows re-read: 2R / height).  A workgroup has one thread per x rounded up to whole wavefronts.
 template <typename T, int R>
 static void launch_xy(const IfCombine& cb, T* out, int ncomp, int nx, int ny, int nz, const IfWeights& wts,
                       hipStream_t s, int rows) {
