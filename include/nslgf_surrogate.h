@@ -52,6 +52,12 @@ int sur_up2_bwd(nslgf_t h, const void *gy, void *gx, int D, int H, int W, int c,
  * (`nblocks` of them, nblocks = 1024); the caller sums them. target is [voxel][used] FP32. */
 int sur_mse(nslgf_t h, const void *pred, const void *target, void *grad, void *partial_f64, long long nvox, int c,
             int used, void *stream);
+/* sur_mse with the gradient written only as its BF16 copy y_bf16 [voxel][c] and, when yb_bf16 is given, its
+ * blocked copy (the layout of sur_to_blocked8): the same bits as sur_mse followed by sur_cast_bf16_ex of
+ * the gradient, without the FP32 gradient; partial_f64 as sur_mse (1024 per-block sums, summed in another
+ * fixed order).  nvox % 8 == 0, c % 8 == 0, y_bf16 and yb_bf16 16-byte aligned. */
+int sur_mse_cast(nslgf_t h, const void *pred, const void *target, void *partial_f64, void *y_bf16, void *yb_bf16,
+                 long long nvox, int c, int used, void *stream);
 /* Adam step on FP32 master weights (t = step number from 1) and their BF16 copy. */
 int sur_adam(nslgf_t h, void *w, void *w_bf16, const void *g, void *m, void *v, long long n, float lr, float b1,
              float b2, float eps, int t, void *stream);

@@ -613,6 +613,58 @@ __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ pred, con
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// Squared error with the gradient written only as its BF16 copy y[v][c] and, when yb is given, the
+// blocked copy yb[v / 8][c][v % 8] (the layout of k_to_blocked8): the gradient values are those of
+// k_mse, rounded as k_cast_ex rounds them.  One thread: 8 voxels x 8 channels (grid-stride); per-block
+// FP64 partial sums of the squared error, in the order of this decomposition.
+__global__ void __launch_bounds__(256) k_mse_cast(const float* __restrict__ pred, const float* __restrict__ tgt,
+                                                  bf16_t* __restrict__ y, bf16_t* __restrict__ yb,
+                                                  double* __restrict__ partial, long long nvox, int C, int used) {
+    __shared__ double red[256];
+    const double inv = 2.0 / ((double)nvox * used);
+    const int cgs = C / 8;
+    const long long ngroups = nvox / 8;
+    double s = 0.0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < ngroups * cgs;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long g = e / cgs;
+        const int cg = (int)(e % cgs) * 8;
+        bf16_t o[64];  // o[j * 8 + c]: voxel j, channel cg + c
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const long long v = g * 8 + j;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int ch = cg + c;
+                float gv = 0.f;
+                if (ch < used) {
+                    const double d = (double)pred[v * C + ch] - (double)tgt[v * used + ch];
+                    s += d * d;
+                    gv = (float)(inv * d);
+                }
+                o[j * 8 + c] = f2bf(gv);
+            }
+            *(uint4*)(y + v * C + cg) = *(const uint4*)(o + j * 8);
+        }
+        if (yb) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                bf16_t t[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) t[j] = o[j * 8 + c];
+                *(uint4*)(yb + (g * C + cg + c) * 8) = *(const uint4*)t;
+            }
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 __global__ void k_adam(float* __restrict__ w, bf16_t* __restrict__ wb, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, long long n, float lr, float b1, float b2, float eps, float c1, float c2) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -994,6 +1046,19 @@ int sur_mse(nslgf_t h, const void* pred, const void* target, void* grad, void* p
     else
         hipLaunchKernelGGL(k_mse<false>, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred,
                            (const float*)target, (float*)grad, (double*)partial, nvox, c, used, 0);
+    NSLGF_LAUNCH_CHECK();
+    return NSLGF_OK;
+}
+
+int sur_mse_cast(nslgf_t h, const void* pred, const void* target, void* partial, void* y, void* yb, long long nvox,
+                 int c, int used, void* stream) {
+    SUR_ENTER(h);
+    NSLGF_CHECK_ARG(pred && target && partial && y && nvox > 0 && nvox % 8 == 0 && c > 0 && c % 8 == 0 && used >= 1 &&
+                        used <= c,
+                    "sur_mse_cast: need pred, target, partial, y, nvox % 8 == 0, c % 8 == 0, 1 <= used <= c");
+    NSLGF_CHECK_ARG(a16(y) && a16(yb), "sur_mse_cast: tensors must be 16-byte aligned");
+    hipLaunchKernelGGL(k_mse_cast, dim3(1024), dim3(256), 0, (hipStream_t)stream, (const float*)pred,
+                       (const float*)target, (bf16_t*)y, (bf16_t*)yb, (double*)partial, nvox, c, used);
     NSLGF_LAUNCH_CHECK();
     return NSLGF_OK;
 }

@@ -55,6 +55,7 @@ def _bind():
         "sur_up2_fwd": [vp, vp, vp, i, i, i, i, vp],
         "sur_up2_bwd": [vp, vp, vp, i, i, i, i, vp],
         "sur_mse": [vp, vp, vp, vp, vp, ll, i, i, vp],
+        "sur_mse_cast": [vp, vp, vp, vp, vp, vp, ll, i, i, vp],
         "sur_adam": [vp, vp, vp, vp, vp, vp, ll, f, f, f, f, i, vp],
         "sur_pack_input": [vp, vp, vp, i, i, i, d, d, vp],
         "sur_pack_input_pair": [vp, vp, vp, vp, i, i, i, d, d, d, vp],
@@ -208,8 +209,9 @@ class UNet:
         return A["y"][: nv[0] * OUT_CH]
 
     # ---- backward -----------------------------------------------------------------------------
-    def backward(self, gy: torch.Tensor):
-        """gy: FP32 gradient of the loss w.r.t. the output [R^3][32]; fills self.gw.  After a forward with
+    def backward(self, gy: torch.Tensor | None):
+        """gy: FP32 gradient of the loss w.r.t. the output [R^3][32], or None for the BF16 copies that
+        loss_and_grad(..., fused=True) wrote; fills self.gw.  After a forward with
         `train`, the weight gradients read blocked copies written by the casts (the ReLU backward folded
         into the gradient casts); otherwise they copy their operands themselves.  Same results."""
         A = self.A
@@ -247,7 +249,7 @@ class UNet:
                 call("sur_relu_bwd", act, g, nv[lv] * c)
             return self._cast(g, key, nv[lv] * c)
 
-        gy_b = castg(gy, "gy", 0, 32)
+        gy_b = self.bufs["gy_b"] if gy is None else castg(gy, "gy", 0, 32)  # (None: cast by loss_and_grad)
         wgrad(9, "gy", gy_b, "d1")
         gd1 = dgrad(9, gy_b, "gd1")
         gd1_b = castg(gd1, "gd1", 0, 32, A["d1"])
@@ -290,9 +292,17 @@ class UNet:
             call("sur_adam", self.w[li], self.wb[li], self.gw[li], self.m[li], self.v[li], self.w[li].numel(),
                  lr, b1, b2, eps, self.t)
 
-    def loss_and_grad(self, y: torch.Tensor, target: torch.Tensor, nvox: int):
-        grad = self._buf("gy_f", nvox * OUT_CH)
+    def loss_and_grad(self, y: torch.Tensor, target: torch.Tensor, nvox: int, fused: bool = False):
+        """Per-block partial sums of the squared error and the FP32 gradient of the loss w.r.t. y; with
+        `fused`, the gradient is written only as the BF16 copy (and, after a training forward, the blocked
+        copy) that backward(None) reads, and None is returned in its place."""
         part = torch.empty(1024, dtype=torch.float64, device=self.device)
+        if fused:
+            gb = self._buf("gy_b", nvox * OUT_CH, bf16=True)
+            gk = self._buf("gy_k", nvox * OUT_CH, bf16=True) if "x_k" in self.A else None
+            call("sur_mse_cast", y, target, part, gb, gk, nvox, OUT_CH, USED)
+            return part, None
+        grad = self._buf("gy_f", nvox * OUT_CH)
         call("sur_mse", y, target, grad, part, nvox, OUT_CH, USED)
         return part, grad
 
@@ -402,8 +412,8 @@ def train(net: UNet, trajs: list, res: list, horizon: int, iters: int, lr: float
             pack_input(w_k, scales[i], res[i], out=xb)
             pack_target(combine3(w_h, w_k, None, 1.0, -1.0), scales[i] * gain, out=tg)
         y = net.forward(xb, R, train=True)
-        part, grad = net.loss_and_grad(y, tg, nvox)
-        net.backward(grad)
+        part, _ = net.loss_and_grad(y, tg, nvox, fused=True)
+        net.backward(None)
         lr_it = lr if lr_min is None else lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * it / max(1, iters - 1)))
         net.adam(lr=lr_it)
         if log_every and (it % log_every == 0 or it == iters - 1):

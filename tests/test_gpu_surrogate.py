@@ -324,3 +324,42 @@ def test_fused_resample_skip_cast(c, D, H, W):
                 assert torch.equal(yk, ref_k), (scale, use_act)
             else:
                 assert bool((yk == 7).all())
+
+
+def test_fused_loss_gradient():
+    """sur_mse_cast writes the bits of sur_mse followed by sur_cast_bf16_ex of its gradient (BF16 and
+    blocked copies) and the same loss up to the order of its FP64 partial sums; training with it
+    (loss_and_grad(fused=True), backward(None)) gives the weight gradients of the FP32 path bit for bit."""
+    nvox, c, used = 4 * 8 * 16, 32, 3
+    g = torch.Generator(device="cpu").manual_seed(5)
+    p = torch.randn(nvox * c, generator=g).to(DEV)
+    t = torch.randn(nvox * used, generator=g).to(DEV)
+    grad = torch.empty_like(p)
+    part = torch.empty(1024, dtype=torch.float64, device=DEV)
+    S.call("sur_mse", p, t, grad, part, nvox, c, used)
+    ref_b, ref_k = S.bf16_empty(nvox * c, DEV), S.bf16_empty(nvox * c, DEV)
+    S.call("sur_cast_bf16_ex", grad, None, ref_b, ref_k, nvox, c)
+    y, yk = S.bf16_empty(nvox * c, DEV), S.bf16_empty(nvox * c, DEV)
+    part2 = torch.empty(1024, dtype=torch.float64, device=DEV)
+    S.call("sur_mse_cast", p, t, part2, y, yk, nvox, c, used)
+    assert torch.equal(y, ref_b) and torch.equal(yk, ref_k)
+    assert abs(part2.sum().item() - part.sum().item()) <= 1e-12 * part.sum().item()
+    # the training path
+    R = 32
+    net = S.UNet(DEV, seed=3)
+    x = np.zeros((R, R, R, 16))
+    x[..., :4] = C.bf16_round(np.random.default_rng(8).standard_normal((R, R, R, 4)))
+    xb = to_bf16_bits(x).reshape(-1)
+    tg = torch.randn(R ** 3 * S.USED, generator=g).to(DEV)
+    out = net.forward(xb, R, train=True)
+    _, gfp = net.loss_and_grad(out, tg, R ** 3)
+    net.backward(gfp)
+    plain = [w.clone() for w in net.gw]
+    out1 = out.clone()
+    out2 = net.forward(xb, R, train=True)
+    assert torch.equal(out1, out2)
+    _, none = net.loss_and_grad(out2, tg, R ** 3, fused=True)
+    assert none is None
+    net.backward(None)
+    for li in range(10):
+        assert torch.equal(net.gw[li], plain[li]), li
