@@ -249,7 +249,10 @@ class UNet:
                 call("sur_relu_bwd", act, g, nv[lv] * c)
             return self._cast(g, key, nv[lv] * c)
 
+        if gy is None and not getattr(self, "_gy_cast", False):
+            raise ValueError("backward(None) needs loss_and_grad(..., fused=True) first")
         gy_b = self.bufs["gy_b"] if gy is None else castg(gy, "gy", 0, 32)  # (None: cast by loss_and_grad)
+        self._gy_cast = False
         wgrad(9, "gy", gy_b, "d1")
         gd1 = dgrad(9, gy_b, "gd1")
         gd1_b = castg(gd1, "gd1", 0, 32, A["d1"])
@@ -297,6 +300,7 @@ class UNet:
         `fused`, the gradient is written only as the BF16 copy (and, after a training forward, the blocked
         copy) that backward(None) reads, and None is returned in its place."""
         part = torch.empty(1024, dtype=torch.float64, device=self.device)
+        self._gy_cast = fused
         if fused:
             gb = self._buf("gy_b", nvox * OUT_CH, bf16=True)
             gk = self._buf("gy_k", nvox * OUT_CH, bf16=True) if "x_k" in self.A else None

@@ -3,10 +3,11 @@ and C, FP64) on an elongated box, sampled at fixed points.  Calls only oracle/ a
 
 The box, (nz, ny, nx) = (200, 136, 16), is chosen for the code paths it reaches on the GPU: a padded
 z length of 512 (2 nz - 1 > 384), a y extent above 128 rows (the fused x-y integrating-factor pass
-splits a plane into several row tiles) and z lines long enough for the interior segments of the z
-integrating-factor pass.  The initial velocity is a compact random blob straddling the row-tile
-boundary at y = 128 plus one in the lower half of the box; it is not divergence-free, so the first
-pressure solve has a source everywhere the blob is.
+splits a plane into row tiles: by default three of 46 rows, boundaries at y = 46 and 92; two of 68
+with 128 rows per workgroup) and z lines long enough for the interior segments of the z
+integrating-factor pass.  The initial velocity is three compact random blobs, around y = 40, 92 and 128
+(the first two across the default tile boundaries); it is not divergence-free, so the first pressure
+solve has a source everywhere the blobs are.
 
 The oracle needs about half an hour on eight cores for the three results; the GPU tests read the
 samples and the full-field maxima from the file.  Run from the repository root:
@@ -24,7 +25,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 SHAPE = (200, 136, 16)
-CENTRES = ((100, 128, 8), (45, 40, 7))
+CENTRES = ((100, 128, 8), (45, 40, 7), (150, 92, 8))
 RADIUS = 13.0
 SEED = 21
 DX, RE, CFL, N_BUF = 0.05, 500.0, 0.5, 2
@@ -40,14 +41,16 @@ def initial_velocity():
 
 
 def sample_index():
-    """Flat indices into one scalar component: full rows around the row-tile boundary in several z
-    planes, whole z lines at several (y, x), and seeded random points."""
+    """Flat indices into one scalar component: full rows around the row-tile boundaries (y = 46, 92 by
+    default, 68 with 128 rows per workgroup) and the top rows in several z planes, whole z lines at
+    several (y, x), and seeded random points."""
     nz, ny, nx = SHAPE
     idx = []
-    for k in (0, 1, 44, 45, 99, 100, 101, 150, 198, 199):
-        for j in range(118, 136):
+    rows = list(range(38, 54)) + list(range(62, 75)) + list(range(84, 100)) + list(range(118, 136))
+    for k in (0, 1, 44, 45, 99, 100, 101, 150, 151, 198, 199):
+        for j in rows:
             idx.extend(k * ny * nx + j * nx + np.arange(nx))
-    for j in (0, 40, 127, 128, 129, 135):
+    for j in (0, 40, 45, 46, 67, 68, 91, 92, 127, 128, 129, 135):
         for i in (0, 7, 8, 15):
             idx.extend(np.arange(nz) * ny * nx + j * nx + i)
     rng = np.random.default_rng(5)

@@ -1,11 +1,12 @@
 """Oracle parity on the code paths the 256^3 benchmark runs, reached on an elongated box small enough
 for the oracle: (nz, ny, nx) = (200, 136, 16).  Its z axis pads to 512 (the length-512 column plans
 and the fused z pass of the step's pressure solves), its planes have more than 128 rows (the fused
-x-y integrating-factor pass splits them into row tiles, with halo rows taken across the tile
-boundary and w^{i,i} written per owned row), and its z lines are long enough for the interior
-segments of the z integrating-factor pass.  Expected values: the oracle's integrating factor and
-plain-recursion IF-HERK steps (Schemes A and C), sampled by tests/golden/make_elongated.py (rows
-around the tile boundary in ten planes, 24 whole z lines, 4000 seeded points)."""
+x-y integrating-factor pass splits them into row tiles, three of 46 rows by default, with halo rows
+taken across the tile boundaries and w^{i,i} written per owned row), and its z lines are long enough
+for the interior segments of the z integrating-factor pass.  Expected values: the oracle's
+integrating factor and plain-recursion IF-HERK steps (Schemes A and C), sampled by
+tests/golden/make_elongated.py (rows around the tile boundaries in eleven planes, 48 whole z lines,
+4000 seeded points)."""
 import os
 import sys
 

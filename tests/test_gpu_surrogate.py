@@ -363,3 +363,5 @@ def test_fused_loss_gradient():
     net.backward(None)
     for li in range(10):
         assert torch.equal(net.gw[li], plain[li]), li
+    with pytest.raises(ValueError):  # the cast gradient is used once
+        net.backward(None)
